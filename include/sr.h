@@ -1,0 +1,288 @@
+/*
+ * sr.h -- C ABI of libsr.so, the MI355X (gfx950) implementation of the
+ * real-time synchrotron photon emission method of Wallin, Gonoskov & Marklund,
+ * "Effects of high energy photon emissions in laser generated ultra-relativistic
+ * plasmas: real-time synchrotron simulations" (arXiv 1409.5574).
+ *
+ * Units: normalised, c = m = e = 1, electron charge q = -1.  Time is in
+ * 1/omega_r, length in c/omega_r, momentum in mc, energy in mc^2, fields in
+ * eE/(mc omega_r) and eB/(m omega_r).  hbar_n = hbar omega_r/(mc^2).
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are HIP device pointers owned by the caller
+ *    (typically PyTorch tensors).  The library never frees or retains them
+ *    beyond the call.  Pointers marked "host" are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously on it unless the entry point says
+ *    SYNCHRONOUS.
+ *  - Return value: SR_OK (0) or a negative sr_error code.  Argument errors are
+ *    detected on the host before anything is launched, so a failed call has
+ *    enqueued no work.  Conditions found on the device (photon-segment
+ *    overflow, recoil clamping, non-finite inputs) are latched as bits in the
+ *    caller's status word and read back by sr_status().
+ *  - Hot calls (sr_gather_push_emit*, sr_ledger_reduce, sr_spectrum_histogram,
+ *    sr_field_standing_wave, sr_sort_particles, sr_mlp_*) allocate nothing.
+ *    Only sr_table_build allocates device memory (released by sr_table_free).
+ *  - Calls that share device buffers must be ordered by the caller (same
+ *    stream or events); the library keeps no global mutable state apart from
+ *    the tables it hands out.
+ */
+#ifndef SR_H
+#define SR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+typedef enum {
+    SR_OK = 0,
+    SR_E_INVAL = -1,       /* bad argument (null pointer, size, mode)          */
+    SR_E_HIP = -2,         /* a HIP runtime call failed                         */
+    SR_E_NOMEM = -3,       /* sr_table_build could not allocate                 */
+    SR_E_UNSUPPORTED = -4  /* valid request this build does not provide         */
+} sr_error;
+
+/* Bits latched in the device status word (sr_ledger.status). */
+enum {
+    SR_W_PHOTON_OVERFLOW = 1u, /* a chunk emitted more photons than its segment holds;
+                                  the surplus is counted, not stored, and its energy
+                                  goes to ledger column SR_LED_DROPPED             */
+    SR_W_RECOIL_CLAMP = 2u,    /* recoil larger than |p|: p set to 0, remainder in
+                                  ledger column SR_LED_CLAMPED                      */
+    SR_W_NONFINITE = 4u        /* a non-finite momentum or field value was met      */
+};
+
+/* Ledger columns: one row of SR_LEDGER_COLS doubles per time step (FP64). */
+enum {
+    SR_LED_EMITTED = 0,  /* sum over emitted photons of weight * energy          */
+    SR_LED_LL = 1,       /* sum w (2/3)(alpha/hbar_n) chi^2 beta^2 dt: the energy the
+                            Landau-Lifshitz force (eq:LLformOfRRForce) removes     */
+    SR_LED_RECOIL = 2,   /* sum w (gamma_after - gamma_before) of the recoil      */
+    SR_LED_CLAMPED = 3,  /* sum w (recoil - |p|) where recoil exceeded |p|        */
+    SR_LED_DROPPED = 4,  /* weight * energy of photons that did not fit           */
+    SR_LED_PHOTONS = 5,  /* number of photons emitted (stored + dropped)          */
+    SR_LED_WEIGHT = 6,   /* sum of particle weights processed                     */
+    SR_LED_CHI_MAX = 7,  /* largest chi of the step                               */
+    SR_LEDGER_COLS = 8
+};
+
+/* Particles per chunk when the caller gives no explicit chunking. */
+#define SR_CHUNK 256
+
+/* --------------------------------------------------------------- data types */
+/* Macro-electrons, structure of arrays, FP32.  x[a] are positions measured from
+ * the grid's lower corner (x[2] may be NULL for 2D, all may be NULL for the
+ * uniform-field mode); p[a] = gamma v_a is the momentum at half step n-1/2 on
+ * entry and n+1/2 on return; w are weights; id are persistent identifiers that
+ * key the random streams (so results do not depend on the array order).  All
+ * arrays are device, length n. */
+typedef struct {
+    int64_t n;
+    float *x[3];
+    float *p[3];
+    float *w;          /* read only in the step */
+    uint32_t *id;      /* read only in the step */
+} sr_particles_f32;
+
+/* Same, FP64 state (the precision-comparison path). */
+typedef struct {
+    int64_t n;
+    double *x[3];
+    double *p[3];
+    double *w;         /* read only in the step */
+    uint32_t *id;      /* read only in the step */
+} sr_particles_f64;
+
+/* Fields on a Yee grid, six device component arrays of n[0]*n[1]*n[2] FP32
+ * values, x fastest.  Staggering in cells: Ex(1/2,0,0) Ey(0,1/2,0) Ez(0,0,1/2)
+ * Bx(0,1/2,1/2) By(1/2,0,1/2) Bz(1/2,1/2,0).  Unused for dim == 0. */
+typedef struct {
+    const float *e[3];
+    const float *b[3];
+} sr_fields_f32;
+
+/* Grid.  dim 0: uniform fields e0, b0 (no grid, positions not wrapped);
+ * dim 2: n[2] == 1, positions x, y; dim 3: x, y, z.  Periodic in every axis;
+ * the lower corner is the origin of the positions. */
+typedef struct {
+    int32_t dim;
+    int32_t reserved;
+    int64_t n[3];
+    double dx[3];
+    double e0[3];
+    double b0[3];
+} sr_grid;
+
+enum { SR_SAMPLER_S = 0,          /* proposal S(x), section "Monte Carlo method"     */
+       SR_SAMPLER_TABLE = 1,      /* direct: total rate, x from the inverse-CDF table */
+       SR_SAMPLER_MLP = 2 };      /* direct: total rate, x from the MLP surrogate     */
+enum { SR_RECOIL_NONE = 0, SR_RECOIL_PHOTON = 1, SR_RECOIL_LL = 2 };
+enum { SR_DN_WEIGHT = 0, SR_DN_CLAMP = 1 };
+
+typedef struct {
+    double hbar_n;          /* hbar omega_r / (m c^2)                               */
+    double alpha;           /* fine-structure constant                              */
+    int32_t n_samples;      /* K >= 1 frequency trials per particle and step, each
+                               carrying weight w/K (section "Monte Carlo method",
+                               super-photon count and weights)                     */
+    int32_t sampler;        /* SR_SAMPLER_*                                         */
+    int32_t recoil;         /* SR_RECOIL_*                                          */
+    int32_t dn_policy;      /* SR_DN_WEIGHT: dN >= 1 emits with weight w dN/K;
+                               SR_DN_CLAMP: dN >= 1 emits with weight w/K           */
+    int32_t kin_cut;        /* 1: no photon above the emitter's energy (x > 2/(3 chi)) */
+    int32_t push_position;  /* 1: advance positions by dt p/gamma after the push    */
+} sr_params;
+
+/* Chunking of the particle array.  Chunk c covers particles
+ * [start[c], start[c+1]) when start != NULL (device, n_chunks+1 int64 values,
+ * non-decreasing, start[0] = 0, start[n_chunks] = n), else
+ * [c*SR_CHUNK, min((c+1)*SR_CHUNK, n)) with n_chunks = ceil(n / SR_CHUNK). */
+typedef struct {
+    int64_t n_chunks;
+    const int64_t *start;
+} sr_chunking;
+
+/* Photon output.  The buffer is split into one segment per chunk: chunk c owns
+ * slots [s_c * per_particle, e_c * per_particle) where [s_c, e_c) is its
+ * particle range.  seg_count[c] receives the number of photons the chunk
+ * emitted in this call; only the first min(seg_count[c], segment size) are
+ * stored, in no particular order.  Arrays are device, sized n * per_particle
+ * (seg_count: n_chunks).  k and step may be NULL. */
+typedef struct {
+    int64_t per_particle;
+    uint32_t *seg_count;
+    float *eps;         /* photon energy hbar omega in mc^2                        */
+    float *w;           /* photon weight                                           */
+    float *dir[3];      /* unit direction = mean momentum direction (section
+                           "Modelling the relativistic case": photons along the
+                           emitter's motion)                                        */
+    float *pos[3];      /* emitter position x^n (pos[2] may be NULL in 2D)          */
+    uint32_t *parent;   /* emitter id                                              */
+    uint8_t *k;         /* trial index 0..K-1                                      */
+    uint32_t *step;     /* step index                                              */
+} sr_photon_buf;
+
+/* FP64 energy ledger.  rows: device [n_rows][SR_LEDGER_COLS]; partials: device
+ * workspace of at least sr_ledger_partials(n_chunks) doubles; status: device
+ * uint32 whose bits are OR-ed in by the kernels (the caller zeroes it). */
+typedef struct {
+    double *rows;
+    int64_t n_rows;
+    double *partials;
+    int64_t partials_len;
+    uint32_t *status;
+} sr_ledger;
+
+/* Opaque spectrum tables built on the device in FP64 and read in FP32. */
+typedef struct sr_table sr_table;
+
+/* ------------------------------------------------------------ entry points */
+
+/* Build the device tables (the "spectrum-table construction" of the FP64 split):
+ *  - the synchrotron function F(x) = x int_x^inf K_{5/3} (section "Modelling
+ *    the relativistic case"), as piecewise cubics in log2 x for the proposal
+ *    sampler of section "Monte Carlo method";
+ *  - the branch point P(a) of the proposal S(x), a^{4/3} + (7/9)e^{-a} = 1;
+ *  - the inverse CDF of the photon-number spectrum F(x)/x with the optional
+ *    kinematic cut, on a (log chi, u) grid, and the cut rate integral, for the
+ *    direct samplers.
+ * Allocates device memory, runs FP64 kernels on `stream` and synchronises it.
+ * *out receives the handle.  SYNCHRONOUS. */
+int sr_table_build(sr_table **out, void *stream);
+void sr_table_free(sr_table *tab);
+
+/* Host-side description of a built table (for tests and diagnostics). */
+typedef struct {
+    float proposal_pa;      /* binary32 branch point P(a)                          */
+    int32_t f_pieces;       /* cubic pieces of log2 F                              */
+    double proposal_a;      /* a, FP64                                             */
+    int32_t t1_pieces;      /* cubic pieces of the uncut inverse number-CDF        */
+    int32_t r_nodes;        /* nodes of the cut fraction r(chi)                     */
+    double r_log10chi_lo, r_log10chi_hi;
+} sr_table_info;
+int sr_table_query(const sr_table *tab, sr_table_info *info);
+
+/* Evaluate the table's F at n device points x (device out).  The same device
+ * function the emission kernel uses. */
+int sr_eval_synchrotron_F(const sr_table *tab, const float *x, float *out, int64_t n, void *stream);
+
+/* dN of one proposal trial for n device (uniform word a, rate, chi) triples:
+ * out_dn = rate F(x)/(x S(x)) (0 above the cut when kin_cut), out_x = x.
+ * The same device function the emission kernel uses (steps 3-5 of the list at
+ * the end of section "Monte Carlo method"). */
+int sr_eval_trial(const sr_table *tab, const uint32_t *a, const float *rate, const float *chi,
+                  int32_t kin_cut, float *out_dn, float *out_x, int64_t n, void *stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) as used by the kernels: n counters
+ * ctr[i][4] (device) with key (seed low, seed high) -> out[i][4] (device). */
+int sr_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out, int64_t n, void *stream);
+
+/* One time step of the emission method for every particle (FP32 path):
+ *   gather E, B at x^n (CIC on the Yee grid, or the uniform fields);
+ *   Boris push p^{n-1/2} -> p^{n+1/2};
+ *   H_eff from the two momenta (eq:effective_H) with dp_perp/p limited to 1;
+ *   omega_c = 1.5 H_eff gamma^2 and chi = hbar_n H_eff gamma;
+ *   K Monte-Carlo trials (the six steps listed at the end of section "Monte
+ *   Carlo method"), random words from Philox4x32-10 with counter
+ *   (id, step, k/2, 0) and key seed;
+ *   photon append into the chunk's segment, recoil, position push;
+ *   per-chunk FP64 ledger partials into ledger->partials.
+ * Then reduces the partials into ledger->rows[row] (see sr_ledger_reduce).
+ * photons may have per_particle == 0 only if nothing is to be stored (every
+ * photon is then counted as dropped). */
+int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields, const sr_grid *grid,
+                        double dt, uint64_t seed, uint64_t step, const sr_params *prm,
+                        const sr_table *tab, const sr_chunking *chunks, sr_photon_buf *photons,
+                        sr_ledger *ledger, int64_t row, void *stream);
+
+/* The same step with FP64 state, FP64 gather (of the FP32 grid values), FP64
+ * Boris push and H_eff; the trials run in FP32 as in the FP32 path. */
+int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields,
+                            const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
+                            const sr_params *prm, const sr_table *tab, const sr_chunking *chunks,
+                            sr_photon_buf *photons, sr_ledger *ledger, int64_t row, void *stream);
+
+/* Workspace length (doubles) for ledger->partials with n_chunks chunks. */
+int64_t sr_ledger_partials(int64_t n_chunks);
+
+/* Copy ledger row `row` to host out[SR_LEDGER_COLS].  SYNCHRONOUS on stream. */
+int sr_energy_ledger(const sr_ledger *ledger, int64_t row, double *out, void *stream);
+
+/* Read (and, if clear != 0, zero) the latched status bits.  SYNCHRONOUS. */
+int sr_status(const sr_ledger *ledger, uint32_t *flags, int32_t clear, void *stream);
+
+/* Energy-weighted photon spectrum: hist[0..n_bins) += sum w*eps and
+ * hist[n_bins..2 n_bins) += sum w over the stored photons of every chunk,
+ * binned in log eps on [eps_lo, eps_hi).  hist is device FP64; work is a
+ * device workspace of sr_hist_work(n_bins) doubles. */
+int sr_spectrum_histogram(const sr_photon_buf *photons, const sr_chunking *chunks, int64_t n,
+                          double eps_lo, double eps_hi, int32_t n_bins, double *hist,
+                          double *work, void *stream);
+int64_t sr_hist_work(int32_t n_bins);
+
+/* Prescribed field for the workloads: two counter-propagating circularly
+ * polarised waves of amplitude a0 along x (k = omega = 1) forming
+ *   E = 2 a0 cos x (0, cos t, -sin t),  B = 2 a0 sin x (0, -cos t, sin t),
+ * written at the Yee points of the grid at time t (device outputs). */
+int sr_field_standing_wave(float *e[3], float *b[3], const sr_grid *grid, double a0, double t,
+                           void *stream);
+
+/* Counting sort of the particles by tile of tile[0] x tile[1] x tile[2] cells
+ * (tiles x fastest), for gather locality.  src and dst are two particle sets of
+ * the same n (distinct storage); dst receives the permuted particles.  work:
+ * device workspace of sr_sort_work(grid, tile, n) bytes.  Order inside a tile
+ * is unspecified. */
+int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *dst, const sr_grid *grid,
+                      const int32_t tile[3], void *work, void *stream);
+int64_t sr_sort_work(const sr_grid *grid, const int32_t tile[3], int64_t n);
+
+/* Human-readable text for a code. */
+const char *sr_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SR_H */

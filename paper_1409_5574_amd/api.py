@@ -1,0 +1,329 @@
+"""Thin Python layer over libsr.so: builds the C structs from torch tensors and
+calls the entry points with the current HIP stream.  PyTorch provides device
+memory and streams only; all arithmetic of the emission path runs in libsr.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DEV = "cuda"
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def lib():
+    return L.load()
+
+
+# ------------------------------------------------------------------ tables
+class Table:
+    """Device spectrum tables (built in FP64 on the GPU)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        L.check(lib().sr_table_build(C.byref(h), _stream()), "sr_table_build")
+        self.handle = h
+
+    def info(self) -> L.TableInfo:
+        inf = L.TableInfo()
+        L.check(lib().sr_table_query(self.handle, C.byref(inf)), "sr_table_query")
+        return inf
+
+    def free(self):
+        if self.handle:
+            lib().sr_table_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def eval_F(table: Table, x: torch.Tensor) -> torch.Tensor:
+    x = x.contiguous().to(DEV, torch.float32)
+    out = torch.empty_like(x)
+    L.check(lib().sr_eval_synchrotron_F(table.handle, _ptr(x), _ptr(out), x.numel(), _stream()),
+            "sr_eval_synchrotron_F")
+    return out
+
+
+def eval_trial(table: Table, a: torch.Tensor, rate: torch.Tensor, chi: torch.Tensor, kin_cut: bool):
+    a = a.contiguous().to(DEV, torch.int32)
+    rate = rate.contiguous().to(DEV, torch.float32)
+    chi = chi.contiguous().to(DEV, torch.float32)
+    dn = torch.empty_like(rate)
+    xo = torch.empty_like(rate)
+    L.check(lib().sr_eval_trial(table.handle, _ptr(a), _ptr(rate), _ptr(chi), int(kin_cut),
+                                _ptr(dn), _ptr(xo), a.numel(), _stream()), "sr_eval_trial")
+    return dn, xo
+
+
+def philox(ctr: torch.Tensor, seed: int) -> torch.Tensor:
+    """ctr: [n,4] int32 (uint32 bit patterns) -> [n,4] int32."""
+    ctr = ctr.contiguous().to(DEV, torch.int32)
+    out = torch.empty_like(ctr)
+    L.check(lib().sr_philox(_ptr(ctr), seed & 0xFFFFFFFFFFFFFFFF, _ptr(out), ctr.shape[0],
+                            _stream()), "sr_philox")
+    return out
+
+
+# ------------------------------------------------------------------ state objects
+@dataclasses.dataclass
+class Particles:
+    """SoA particle state on the device (FP32 or FP64)."""
+    x: list
+    p: list
+    w: torch.Tensor
+    id: torch.Tensor
+
+    @property
+    def n(self):
+        return int(self.w.numel())
+
+    @property
+    def dtype(self):
+        return self.w.dtype
+
+    @staticmethod
+    def from_numpy(d: dict, dtype=torch.float32, dim: int = 3) -> "Particles":
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+        xs = [t(d["x"]), t(d["y"]), t(d["z"]) if dim == 3 or dim == 0 else None]
+        if dim == 2:
+            xs[2] = None
+        ids = torch.from_numpy(d["id"].astype(np.int64).astype(np.uint32).view(np.int32)).to(DEV)
+        return Particles(xs, [t(d["px"]), t(d["py"]), t(d["pz"])], t(d["w"]), ids)
+
+    def to_numpy(self) -> dict:
+        out = {k: v.double().cpu().numpy() if v is not None else None
+               for k, v in (("x", self.x[0]), ("y", self.x[1]), ("z", self.x[2]))}
+        out.update({"px": self.p[0].double().cpu().numpy(), "py": self.p[1].double().cpu().numpy(),
+                    "pz": self.p[2].double().cpu().numpy(), "w": self.w.double().cpu().numpy(),
+                    "id": self.id.cpu().numpy().view(np.uint32)})
+        return out
+
+    def empty_like(self) -> "Particles":
+        return Particles([None if a is None else torch.empty_like(a) for a in self.x],
+                         [torch.empty_like(a) for a in self.p], torch.empty_like(self.w),
+                         torch.empty_like(self.id))
+
+    def struct(self):
+        S = L.Particles64 if self.dtype == torch.float64 else L.Particles32
+        s = S()
+        s.n = self.n
+        for a in range(3):
+            s.x[a] = None if self.x[a] is None else self.x[a].data_ptr()
+            s.p[a] = self.p[a].data_ptr()
+        s.w = self.w.data_ptr()
+        s.id = self.id.data_ptr()
+        return s
+
+
+def grid_struct(dim: int, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), e0=(0, 0, 0), b0=(0, 0, 0)) -> L.Grid:
+    g = L.Grid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.dx[a] = float(dx[a])
+        g.e0[a] = float(e0[a])
+        g.b0[a] = float(b0[a])
+    if dim == 2:
+        g.n[2] = 1
+    return g
+
+
+class Fields:
+    """Six Yee component arrays (FP32) on the device."""
+
+    def __init__(self, E=None, B=None, ncells: int | None = None):
+        if E is None:
+            self.e = [torch.empty(ncells, device=DEV, dtype=torch.float32) for _ in range(3)]
+            self.b = [torch.empty(ncells, device=DEV, dtype=torch.float32) for _ in range(3)]
+        else:
+            self.e = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in E]
+            self.b = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in B]
+
+    def struct(self) -> L.Fields32:
+        f = L.Fields32()
+        for a in range(3):
+            f.e[a] = self.e[a].data_ptr()
+            f.b[a] = self.b[a].data_ptr()
+        return f
+
+
+def standing_wave(fields: Fields, grid: L.Grid, a0: float, t: float):
+    e = L.P3(*[f.data_ptr() for f in fields.e])
+    b = L.P3(*[f.data_ptr() for f in fields.b])
+    L.check(lib().sr_field_standing_wave(e, b, C.byref(grid), a0, t, _stream()),
+            "sr_field_standing_wave")
+
+
+def n_chunks_uniform(n: int) -> int:
+    return (n + L.SR_CHUNK - 1) // L.SR_CHUNK
+
+
+class PhotonBuffer:
+    def __init__(self, n: int, per_particle: int, n_chunks: int | None = None, dim: int = 3,
+                 with_k: bool = True, with_step: bool = False):
+        n_chunks = n_chunks_uniform(n) if n_chunks is None else n_chunks
+        cap = max(n * per_particle, 1)
+        f = dict(device=DEV, dtype=torch.float32)
+        self.per_particle = per_particle
+        self.n_chunks = n_chunks
+        self.seg_count = torch.zeros(max(n_chunks, 1), device=DEV, dtype=torch.int32)
+        self.eps = torch.empty(cap, **f)
+        self.w = torch.empty(cap, **f)
+        self.dir = [torch.empty(cap, **f) for _ in range(3)]
+        self.pos = [torch.empty(cap, **f) for _ in range(3 if dim != 2 else 2)] + \
+            ([None] if dim == 2 else [])
+        self.parent = torch.empty(cap, device=DEV, dtype=torch.int32)
+        self.k = torch.empty(cap, device=DEV, dtype=torch.uint8) if with_k else None
+        self.step = torch.empty(cap, device=DEV, dtype=torch.int32) if with_step else None
+
+    def struct(self) -> L.PhotonBuf:
+        s = L.PhotonBuf()
+        s.per_particle = self.per_particle
+        s.seg_count = self.seg_count.data_ptr()
+        s.eps = self.eps.data_ptr()
+        s.w = self.w.data_ptr()
+        for a in range(3):
+            s.dir[a] = self.dir[a].data_ptr()
+            s.pos[a] = None if self.pos[a] is None else self.pos[a].data_ptr()
+        s.parent = self.parent.data_ptr()
+        s.k = None if self.k is None else self.k.data_ptr()
+        s.step = None if self.step is None else self.step.data_ptr()
+        return s
+
+    def gather(self, n: int, start: torch.Tensor | None = None) -> dict:
+        """Copy the stored photons of every segment to host numpy arrays."""
+        cnt = self.seg_count.cpu().numpy().view(np.uint32).astype(np.int64)
+        if start is None:
+            s = np.arange(self.n_chunks, dtype=np.int64) * L.SR_CHUNK
+            e = np.minimum(s + L.SR_CHUNK, n)
+        else:
+            st = start.cpu().numpy()
+            s, e = st[:-1], st[1:]
+        cap = (e - s) * self.per_particle
+        stored = np.minimum(cnt, cap)
+        idx = np.concatenate([np.arange(b * self.per_particle, b * self.per_particle + c)
+                              for b, c in zip(s, stored)]) if stored.sum() else np.zeros(0, np.int64)
+        it = torch.from_numpy(idx).to(DEV)
+
+        def g(t):
+            return None if t is None else t[it].cpu().numpy()
+        out = {"eps": g(self.eps), "w": g(self.w),
+               "dir": np.stack([g(d) for d in self.dir], 1) if len(idx) else np.zeros((0, 3)),
+               "pos": np.stack([g(d) if d is not None else np.zeros(len(idx), np.float32)
+                                for d in self.pos], 1) if len(idx) else np.zeros((0, 3)),
+               "parent": g(self.parent).view(np.uint32) if len(idx) else np.zeros(0, np.uint32),
+               "k": g(self.k) if self.k is not None else None,
+               "count": int(cnt.sum()), "stored": int(stored.sum())}
+        return out
+
+
+class LedgerBuf:
+    def __init__(self, n_rows: int, n_chunks: int):
+        self.rows = torch.zeros((max(n_rows, 1), L.SR_LEDGER_COLS), device=DEV, dtype=torch.float64)
+        plen = int(lib().sr_ledger_partials(n_chunks))
+        self.partials = torch.zeros(max(plen, 1), device=DEV, dtype=torch.float64)
+        self.status = torch.zeros(1, device=DEV, dtype=torch.int32)
+        self.n_rows = n_rows
+
+    def struct(self) -> L.Ledger:
+        s = L.Ledger()
+        s.rows = self.rows.data_ptr()
+        s.n_rows = self.n_rows
+        s.partials = self.partials.data_ptr()
+        s.partials_len = self.partials.numel()
+        s.status = self.status.data_ptr()
+        return s
+
+    def row(self, r: int) -> np.ndarray:
+        out = np.zeros(L.SR_LEDGER_COLS)
+        s = self.struct()
+        L.check(lib().sr_energy_ledger(C.byref(s), r, out.ctypes.data_as(C.c_void_p), _stream()),
+                "sr_energy_ledger")
+        return out
+
+    def read_status(self, clear: bool = False) -> int:
+        v = C.c_uint32()
+        s = self.struct()
+        L.check(lib().sr_status(C.byref(s), C.byref(v), int(clear), _stream()), "sr_status")
+        return v.value
+
+
+def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.SR_RECOIL_PHOTON,
+                  dn_policy=L.SR_DN_WEIGHT, kin_cut=False, push_position=True) -> L.Params:
+    return L.Params(float(hbar_n), float(alpha), int(n_samples), int(sampler), int(recoil),
+                    int(dn_policy), int(bool(kin_cut)), int(bool(push_position)))
+
+
+def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, seed: int,
+                     step: int, prm: L.Params, table: Table, photons: PhotonBuffer,
+                     ledger: LedgerBuf, row: int, start: torch.Tensor | None = None,
+                     structs: tuple | None = None):
+    """One emission step.  `structs` may hold pre-built (parts, fields, chunking,
+    photons, ledger) C structs to avoid rebuilding them every call."""
+    if structs is None:
+        structs = make_structs(parts, fields, photons, ledger, start)
+    ps, fs, cs, phs, ls = structs
+    fn = lib().sr_gather_push_emit_f64 if parts.dtype == torch.float64 else lib().sr_gather_push_emit
+    rc = fn(C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid), float(dt),
+            seed & 0xFFFFFFFFFFFFFFFF, int(step), C.byref(prm), table.handle, C.byref(cs),
+            C.byref(phs), C.byref(ls), int(row), _stream())
+    L.check(rc, "sr_gather_push_emit")
+
+
+def make_structs(parts, fields, photons, ledger, start=None):
+    cs = L.Chunking()
+    if start is None:
+        cs.n_chunks = n_chunks_uniform(parts.n)
+        cs.start = None
+    else:
+        cs.n_chunks = start.numel() - 1
+        cs.start = start.data_ptr()
+    return (parts.struct(), fields.struct() if fields is not None else None, cs, photons.struct(),
+            ledger.struct())
+
+
+def spectrum_histogram(photons: PhotonBuffer, n: int, eps_lo: float, eps_hi: float, n_bins: int,
+                       hist: torch.Tensor, work: torch.Tensor, start: torch.Tensor | None = None):
+    cs = L.Chunking()
+    cs.n_chunks = n_chunks_uniform(n) if start is None else start.numel() - 1
+    cs.start = None if start is None else start.data_ptr()
+    phs = photons.struct()
+    L.check(lib().sr_spectrum_histogram(C.byref(phs), C.byref(cs), n, eps_lo, eps_hi, n_bins,
+                                        _ptr(hist), _ptr(work), _stream()), "sr_spectrum_histogram")
+
+
+def hist_work(n_bins: int) -> torch.Tensor:
+    return torch.zeros(int(lib().sr_hist_work(n_bins)), device=DEV, dtype=torch.float64)
+
+
+def sort_work(grid: L.Grid, tile, n: int) -> torch.Tensor:
+    t = (C.c_int32 * 3)(*tile)
+    nbytes = int(lib().sr_sort_work(C.byref(grid), t, n))
+    if nbytes < 0:
+        raise L.SRError("sr_sort_work: bad grid or tile")
+    return torch.empty(max(nbytes, 4), device=DEV, dtype=torch.uint8)
+
+
+def sort_particles(src: Particles, dst: Particles, grid: L.Grid, tile, work: torch.Tensor):
+    t = (C.c_int32 * 3)(*tile)
+    s, d = src.struct(), dst.struct()
+    L.check(lib().sr_sort_particles(C.byref(s), C.byref(d), C.byref(grid), t, _ptr(work),
+                                    _stream()), "sr_sort_particles")

@@ -1,0 +1,320 @@
+// sr_aux.hip -- helpers around the emission step: the prescribed standing-wave
+// field on the Yee grid, the tile counting sort of the particles, the photon
+// spectrum histogram, and error strings.
+#include <math.h>
+
+#include "sr_common.hpp"
+
+namespace sr {
+namespace {
+
+// ------------------------------------------------------------ standing wave
+// E = 2 a0 cos x (0, cos t, -sin t), B = 2 a0 sin x (0, -cos t, sin t), k = omega = 1.
+// Each block owns 4*256 consecutive x cells and loops over rows (y, z); the x
+// profile is computed once per thread in FP64 and rounded to binary32.
+constexpr int kWaveXPerThread = 4;
+
+__global__ __launch_bounds__(256) void standing_wave_kernel(float *ex, float *ey, float *ez,
+                                                            float *bx, float *by, float *bz,
+                                                            int nx, int64_t rows, int rows_per_block,
+                                                            double dx, double a0, double t) {
+    const int i0 = (blockIdx.x * 256 + threadIdx.x) * kWaveXPerThread;
+    if (i0 >= nx) return;
+    const double amp = 2.0 * a0, ct = cos(t), st = sin(t);
+    float vey[kWaveXPerThread], vez[kWaveXPerThread], vby[kWaveXPerThread], vbz[kWaveXPerThread];
+#pragma unroll
+    for (int q = 0; q < kWaveXPerThread; ++q) {
+        const int i = min(i0 + q, nx - 1);
+        const double xe = (double)i * dx;          // Ey, Ez: no x offset
+        const double xb = ((double)i + 0.5) * dx;  // By, Bz: x offset 1/2
+        const double ce = cos(xe), sb = sin(xb);
+        vey[q] = (float)(amp * ce * ct);
+        vez[q] = (float)(-amp * ce * st);
+        vby[q] = (float)(-amp * sb * ct);
+        vbz[q] = (float)(amp * sb * st);
+    }
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+    const int64_t r1 = min(r0 + rows_per_block, rows);
+    const bool vec = (nx % kWaveXPerThread) == 0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const int64_t o = r * nx + i0;
+        if (vec) {
+            *(float4 *)(ex + o) = make_float4(0.f, 0.f, 0.f, 0.f);
+            *(float4 *)(bx + o) = make_float4(0.f, 0.f, 0.f, 0.f);
+            *(float4 *)(ey + o) = make_float4(vey[0], vey[1], vey[2], vey[3]);
+            *(float4 *)(ez + o) = make_float4(vez[0], vez[1], vez[2], vez[3]);
+            *(float4 *)(by + o) = make_float4(vby[0], vby[1], vby[2], vby[3]);
+            *(float4 *)(bz + o) = make_float4(vbz[0], vbz[1], vbz[2], vbz[3]);
+        } else {
+            for (int q = 0; q < kWaveXPerThread && i0 + q < nx; ++q) {
+                ex[o + q] = 0.f; bx[o + q] = 0.f;
+                ey[o + q] = vey[q]; ez[o + q] = vez[q];
+                by[o + q] = vby[q]; bz[o + q] = vbz[q];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ tile sort
+struct SortGeom {
+    int dim;
+    int n[3];
+    int tile[3];
+    int nt[3];          // tiles per axis
+    float inv[3];
+};
+
+__device__ __forceinline__ uint32_t tile_key(const SortGeom &g, float x, float y, float z) {
+    const float v[3] = {x, y, z};
+    uint32_t key = 0, mul = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= g.dim) break;
+        int c = (int)floorf(v[a] * g.inv[a]);
+        c = min(max(c, 0), g.n[a] - 1);
+        key += (uint32_t)(c / g.tile[a]) * mul;
+        mul *= (uint32_t)g.nt[a];
+    }
+    return key;
+}
+
+__global__ void fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void sort_count(const float *x, const float *y, const float *z, int64_t n, SortGeom g,
+                           uint32_t *keys, uint32_t *counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = tile_key(g, x[i], y[i], g.dim == 3 ? z[i] : 0.0f);
+    keys[i] = k;
+    atomicAdd(&counts[k], 1u);
+}
+
+// exclusive scan in blocks of 1024 (256 threads x 4)
+__global__ __launch_bounds__(256) void scan_blocks(const uint32_t *in, uint32_t *out, int64_t n,
+                                                   uint32_t *block_sums) {
+    __shared__ uint32_t s[256];
+    const int64_t b0 = (int64_t)blockIdx.x * 1024;
+    uint32_t v[4], sum = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = b0 + threadIdx.x * 4 + q;
+        v[q] = i < n ? in[i] : 0u;
+        sum += v[q];
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t add = threadIdx.x >= o ? s[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = b0 + threadIdx.x * 4 + q;
+        if (i < n) out[i] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 255 && block_sums) block_sums[blockIdx.x] = s[255];
+}
+
+__global__ void scan_add(uint32_t *out, int64_t n, const uint32_t *block_prefix) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += block_prefix[i / 1024];
+}
+
+__global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const uint32_t *keys,
+                             const uint32_t *offsets, uint32_t *cursor, int dim) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= src.n) return;
+    const uint32_t k = keys[i];
+    const int64_t j = (int64_t)offsets[k] + atomicAdd(&cursor[k], 1u);
+    for (int a = 0; a < 3; ++a) {
+        if (src.x[a] && dst.x[a]) dst.x[a][j] = src.x[a][i];
+        dst.p[a][j] = src.p[a][i];
+    }
+    dst.w[j] = src.w[i];
+    dst.id[j] = src.id[i];
+    (void)dim;
+}
+
+// ------------------------------------------------------------ histogram
+constexpr int kHistBlocks = 512;
+constexpr int kMaxBins = 1024;
+
+__global__ __launch_bounds__(256) void hist_kernel(sr_photon_buf ph, const int64_t *start,
+                                                   int64_t n_chunks, int64_t n, float l2lo,
+                                                   float scale, int nbins, double *work) {
+    extern __shared__ double sh[];   // [2*nbins]
+    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) sh[b] = 0.0;
+    __syncthreads();
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const int64_t s0 = start ? start[c] : c * (int64_t)kBlock;
+        const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kBlock, n);
+        const int64_t cap = (e0 - s0) * ph.per_particle;
+        const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
+        const int64_t base = s0 * ph.per_particle;
+        for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+            const float eps = ph.eps[base + q];
+            const float w = ph.w[base + q];
+            if (!(eps > 0.0f)) continue;
+            const float u = (__log2f(eps) - l2lo) * scale;
+            if (u < 0.0f || u >= (float)nbins) continue;
+            const int bin = (int)u;
+            atomicAdd(&sh[bin], (double)w * (double)eps);
+            atomicAdd(&sh[nbins + bin], (double)w);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x)
+        work[(int64_t)blockIdx.x * 2 * nbins + b] = sh[b];
+}
+
+__global__ void hist_reduce(const double *work, int nblocks, int nvals, double *hist) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nvals) return;
+    double s = 0.0;
+    for (int k = 0; k < nblocks; ++k) s += work[(int64_t)k * nvals + b];
+    hist[b] += s;
+}
+
+}  // namespace
+}  // namespace sr
+
+using namespace sr;
+
+extern "C" int sr_field_standing_wave(float *e[3], float *b[3], const sr_grid *grid, double a0,
+                                      double t, void *stream) {
+    if (!e || !b || !grid) return SR_E_INVAL;
+    for (int q = 0; q < 3; ++q)
+        if (!e[q] || !b[q]) return SR_E_INVAL;
+    if (grid->dim != 2 && grid->dim != 3) return SR_E_INVAL;
+    const int64_t nx = grid->n[0], ny = grid->n[1], nz = grid->dim == 3 ? grid->n[2] : 1;
+    if (nx < 1 || ny < 1 || nz < 1 || nx > (1 << 24) || !(grid->dx[0] > 0.0)) return SR_E_INVAL;
+    const int64_t rows = ny * nz;
+    const unsigned bx = (unsigned)((nx + 256 * kWaveXPerThread - 1) / (256 * kWaveXPerThread));
+    // enough blocks to fill the GPU, each writing a band of rows
+    int64_t by = (4096 + bx - 1) / bx;
+    if (by > rows) by = rows;
+    if (by > 65535) by = 65535;
+    const int rows_per_block = (int)((rows + by - 1) / by);
+    by = (rows + rows_per_block - 1) / rows_per_block;
+    standing_wave_kernel<<<dim3(bx, (unsigned)by), 256, 0, (hipStream_t)stream>>>(
+        e[0], e[1], e[2], b[0], b[1], b[2], (int)nx, rows, rows_per_block, grid->dx[0], a0, t);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+static bool sort_geom(const sr_grid *grid, const int32_t tile[3], SortGeom &g, int64_t &n_tiles) {
+    if (!grid || !tile || (grid->dim != 2 && grid->dim != 3)) return false;
+    g.dim = grid->dim;
+    n_tiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= g.dim) {
+            g.n[a] = 1; g.tile[a] = 1; g.nt[a] = 1; g.inv[a] = 0.0f;
+            continue;
+        }
+        if (grid->n[a] < 1 || grid->n[a] > (1 << 24) || tile[a] < 1 || !(grid->dx[a] > 0.0))
+            return false;
+        g.n[a] = (int)grid->n[a];
+        g.tile[a] = tile[a];
+        g.nt[a] = (int)((grid->n[a] + tile[a] - 1) / tile[a]);
+        g.inv[a] = (float)(1.0 / grid->dx[a]);
+        n_tiles *= g.nt[a];
+    }
+    return n_tiles > 0 && n_tiles < ((int64_t)1 << 31);
+}
+
+extern "C" int64_t sr_sort_work(const sr_grid *grid, const int32_t tile[3], int64_t n) {
+    SortGeom g;
+    int64_t nt;
+    if (n < 0 || !sort_geom(grid, tile, g, nt)) return -1;
+    const int64_t nblk = (nt + 1023) / 1024;
+    // counts, offsets, cursor (n_tiles each), block sums + their prefix, keys (n)
+    return (int64_t)sizeof(uint32_t) * (3 * nt + 2 * (nblk + 1024) + n);
+}
+
+extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *dst,
+                                 const sr_grid *grid, const int32_t tile[3], void *work,
+                                 void *stream) {
+    SortGeom g;
+    int64_t nt;
+    if (!src || !dst || !work || !sort_geom(grid, tile, g, nt)) return SR_E_INVAL;
+    const int64_t n = src->n;
+    if (n < 0 || dst->n != n || n > 0xFFFFFFFFll) return SR_E_INVAL;
+    if (n == 0) return SR_OK;
+    for (int a = 0; a < 3; ++a)
+        if (!src->p[a] || !dst->p[a]) return SR_E_INVAL;
+    if (!src->x[0] || !src->x[1] || (g.dim == 3 && !src->x[2]) || !src->w || !src->id ||
+        !dst->x[0] || !dst->x[1] || (g.dim == 3 && !dst->x[2]) || !dst->w || !dst->id)
+        return SR_E_INVAL;
+    const int64_t nblk = (nt + 1023) / 1024;
+    if (nblk > 1024 * 1024) return SR_E_UNSUPPORTED;
+    uint32_t *counts = (uint32_t *)work;
+    uint32_t *offsets = counts + nt;
+    uint32_t *cursor = offsets + nt;
+    uint32_t *bsum = cursor + nt;
+    uint32_t *bpre = bsum + nblk + 1024;
+    uint32_t *keys = bpre + nblk + 1024;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned g256 = (unsigned)((nt + 255) / 256);
+    fill_u32<<<g256, 256, 0, st>>>(counts, nt, 0u);
+    fill_u32<<<g256, 256, 0, st>>>(cursor, nt, 0u);
+    sort_count<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src->x[0], src->x[1], src->x[2], n, g,
+                                                            keys, counts);
+    scan_blocks<<<(unsigned)nblk, 256, 0, st>>>(counts, offsets, nt, bsum);
+    if (nblk > 1) {
+        // scan of the block sums: at most 1024*1024 tiles, so one more level of
+        // blocks and a final single-block scan suffice
+        const int64_t nblk2 = (nblk + 1023) / 1024;
+        uint32_t *b2sum = bpre + nblk;   // fits: bpre has nblk + 1024 slots
+        scan_blocks<<<(unsigned)nblk2, 256, 0, st>>>(bsum, bpre, nblk, nblk2 > 1 ? b2sum : nullptr);
+        if (nblk2 > 1) {
+            uint32_t *b2pre = bsum + nblk;   // bsum has nblk + 1024 slots
+            scan_blocks<<<1, 256, 0, st>>>(b2sum, b2pre, nblk2, nullptr);
+            scan_add<<<(unsigned)((nblk + 255) / 256), 256, 0, st>>>(bpre, nblk, b2pre);
+        }
+        scan_add<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(offsets, nt, bpre);
+    }
+    sort_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(*src, *dst, keys, offsets, cursor,
+                                                              g.dim);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int64_t sr_hist_work(int32_t n_bins) {
+    if (n_bins < 1 || n_bins > kMaxBins) return -1;
+    return (int64_t)kHistBlocks * 2 * n_bins;
+}
+
+extern "C" int sr_spectrum_histogram(const sr_photon_buf *ph, const sr_chunking *chunks,
+                                     int64_t n, double eps_lo, double eps_hi, int32_t n_bins,
+                                     double *hist, double *work, void *stream) {
+    if (!ph || !chunks || !hist || !work || n < 0 || n_bins < 1 || n_bins > kMaxBins ||
+        !(eps_lo > 0.0) || !(eps_hi > eps_lo) || !ph->seg_count)
+        return SR_E_INVAL;
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kBlock - 1) / kBlock;
+    if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
+    if (!ph->eps || !ph->w) return SR_E_INVAL;
+    const float l2lo = (float)log2(eps_lo);
+    const float scale = (float)(n_bins / (log2(eps_hi) - log2(eps_lo)));
+    const int nb = (int)(n_chunks < kHistBlocks ? n_chunks : kHistBlocks);
+    hipStream_t st = (hipStream_t)stream;
+    hist_kernel<<<nb, 256, sizeof(double) * 2 * n_bins, st>>>(*ph, chunks->start, n_chunks, n,
+                                                               l2lo, scale, n_bins, work);
+    hist_reduce<<<(2 * n_bins + 255) / 256, 256, 0, st>>>(work, nb, 2 * n_bins, hist);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" const char *sr_strerror(int code) {
+    switch (code) {
+        case SR_OK: return "ok";
+        case SR_E_INVAL: return "invalid argument";
+        case SR_E_HIP: return "HIP runtime error";
+        case SR_E_NOMEM: return "device allocation failed";
+        case SR_E_UNSUPPORTED: return "unsupported request";
+        default: return "unknown error code";
+    }
+}

@@ -1,0 +1,297 @@
+// sr_common.hpp -- device helpers shared by the libsr kernels (gfx950, wave64).
+//
+// Normalised units, c = m = e = 1, electron charge q = -1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sr.h"
+
+#define SR_HIP_CHECK(expr)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return SR_E_HIP;               \
+    } while (0)
+
+namespace sr {
+
+constexpr int kBlock = 256;     // threads per block, one particle each
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxK = 16;       // largest supported number of trials per step
+
+// ---------------------------------------------------------------------------
+// Synchrotron-function table (built in FP64 by the table kernels, read here).
+// Two families of cubic pieces in t = log2 x with 32 pieces per unit of t:
+//   lower (x below the proposal branch point):  L(t) = log2( F(x) / x^{1/3} )
+//   upper (x above it):                         L(t) = log2( F(x) e^{x} / x^{1/3} )
+// Both stay O(1) over their ranges, so a binary32 cubic holds them to ~1e-7.
+// Piece j covers t in [j/32, (j+1)/32); coefficients are for s in [0,1).
+// ---------------------------------------------------------------------------
+constexpr int kFPerUnit = 32;
+constexpr int kFLoJ0 = -592;    // t from -18.5 (x = 2^-18.5) ...
+constexpr int kFLoN = 592;      // ... to 0
+constexpr int kFUpJ0 = -32;     // t from -1 ...
+constexpr int kFUpN = 176;      // ... to 4.5 (x = 22.6)
+constexpr int kFTotal = kFLoN + kFUpN;
+
+// Direct samplers.  With the kinematic cut the photon-number CDF is
+// N(x)/N(xmax(chi)), N(x) = int_0^x F(t)/t dt, xmax = 2/(3 chi); hence
+// x = T1(U) with U = u r(chi), r = N(xmax)/N(inf), T1 the uncut inverse CDF.
+//   T1: cubic pieces of y = log2 x in w = logit(U) on [-kT1W, kT1W].
+//   r : r(chi) and 1 - r(chi) on log10 chi nodes, linear between nodes.
+constexpr int kT1N = 6144;              // pieces of T1 (128 per unit of logit)
+constexpr double kT1W = 24.0;           // logit range: U down to 3.8e-11
+constexpr int kRPerDecade = 512;
+constexpr double kRLogChiLo = -6.0;     // below: r = 1 to binary32 precision
+constexpr double kRLogChiHi = 4.0;      // above: r ~ chi^{-1/3} (small-x form of N)
+constexpr int kRN = (int)((kRLogChiHi - kRLogChiLo) * kRPerDecade) + 1;
+
+struct TableDev {
+    const float4 *ftab;     // [kFTotal]
+    float pa;               // binary32 branch point P(a)
+    const float4 *t1;       // [kT1N]
+    const float2 *r;        // [kRN] (r, 1 - r)
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(m1 >> 32) ^ c.y ^ k0, (uint32_t)m1,
+                       (uint32_t)(m0 >> 32) ^ c.w ^ k1, (uint32_t)m0);
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// F-table lookup.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ftab_eval(const float4 *__restrict__ tab, float t, int j0, int n,
+                                           int base) {
+    const float u = t * (float)kFPerUnit;   // exact scaling
+    const float fj = floorf(u);
+    int j = (int)fj - j0;
+    j = min(max(j, 0), n - 1);
+    const float s = u - (float)(j + j0);    // exact for in-range t
+    const float4 c = tab[base + j];
+    return fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
+}
+
+// One Monte-Carlo trial with the proposal S(x) (steps 3-5 of the recipe at the
+// end of section "Monte Carlo method").  `a` is the uniform word for R' (23-bit
+// midpoint, never 0 or 1).  Returns dN = rate F(x)/(x S(x)) and writes x.
+//   lower branch (R' <= P(a)):  x = R'^{3/4},  x S = (4/3) R'
+//   upper branch:               x = -ln((9/7)(1-R')),  S = 1 - R' = (7/9) e^{-x}
+__device__ __forceinline__ float trial_dn(uint32_t a, float rate, const float4 *__restrict__ tab,
+                                          float pa, float &x) {
+    const float rp = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
+    float q;
+    if (rp <= pa) {
+        const float s = sqrtf(rp);
+        x = s * sqrtf(s);
+        const float t = 0.75f * __log2f(rp);
+        const float L = ftab_eval(tab, t, kFLoJ0, kFLoN, 0);
+        // F/(x S) = (3/4) (F / x^{1/3}) / x
+        q = 0.75f * __fdividef(exp2f(L), x);
+    } else {
+        const float om = 1.0f - rp;          // exact
+        x = -0.69314718055994531f * __log2f(om) - 0.25131442828090605f;  // -ln om - ln(9/7)
+        const float t = __log2f(x);
+        const float L = ftab_eval(tab, t, kFUpJ0, kFUpN, kFLoN);
+        // F/(x S) = (9/7) F e^{x} / x = (9/7) 2^{L} x^{-2/3}
+        q = 1.2857142857142857f * exp2f(L - 0.66666666666666667f * t);
+    }
+    return rate * q;
+}
+
+// r(chi) and 1 - r(chi), linear in log10 chi; r ~ chi^{-1/3} above the table.
+__device__ __forceinline__ float2 r_lookup(const float2 *__restrict__ rt, float chi) {
+    if (!(chi > 0.0f)) return make_float2(1.0f, 0.0f);
+    const float u = (__log2f(chi) * 0.30102999566398120f - (float)kRLogChiLo) * (float)kRPerDecade;
+    if (u <= 0.0f) return rt[0];
+    if (u >= (float)(kRN - 1)) {
+        const float r = rt[kRN - 1].x * exp2f((float)(kRN - 1 - u) * (1.0f / 3.0f) *
+                                              (3.3219280948873623f / kRPerDecade));
+        return make_float2(r, 1.0f - r);
+    }
+    const int j = (int)u;
+    const float s = u - (float)j;
+    const float2 a = rt[j], b = rt[j + 1];
+    return make_float2(fmaf(s, b.x - a.x, a.x), fmaf(s, b.y - a.y, a.y));
+}
+
+// x = T1(U) from ln U and ln(1-U) (the uncut inverse number-CDF).
+__device__ __forceinline__ float t1_log2x(const float4 *__restrict__ t1, float lnU, float ln1mU) {
+    const float w = lnU - ln1mU;
+    const float u = (w + (float)kT1W) * (float)(kT1N / (2.0 * kT1W));
+    int j = (int)floorf(u);
+    j = min(max(j, 0), kT1N - 1);
+    const float s = u - (float)j;
+    const float4 c = t1[j];
+    return fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
+}
+
+// ln U and ln(1-U) for U = u r with u a 23-bit midpoint from word a and
+// (r, 1-r) from r_lookup: 1 - U = (1-u) + u (1-r) keeps the upper tail exact.
+__device__ __forceinline__ void direct_u(uint32_t a, float2 r, float &lnU, float &ln1mU) {
+    const float u = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
+    const float om = 1.0f - u;  // exact
+    lnU = 0.69314718055994531f * (__log2f(u) + __log2f(r.x));
+    ln1mU = 0.69314718055994531f * __log2f(fmaf(u, r.y, om));
+}
+
+// ---------------------------------------------------------------------------
+// Grid description passed to the kernels.
+// ---------------------------------------------------------------------------
+struct GridK {
+    int dim;
+    int n[3];
+    float inv_hi[3], inv_lo[3];   // 1/dx split into a binary32 pair
+    double inv_d[3];              // 1/dx in FP64 (FP64 path)
+    float L[3];                   // box lengths (binary32)
+    double Ld[3];                 // box lengths (FP64)
+    float e0[3], b0[3];           // uniform fields (dim 0)
+    double e0d[3], b0d[3];
+};
+
+// Cell index and fraction of a coordinate for nodes at offset 0 and 1/2.
+template <typename R>
+struct Axis {
+    int i0, i1;    // base nodes (wrapped) for offset 0 and 1/2
+    int i0p, i1p;  // next nodes (wrapped)
+    R f0, f1;      // fractions
+};
+
+// One periodic wrap, then a clamp so that even a corrupt position (NaN, far
+// outside the box) can never index outside the grid.
+__device__ __forceinline__ int wrap_i(int i, int n) {
+    i = i < 0 ? i + n : (i >= n ? i - n : i);
+    return min(max(i, 0), n - 1);
+}
+
+// binary32: u = x/dx with the product split so the fraction keeps ~2^-24 absolute accuracy
+__device__ __forceinline__ void axis_setup(float x, float inv_hi, float inv_lo, int n,
+                                           Axis<float> &ax) {
+    const float u = x * inv_hi;
+    float fi = floorf(u);
+    float f = fmaf(x, inv_hi, -fi) + x * inv_lo;
+    if (f < 0.0f) { f += 1.0f; fi -= 1.0f; }
+    if (f >= 1.0f) { f -= 1.0f; fi += 1.0f; }
+    int i0 = (int)fi;
+    int i1;
+    float f1;
+    if (f >= 0.5f) { i1 = i0; f1 = f - 0.5f; } else { i1 = i0 - 1; f1 = f + 0.5f; }
+    ax.i0 = wrap_i(i0, n);
+    ax.i0p = wrap_i(ax.i0 + 1, n);
+    ax.i1 = wrap_i(i1, n);
+    ax.i1p = wrap_i(ax.i1 + 1, n);
+    ax.f0 = f;
+    ax.f1 = f1;
+}
+
+__device__ __forceinline__ void axis_setup(double x, double inv, int n, Axis<double> &ax) {
+    const double u = x * inv;
+    double fi = floor(u);
+    double f = u - fi;
+    int i0 = (int)fi;
+    int i1;
+    double f1;
+    if (f >= 0.5) { i1 = i0; f1 = f - 0.5; } else { i1 = i0 - 1; f1 = f + 0.5; }
+    ax.i0 = wrap_i(i0, n);
+    ax.i0p = wrap_i(ax.i0 + 1, n);
+    ax.i1 = wrap_i(i1, n);
+    ax.i1p = wrap_i(ax.i1 + 1, n);
+    ax.f0 = f;
+    ax.f1 = f1;
+}
+
+// Bilinear (2D) / trilinear (3D) interpolation of one component.  sx, sy, sz
+// select offset 0 (false) or 1/2 (true) on each axis.
+template <typename R, int DIM>
+__device__ __forceinline__ R cic(const float *__restrict__ a, const Axis<R> &X, const Axis<R> &Y,
+                                 const Axis<R> &Z, bool sx, bool sy, bool sz, int nx, int ny) {
+    const int ix0 = sx ? X.i1 : X.i0, ix1 = sx ? X.i1p : X.i0p;
+    const R fx = sx ? X.f1 : X.f0;
+    const int iy0 = sy ? Y.i1 : Y.i0, iy1 = sy ? Y.i1p : Y.i0p;
+    const R fy = sy ? Y.f1 : Y.f0;
+    const R gx = (R)1 - fx, gy = (R)1 - fy;
+    if (DIM == 2) {
+        const int64_t r0 = (int64_t)iy0 * nx, r1 = (int64_t)iy1 * nx;
+        const R v00 = (R)a[r0 + ix0], v01 = (R)a[r0 + ix1];
+        const R v10 = (R)a[r1 + ix0], v11 = (R)a[r1 + ix1];
+        return gy * (gx * v00 + fx * v01) + fy * (gx * v10 + fx * v11);
+    } else {
+        const int iz0 = sz ? Z.i1 : Z.i0, iz1 = sz ? Z.i1p : Z.i0p;
+        const R fz = sz ? Z.f1 : Z.f0;
+        const R gz = (R)1 - fz;
+        const int64_t p00 = ((int64_t)iz0 * ny + iy0) * nx, p01 = ((int64_t)iz0 * ny + iy1) * nx;
+        const int64_t p10 = ((int64_t)iz1 * ny + iy0) * nx, p11 = ((int64_t)iz1 * ny + iy1) * nx;
+        const R c00 = gx * (R)a[p00 + ix0] + fx * (R)a[p00 + ix1];
+        const R c01 = gx * (R)a[p01 + ix0] + fx * (R)a[p01 + ix1];
+        const R c10 = gx * (R)a[p10 + ix0] + fx * (R)a[p10 + ix1];
+        const R c11 = gx * (R)a[p11 + ix0] + fx * (R)a[p11 + ix1];
+        return gz * (gy * c00 + fy * c01) + fz * (gy * c10 + fy * c11);
+    }
+}
+
+// a*b - c*d with one rounding error (Kahan's fused algorithm).
+__device__ __forceinline__ float diff_of_products(float a, float b, float c, float d) {
+    const float w = c * d;
+    const float e = fmaf(-c, d, w);
+    const float f = fmaf(a, b, -w);
+    return f + e;
+}
+__device__ __forceinline__ double diff_of_products(double a, double b, double c, double d) {
+    return a * b - c * d;
+}
+
+template <typename R> __device__ __forceinline__ R sqrt_r(R v);
+template <> __device__ __forceinline__ float sqrt_r<float>(float v) { return sqrtf(v); }
+template <> __device__ __forceinline__ double sqrt_r<double>(double v) { return sqrt(v); }
+
+// ---------------------------------------------------------------------------
+// Wave64 reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Logical chunk for a block so that chunks adjacent in memory land on the same
+// XCD (blocks are dealt round-robin to the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8;
+    const int64_t xcd = b % 8, local = b / 8;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+}  // namespace sr
+
+// Host-side table object.
+struct sr_table {
+    float4 *ftab = nullptr;
+    float4 *t1 = nullptr;
+    float2 *r = nullptr;
+    float pa = 0.0f;
+    double a = 0.0;
+    int device = 0;
+};

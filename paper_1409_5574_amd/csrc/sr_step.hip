@@ -1,0 +1,590 @@
+// sr_step.hip -- the per-particle, per-step emission kernel and its ledger
+// reduction.
+//
+// One thread per macro-electron, one block (256 threads, 4 waves) per chunk of
+// the particle array.  Per particle (section "Numerical implementation" and
+// the recipe at the end of section "Monte Carlo method"):
+//   gather E, B at x^n -> Boris push -> H_eff (eq:effective_H, dp_perp/p <= 1)
+//   -> omega_c = 1.5 H gamma^2, chi = hbar_n H gamma -> K trials
+//   -> photon append -> recoil -> position push.
+// Photon append uses no global atomics: each chunk owns a segment of the
+// photon buffer, the wave ballot + lane prefix (mbcnt) give every emitted
+// trial its slot inside the wave, and the four wave totals are combined in
+// LDS.  The FP64 ledger is reduced per block and written as one partial row per
+// chunk, then summed in a fixed order by ledger_reduce (deterministic).
+#include <math.h>
+
+#include "sr_common.hpp"
+
+namespace sr {
+namespace {
+
+template <typename R>
+struct StepArgs {
+    int64_t n;
+    R *x[3];
+    R *p[3];
+    const R *w;
+    const uint32_t *id;
+    const float *f[6];
+    GridK g;
+    R dt;
+    uint32_t seed_lo, seed_hi, step;
+    int K, recoil, dn_policy, kin_cut, push_position, has_pos;
+    R hbar_n;
+    float rate_c;      // dt sqrt3/(2 pi) alpha        (x H gives the trial rate)
+    float direct_c;    // dt 5/(2 sqrt3) alpha          (x H r gives the direct rate)
+    R ll_c;            // (2/3)(alpha/hbar_n) dt        (x chi^2 beta^2 gives the LL loss)
+    TableDev tab;
+    const int64_t *start;
+    int64_t per_particle;
+    uint32_t *seg_count;
+    float *ph_eps, *ph_w, *ph_dir[3], *ph_pos[3];
+    uint32_t *ph_parent, *ph_step;
+    uint8_t *ph_k;
+    double *partials;
+    uint32_t *status;
+};
+
+template <typename R>
+__device__ __forceinline__ void setup_axis(const GridK &g, int ax, R x, Axis<R> &A);
+template <>
+__device__ __forceinline__ void setup_axis<float>(const GridK &g, int ax, float x, Axis<float> &A) {
+    axis_setup(x, g.inv_hi[ax], g.inv_lo[ax], g.n[ax], A);
+}
+template <>
+__device__ __forceinline__ void setup_axis<double>(const GridK &g, int ax, double x,
+                                                   Axis<double> &A) {
+    axis_setup(x, g.inv_d[ax], g.n[ax], A);
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void gather_grid(const StepArgs<R> &a, const R pos[3], R E[3], R B[3]) {
+    Axis<R> X, Y, Z;
+    setup_axis<R>(a.g, 0, pos[0], X);
+    setup_axis<R>(a.g, 1, pos[1], Y);
+    if (DIM == 3) setup_axis<R>(a.g, 2, pos[2], Z);
+    else Z = Y;
+    const int nx = a.g.n[0], ny = a.g.n[1];
+    // Yee offsets: Ex(1/2,0,0) Ey(0,1/2,0) Ez(0,0,1/2) Bx(0,1/2,1/2) By(1/2,0,1/2) Bz(1/2,1/2,0)
+    E[0] = cic<R, DIM>(a.f[0], X, Y, Z, true, false, false, nx, ny);
+    E[1] = cic<R, DIM>(a.f[1], X, Y, Z, false, true, false, nx, ny);
+    E[2] = cic<R, DIM>(a.f[2], X, Y, Z, false, false, true, nx, ny);
+    B[0] = cic<R, DIM>(a.f[3], X, Y, Z, false, true, true, nx, ny);
+    B[1] = cic<R, DIM>(a.f[4], X, Y, Z, true, false, true, nx, ny);
+    B[2] = cic<R, DIM>(a.f[5], X, Y, Z, true, true, false, nx, ny);
+}
+
+template <typename R> __device__ __forceinline__ R box_len(const GridK &g, int q);
+template <> __device__ __forceinline__ float box_len<float>(const GridK &g, int q) { return g.L[q]; }
+template <> __device__ __forceinline__ double box_len<double>(const GridK &g, int q) { return g.Ld[q]; }
+template <typename R> __device__ __forceinline__ R uniform_e(const GridK &g, int q);
+template <typename R> __device__ __forceinline__ R uniform_b(const GridK &g, int q);
+template <> __device__ __forceinline__ float uniform_e<float>(const GridK &g, int q) { return g.e0[q]; }
+template <> __device__ __forceinline__ double uniform_e<double>(const GridK &g, int q) { return g.e0d[q]; }
+template <> __device__ __forceinline__ float uniform_b<float>(const GridK &g, int q) { return g.b0[q]; }
+template <> __device__ __forceinline__ double uniform_b<double>(const GridK &g, int q) { return g.b0d[q]; }
+
+template <typename R>
+__device__ __forceinline__ R wrap_pos(R v, R L) {
+    if (v >= L) v -= L;
+    else if (v < (R)0) v += L;
+    if (v >= L || v < (R)0) v = (R)0;   // rounding guard (and a corrupt value)
+    return v;
+}
+
+template <typename R, int DIM, int KMAX, int SAMPLER>
+__global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) {
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ double s_red[kWaves][7];
+    __shared__ float s_chi[kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int64_t s0 = a.start ? a.start[c] : c * (int64_t)kBlock;
+    const int64_t e0 = a.start ? a.start[c + 1] : min(s0 + (int64_t)kBlock, a.n);
+    const int64_t seg_base = s0 * a.per_particle;
+    const int64_t seg_cap = (e0 - s0) * a.per_particle;
+    const int K = a.K;
+    const float invK = 1.0f / (float)K;
+
+    double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0,
+           acc_w = 0.0;
+    float chi_max = 0.0f;
+    uint32_t flags = 0;
+    int64_t run_base = 0;
+
+    for (int64_t base = s0; base < e0; base += kBlock) {
+        const int64_t i = base + tid;
+        const bool active = i < e0;
+        uint32_t bits = 0;
+        float xk[KMAX], fk[KMAX];
+        float eps_unit = 0.0f, wi_f = 0.0f;
+        float dirf[3] = {0.0f, 0.0f, 0.0f}, posf[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t pid = 0;
+        if (active) {
+            const R wi = a.w[i];
+            pid = a.id[i];
+            R pos[3] = {(R)0, (R)0, (R)0};
+            if (a.has_pos) {
+                pos[0] = a.x[0][i];
+                if (DIM != 0 || a.x[1]) pos[1] = a.x[1][i];
+                if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = a.x[2][i];
+            }
+            const R p0[3] = {a.p[0][i], a.p[1][i], a.p[2][i]};
+            R E[3], B[3];
+            if (DIM == 0) {
+                for (int q = 0; q < 3; ++q) { E[q] = uniform_e<R>(a.g, q); B[q] = uniform_b<R>(a.g, q); }
+            } else {
+                gather_grid<R, DIM>(a, pos, E, B);
+            }
+            // ---- Boris push (q = -1), keeping the momentum increment d explicitly
+            const R h = (R)(-0.5) * a.dt;
+            const R um[3] = {p0[0] + h * E[0], p0[1] + h * E[1], p0[2] + h * E[2]};
+            const R gm = sqrt_r<R>((R)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+            const R hg = h / gm;
+            const R t[3] = {hg * B[0], hg * B[1], hg * B[2]};
+            const R t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+            const R sc = (R)2 / ((R)1 + t2);
+            const R sv[3] = {sc * t[0], sc * t[1], sc * t[2]};
+            const R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]),
+                             um[1] + (um[2] * t[0] - um[0] * t[2]),
+                             um[2] + (um[0] * t[1] - um[1] * t[0])};
+            const R d[3] = {(up[1] * sv[2] - up[2] * sv[1]) + (R)2 * h * E[0],
+                            (up[2] * sv[0] - up[0] * sv[2]) + (R)2 * h * E[1],
+                            (up[0] * sv[1] - up[1] * sv[0]) + (R)2 * h * E[2]};
+            R pn[3] = {p0[0] + d[0], p0[1] + d[1], p0[2] + d[2]};
+            // ---- H_eff (eq:effective_H) from the mean momentum and d, limited
+            const R pb[3] = {p0[0] + (R)0.5 * d[0], p0[1] + (R)0.5 * d[1], p0[2] + (R)0.5 * d[2]};
+            const R p2 = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2];
+            const R cx = diff_of_products(pb[1], d[2], pb[2], d[1]);
+            const R cy = diff_of_products(pb[2], d[0], pb[0], d[2]);
+            const R cz = diff_of_products(pb[0], d[1], pb[1], d[0]);
+            const R c2 = cx * cx + cy * cy + cz * cz;
+            const R g_old = sqrt_r<R>((R)1 + p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
+            const R g_new = sqrt_r<R>((R)1 + pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+            const R gb = (R)0.5 * (g_old + g_new);
+            R ratio = p2 > (R)0 ? sqrt_r<R>(c2) / p2 : (R)0;
+            if (ratio > (R)1) ratio = (R)1;
+            const R H = gb * ratio / a.dt;
+            const R chi = a.hbar_n * H * gb;
+            const R pbm = sqrt_r<R>(p2);
+            const float Hf = (float)H, chif = (float)chi, gbf = (float)gb;
+            if (pbm > (R)0) {
+                const R inv = (R)1 / pbm;
+                dirf[0] = (float)(pb[0] * inv); dirf[1] = (float)(pb[1] * inv);
+                dirf[2] = (float)(pb[2] * inv);
+            }
+            posf[0] = (float)pos[0]; posf[1] = (float)pos[1]; posf[2] = (float)pos[2];
+            chi_max = fmaxf(chi_max, chif);
+            eps_unit = 1.5f * chif * gbf;          // hbar omega_c: photon energy per unit x
+            wi_f = (float)wi;
+
+            // ---- K trials
+            float rate;
+            float2 rr = make_float2(1.0f, 0.0f);
+            if (SAMPLER == SR_SAMPLER_S) {
+                rate = a.rate_c * Hf;
+            } else {
+                if (a.kin_cut) rr = r_lookup(a.tab.r, chif);
+                rate = a.direct_c * Hf * rr.x;      // total (cut) photon rate per trial
+            }
+            const float cut15 = a.kin_cut ? 1.5f * chif : 0.0f;
+            uint4 words = make_uint4(0, 0, 0, 0);
+            float delta_ph = 0.0f, e_emit = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                xk[k] = 0.0f;
+                fk[k] = 0.0f;
+                if (k < K) {
+                    if ((k & 1) == 0)
+                        words = philox4x32_10(make_uint4(pid, a.step, (uint32_t)(k >> 1), 0u),
+                                              a.seed_lo, a.seed_hi);
+                    const uint32_t wa = (k & 1) ? words.z : words.x;
+                    const uint32_t wb = (k & 1) ? words.w : words.y;
+                    float x = 0.0f, dn;
+                    if (SAMPLER == SR_SAMPLER_S) {
+                        dn = trial_dn(wa, rate, a.tab.ftab, a.tab.pa, x);
+                        if (cut15 * x > 1.0f) dn = 0.0f;
+                    } else {
+                        dn = rate;
+                    }
+                    bool emit;
+                    float frac = invK;
+                    if (dn >= 1.0f) {
+                        emit = true;
+                        if (a.dn_policy == SR_DN_WEIGHT) frac = dn * invK;
+                    } else {
+                        emit = wb < (uint32_t)(dn * 4294967296.0f);
+                    }
+                    if (emit) {
+                        if (SAMPLER != SR_SAMPLER_S) {
+                            float lnU, ln1mU;
+                            direct_u(wa, rr, lnU, ln1mU);
+                            x = exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                        }
+                        bits |= 1u << k;
+                        xk[k] = x;
+                        fk[k] = frac;
+                        const float eps = eps_unit * x;
+                        delta_ph += frac * eps;
+                        e_emit += frac * eps;
+                    }
+                }
+            }
+            acc_emit += (double)wi_f * (double)e_emit;
+            // Landau-Lifshitz loss of the step (eq:LLformOfRRForce)
+            const R beta2 = p2 / (gb * gb);
+            acc_ll += (double)(wi * a.ll_c * chi * chi * beta2);
+
+            // ---- recoil along the post-push momentum
+            R delta = (R)0;
+            if (a.recoil == SR_RECOIL_PHOTON) delta = (R)delta_ph;
+            else if (a.recoil == SR_RECOIL_LL) delta = a.ll_c * chi * chi * pbm / gb;
+            R g_after = g_new;
+            if (delta > (R)0) {
+                const R pm = sqrt_r<R>(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+                R fac = pm > (R)0 ? (R)1 - delta / pm : (R)-1;
+                R removed = delta;
+                if (fac < (R)0) {
+                    acc_clamp += (double)(wi * (delta - pm));
+                    removed = pm;
+                    fac = (R)0;
+                    flags |= SR_W_RECOIL_CLAMP;
+                }
+                pn[0] *= fac; pn[1] *= fac; pn[2] *= fac;
+                const R pm_after = fac * pm;
+                g_after = sqrt_r<R>((R)1 + pm_after * pm_after);
+                // gamma_after - gamma_before without cancellation
+                acc_de += (double)(-wi * removed * (pm_after + pm) / (g_after + g_new));
+            }
+            if (!(isfinite(pn[0]) && isfinite(pn[1]) && isfinite(pn[2]) && isfinite(H)))
+                flags |= SR_W_NONFINITE;
+            a.p[0][i] = pn[0]; a.p[1][i] = pn[1]; a.p[2][i] = pn[2];
+            // ---- position push
+            if (a.push_position && a.has_pos) {
+                const R vdt = a.dt / g_after;
+                if (DIM == 0) {
+                    a.x[0][i] = pos[0] + vdt * pn[0];
+                    if (a.x[1]) a.x[1][i] = pos[1] + vdt * pn[1];
+                    if (a.x[2]) a.x[2][i] = pos[2] + vdt * pn[2];
+                } else {
+                    a.x[0][i] = wrap_pos<R>(pos[0] + vdt * pn[0], box_len<R>(a.g, 0));
+                    a.x[1][i] = wrap_pos<R>(pos[1] + vdt * pn[1], box_len<R>(a.g, 1));
+                    if (DIM == 3) a.x[2][i] = wrap_pos<R>(pos[2] + vdt * pn[2], box_len<R>(a.g, 2));
+                }
+            }
+            acc_w += (double)wi;
+        }
+
+        // ---- photon slots: per trial a ballot, the lane prefix, then wave totals in LDS
+        uint32_t off[KMAX];
+        uint32_t wave_tot = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            off[k] = 0;
+            if (k < K) {
+                const uint64_t m = __ballot((bits >> k) & 1u);
+                off[k] = wave_tot + lane_prefix(m);
+                wave_tot += (uint32_t)__popcll(m);
+            }
+        }
+        if (lane == 0) s_wave[wave] = wave_tot;
+        __syncthreads();
+        uint32_t wave_base = 0, blk_tot = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            const uint32_t v = s_wave[q];
+            wave_base += q < wave ? v : 0u;
+            blk_tot += v;
+        }
+        __syncthreads();
+        if (bits) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < K && ((bits >> k) & 1u)) {
+                    const int64_t slot = run_base + wave_base + off[k];
+                    const float eps = eps_unit * xk[k];
+                    const float wph = wi_f * fk[k];
+                    if (slot < seg_cap) {
+                        const int64_t o = seg_base + slot;
+                        a.ph_eps[o] = eps;
+                        a.ph_w[o] = wph;
+                        a.ph_dir[0][o] = dirf[0];
+                        a.ph_dir[1][o] = dirf[1];
+                        a.ph_dir[2][o] = dirf[2];
+                        if (a.ph_pos[0]) a.ph_pos[0][o] = posf[0];
+                        if (a.ph_pos[1]) a.ph_pos[1][o] = posf[1];
+                        if (a.ph_pos[2]) a.ph_pos[2][o] = posf[2];
+                        a.ph_parent[o] = pid;
+                        if (a.ph_k) a.ph_k[o] = (uint8_t)k;
+                        if (a.ph_step) a.ph_step[o] = a.step;
+                    } else {
+                        acc_drop += (double)wph * (double)eps;
+                        flags |= SR_W_PHOTON_OVERFLOW;
+                    }
+                }
+            }
+        }
+        run_base += blk_tot;
+    }
+
+    // ---- per-chunk ledger partials (FP64, fixed reduction order)
+    const double v[7] = {wave_sum(acc_emit), wave_sum(acc_ll), wave_sum(acc_de),
+                         wave_sum(acc_clamp), wave_sum(acc_drop), 0.0, wave_sum(acc_w)};
+    const float cm = wave_max(chi_max);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) s_red[wave][q] = v[q];
+        s_chi[wave] = cm;
+    }
+    // latch device-side conditions: one atomic per wave, only when something happened
+    uint32_t wf = flags;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wf |= (uint32_t)__shfl_xor((int)wf, o, 64);
+    if (lane == 0 && wf) atomicOr(a.status, wf);
+    __syncthreads();
+    if (tid == 0) {
+        double* row = a.partials + c * SR_LEDGER_COLS;
+        for (int q = 0; q < 7; ++q) {
+            double sum = 0.0;
+            for (int wv = 0; wv < kWaves; ++wv) sum += s_red[wv][q];
+            row[q] = sum;
+        }
+        row[SR_LED_PHOTONS] = (double)run_base;
+        float m = 0.0f;
+        for (int wv = 0; wv < kWaves; ++wv) m = fmaxf(m, s_chi[wv]);
+        row[SR_LED_CHI_MAX] = (double)m;
+        a.seg_count[c] = (uint32_t)min(run_base, (int64_t)0xFFFFFFFF);
+    }
+}
+
+// Sum rows [lo, hi) of `in` (column 7 is a maximum) into out[b], fixed order.
+__global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__restrict__ in,
+                                                               int64_t n_rows, int64_t per_block,
+                                                               double *__restrict__ out) {
+    __shared__ double s[kBlock];
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = min(lo + per_block, n_rows);
+    for (int col = 0; col < SR_LEDGER_COLS; ++col) {
+        const bool is_max = col == SR_LED_CHI_MAX;
+        double acc = 0.0;
+        for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+            const double v = in[r * SR_LEDGER_COLS + col];
+            acc = is_max ? fmax(acc, v) : acc + v;
+        }
+        s[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w)
+                s[threadIdx.x] = is_max ? fmax(s[threadIdx.x], s[threadIdx.x + w])
+                                        : s[threadIdx.x] + s[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[(int64_t)blockIdx.x * SR_LEDGER_COLS + col] = s[0];
+        __syncthreads();
+    }
+}
+
+__global__ void zero_row_kernel(double *row) {
+    if (threadIdx.x < SR_LEDGER_COLS) row[threadIdx.x] = 0.0;
+}
+
+constexpr int64_t kReduceL1Blocks = 1024;
+
+int reduce_ledger(sr_ledger *led, int64_t n_chunks, int64_t row, hipStream_t st) {
+    double *dst = led->rows + row * SR_LEDGER_COLS;
+    if (n_chunks <= 4 * kBlock) {
+        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(led->partials, n_chunks, n_chunks, dst);
+    } else {
+        const int64_t per = (n_chunks + kReduceL1Blocks - 1) / kReduceL1Blocks;
+        const int64_t nb = (n_chunks + per - 1) / per;
+        double *mid = led->partials + n_chunks * SR_LEDGER_COLS;
+        ledger_reduce_kernel<<<(unsigned)nb, kBlock, 0, st>>>(led->partials, n_chunks, per, mid);
+        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(mid, nb, nb, dst);
+    }
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+void split_inv(double dx, float &hi, float &lo) {
+    const double inv = 1.0 / dx;
+    hi = (float)inv;
+    lo = (float)(inv - (double)hi);
+}
+
+template <typename R, typename PARTS>
+int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
+                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, int64_t row,
+                void *stream) {
+    if (!parts || !grid || !prm || !tab || !chunks || !ph || !led) return SR_E_INVAL;
+    const int64_t n = parts->n;
+    if (n < 0 || !(dt > 0.0)) return SR_E_INVAL;
+    if (!parts->p[0] || !parts->p[1] || !parts->p[2] || !parts->w || !parts->id)
+        return n == 0 ? SR_OK : SR_E_INVAL;
+    const int dim = grid->dim;
+    if (dim != 0 && dim != 2 && dim != 3) return SR_E_INVAL;
+    const int K = prm->n_samples;
+    if (K < 1 || K > kMaxK) return SR_E_INVAL;
+    if (prm->sampler != SR_SAMPLER_S && prm->sampler != SR_SAMPLER_TABLE)
+        return prm->sampler == SR_SAMPLER_MLP ? SR_E_UNSUPPORTED : SR_E_INVAL;
+    if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
+        return SR_E_INVAL;
+    if (!(prm->hbar_n > 0.0) || !(prm->alpha > 0.0)) return SR_E_INVAL;
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kBlock - 1) / kBlock;
+    if (chunks->start == nullptr && chunks->n_chunks != n_chunks) return SR_E_INVAL;
+    if (n_chunks < 0 || n_chunks > 0x7FFFFFFF) return SR_E_INVAL;
+    if (ph->per_particle < 0 || !ph->seg_count) return SR_E_INVAL;
+    if (ph->per_particle > 0 &&
+        (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2] || !ph->parent))
+        return SR_E_INVAL;
+    if (!led->rows || !led->partials || !led->status || row < 0 || row >= led->n_rows)
+        return SR_E_INVAL;
+    if (led->partials_len < sr_ledger_partials(n_chunks)) return SR_E_INVAL;
+    const bool has_pos = parts->x[0] != nullptr;
+    if (dim != 0) {
+        if (!fields) return SR_E_INVAL;
+        for (int q = 0; q < 3; ++q)
+            if (!fields->e[q] || !fields->b[q]) return SR_E_INVAL;
+        if (!parts->x[0] || !parts->x[1] || (dim == 3 && !parts->x[2])) return SR_E_INVAL;
+        for (int q = 0; q < dim; ++q)
+            if (grid->n[q] < 1 || grid->n[q] > (1 << 24) || !(grid->dx[q] > 0.0)) return SR_E_INVAL;
+        if (dim == 2 && grid->n[2] != 1) return SR_E_INVAL;
+        const int64_t cells = grid->n[0] * grid->n[1] * (dim == 3 ? grid->n[2] : 1);
+        if (cells <= 0 || cells > ((int64_t)1 << 34)) return SR_E_INVAL;
+    }
+    if (n_chunks == 0) {
+        zero_row_kernel<<<1, 64, 0, (hipStream_t)stream>>>(led->rows + row * SR_LEDGER_COLS);
+        SR_HIP_CHECK(hipGetLastError());
+        return SR_OK;
+    }
+
+    StepArgs<R> a;
+    a.n = n;
+    for (int q = 0; q < 3; ++q) { a.x[q] = parts->x[q]; a.p[q] = parts->p[q]; }
+    a.w = parts->w;
+    a.id = parts->id;
+    for (int q = 0; q < 3; ++q) {
+        a.f[q] = fields ? fields->e[q] : nullptr;
+        a.f[3 + q] = fields ? fields->b[q] : nullptr;
+    }
+    GridK &g = a.g;
+    g.dim = dim;
+    for (int q = 0; q < 3; ++q) {
+        g.n[q] = (int)(dim == 0 ? 1 : grid->n[q]);
+        const double dxq = dim == 0 ? 1.0 : grid->dx[q];
+        split_inv(dxq, g.inv_hi[q], g.inv_lo[q]);
+        g.inv_d[q] = 1.0 / dxq;
+        g.Ld[q] = (double)g.n[q] * dxq;
+        g.L[q] = (float)g.Ld[q];
+        g.e0[q] = (float)grid->e0[q];
+        g.b0[q] = (float)grid->b0[q];
+        g.e0d[q] = grid->e0[q];
+        g.b0d[q] = grid->b0[q];
+    }
+    if (dim == 2) { g.n[2] = 1; }
+    a.dt = (R)dt;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.step = (uint32_t)step;
+    a.K = K;
+    a.recoil = prm->recoil;
+    a.dn_policy = prm->dn_policy;
+    a.kin_cut = prm->kin_cut;
+    a.push_position = prm->push_position;
+    a.has_pos = has_pos ? 1 : 0;
+    a.hbar_n = (R)prm->hbar_n;
+    a.rate_c = (float)(dt * 1.7320508075688772 / (2.0 * 3.14159265358979323846) * prm->alpha);
+    a.direct_c = (float)(dt * 5.0 / (2.0 * 1.7320508075688772) * prm->alpha);
+    a.ll_c = (R)((2.0 / 3.0) * (prm->alpha / prm->hbar_n) * dt);
+    a.tab.ftab = tab->ftab;
+    a.tab.pa = tab->pa;
+    a.tab.t1 = tab->t1;
+    a.tab.r = tab->r;
+    a.start = chunks->start;
+    a.per_particle = ph->per_particle;
+    a.seg_count = ph->seg_count;
+    a.ph_eps = ph->eps;
+    a.ph_w = ph->w;
+    for (int q = 0; q < 3; ++q) { a.ph_dir[q] = ph->dir[q]; a.ph_pos[q] = ph->pos[q]; }
+    a.ph_parent = ph->parent;
+    a.ph_k = ph->k;
+    a.ph_step = ph->step;
+    a.partials = led->partials;
+    a.status = led->status;
+
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grd((unsigned)n_chunks), blk(kBlock);
+    const int KM = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : 16;
+
+#define SR_LAUNCH(DIMV, KMV, SMP) \
+    push_emit_kernel<R, DIMV, KMV, SMP><<<grd, blk, 0, st>>>(a)
+#define SR_BY_K(DIMV, SMP)                             \
+    switch (KM) {                                      \
+        case 1: SR_LAUNCH(DIMV, 1, SMP); break;        \
+        case 2: SR_LAUNCH(DIMV, 2, SMP); break;        \
+        case 4: SR_LAUNCH(DIMV, 4, SMP); break;        \
+        case 8: SR_LAUNCH(DIMV, 8, SMP); break;        \
+        default: SR_LAUNCH(DIMV, 16, SMP); break;      \
+    }
+#define SR_BY_DIM(SMP)                                 \
+    switch (dim) {                                     \
+        case 0: SR_BY_K(0, SMP); break;                \
+        case 2: SR_BY_K(2, SMP); break;                \
+        default: SR_BY_K(3, SMP); break;               \
+    }
+    if (prm->sampler == SR_SAMPLER_S) { SR_BY_DIM(SR_SAMPLER_S); }
+    else { SR_BY_DIM(SR_SAMPLER_TABLE); }
+#undef SR_BY_DIM
+#undef SR_BY_K
+#undef SR_LAUNCH
+    SR_HIP_CHECK(hipGetLastError());
+    return reduce_ledger(led, n_chunks, row, st);
+}
+
+}  // namespace
+}  // namespace sr
+
+using namespace sr;
+
+extern "C" int64_t sr_ledger_partials(int64_t n_chunks) {
+    if (n_chunks < 0) return 0;
+    return (n_chunks + kReduceL1Blocks + 1) * SR_LEDGER_COLS;
+}
+
+extern "C" int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                                   const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
+                                   const sr_params *prm, const sr_table *tab,
+                                   const sr_chunking *chunks, sr_photon_buf *photons,
+                                   sr_ledger *ledger, int64_t row, void *stream) {
+    return launch_step<float>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
+                              ledger, row, stream);
+}
+
+extern "C" int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields,
+                                       const sr_grid *grid, double dt, uint64_t seed,
+                                       uint64_t step, const sr_params *prm, const sr_table *tab,
+                                       const sr_chunking *chunks, sr_photon_buf *photons,
+                                       sr_ledger *ledger, int64_t row, void *stream) {
+    return launch_step<double>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
+                               ledger, row, stream);
+}
+
+extern "C" int sr_energy_ledger(const sr_ledger *led, int64_t row, double *out, void *stream) {
+    if (!led || !out || !led->rows || row < 0 || row >= led->n_rows) return SR_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    SR_HIP_CHECK(hipMemcpyAsync(out, led->rows + row * SR_LEDGER_COLS,
+                                sizeof(double) * SR_LEDGER_COLS, hipMemcpyDeviceToHost, st));
+    SR_HIP_CHECK(hipStreamSynchronize(st));
+    return SR_OK;
+}
+
+extern "C" int sr_status(const sr_ledger *led, uint32_t *flags, int32_t clear, void *stream) {
+    if (!led || !flags || !led->status) return SR_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    SR_HIP_CHECK(hipMemcpyAsync(flags, led->status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    if (clear) SR_HIP_CHECK(hipMemsetAsync(led->status, 0, sizeof(uint32_t), st));
+    SR_HIP_CHECK(hipStreamSynchronize(st));
+    return SR_OK;
+}

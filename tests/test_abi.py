@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/sr.h declares, and rejects bad arguments on the host (no launch)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(sr_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1409_5574_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1409_5574_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("sr_gather_push_emit", "sr_gather_push_emit_f64", "sr_energy_ledger",
+                 "sr_table_build", "sr_table_free", "sr_status", "sr_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1409_5574_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    # and the Python binding knows every one of them
+    assert set(_declared()) <= set(_lib.SIGNATURES)
+
+
+def test_strerror_and_sizes(lib):
+    from paper_1409_5574_amd import _lib as L
+    assert lib.sr_strerror(0) == b"ok"
+    assert lib.sr_strerror(L.SR_E_INVAL) == b"invalid argument"
+    assert lib.sr_strerror(12345) == b"unknown error code"
+    assert lib.sr_ledger_partials(100) >= 100 * L.SR_LEDGER_COLS
+    assert lib.sr_ledger_partials(-1) == 0
+    assert lib.sr_hist_work(64) > 0 and lib.sr_hist_work(0) == -1 and lib.sr_hist_work(5000) == -1
+    g = L.Grid()
+    g.dim = 3
+    for a in range(3):
+        g.n[a] = 64
+        g.dx[a] = 0.1
+    tile = (C.c_int32 * 3)(8, 8, 8)
+    assert lib.sr_sort_work(C.byref(g), tile, 1000) > 4 * 1000
+    bad = (C.c_int32 * 3)(0, 8, 8)
+    assert lib.sr_sort_work(C.byref(g), bad, 1000) == -1
+
+
+def test_step_rejects_bad_arguments_on_host(lib):
+    from paper_1409_5574_amd import _lib as L
+    p = L.Particles32()
+    p.n = 10
+    grid = L.Grid()
+    grid.dim = 0
+    prm = L.Params(1e-5, 7.3e-3, 1, 0, 1, 0, 0, 0)
+    ch = L.Chunking(1, None)
+    ph = L.PhotonBuf()
+    led = L.Ledger()
+    args = dict(dt=0.1, seed=1, step=0)
+    # null particle arrays with n > 0
+    rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), args["dt"], 1, 0, C.byref(prm),
+                                 None, C.byref(ch), C.byref(ph), C.byref(led), 0, None)
+    assert rc == L.SR_E_INVAL
+    # bad K, bad dt, bad grid dim: all caught before any launch
+    dummy = C.c_void_p(16)
+    for a in range(3):
+        p.p[a] = dummy
+    p.w = dummy
+    p.id = dummy
+    for bad_prm, dt, dim in ((L.Params(1e-5, 7.3e-3, 0, 0, 1, 0, 0, 0), 0.1, 0),
+                             (prm, -1.0, 0), (prm, 0.1, 1),
+                             (L.Params(1e-5, 7.3e-3, 17, 0, 1, 0, 0, 0), 0.1, 0),
+                             (L.Params(0.0, 7.3e-3, 1, 0, 1, 0, 0, 0), 0.1, 0)):
+        grid.dim = dim
+        rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), dt, 1, 0, C.byref(bad_prm),
+                                     dummy, C.byref(ch), C.byref(ph), C.byref(led), 0, None)
+        assert rc == L.SR_E_INVAL
+    assert lib.sr_table_build(None, None) == L.SR_E_INVAL
+    assert lib.sr_energy_ledger(None, 0, None, None) == L.SR_E_INVAL

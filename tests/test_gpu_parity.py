@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances are defined in tests/parity.py."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests import parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1409_5574_amd import api
+    api.lib()
+    return api
+
+
+@pytest.fixture(scope="module")
+def table(sr):
+    _say("table build")
+    t = sr.Table()
+    torch.cuda.synchronize()
+    return t
+
+
+# ------------------------------------------------------------------ primitives
+def test_philox_bit_exact(sr, oracle):
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    seed = 0x0123456789ABCDEF
+    _say("philox 4096")
+    got = sr.philox(torch.from_numpy(ctr.view(np.int32)), seed).cpu().numpy().view(np.uint32)
+    ref = oracle.philox4x32_10(ctr, [seed & 0xFFFFFFFF, seed >> 32])
+    assert np.array_equal(got, ref)
+
+
+def test_table_constants(sr, table, oracle):
+    info = table.info()
+    assert info.proposal_pa == np.float32(oracle.proposal_Pa_f32())
+    assert info.proposal_a == pytest.approx(oracle.proposal_a(), rel=1e-15)
+
+
+def test_table_F_against_oracle(sr, table, oracle):
+    x = np.geomspace(2.0 ** -18.4, 22.0, 20001)
+    _say("eval F 20001")
+    got = sr.eval_F(table, torch.from_numpy(x.astype(np.float32))).cpu().numpy().astype(np.float64)
+    ref = oracle.synchrotron_F(x.astype(np.float32).astype(np.float64))
+    rel = np.abs(got / ref - 1.0)
+    assert rel.max() < 3e-6, rel.max()
+
+
+def test_trial_dn_against_oracle(sr, table, oracle):
+    rng = np.random.default_rng(9)
+    n = 20000
+    a = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    rate = np.float32(0.013)
+    chi = np.full(n, 0.4, np.float32)
+    _say("eval trial 20000")
+    dn, xg = sr.eval_trial(table, torch.from_numpy(a.view(np.int32)),
+                           torch.full((n,), float(rate)), torch.from_numpy(chi), False)
+    dn, xg = dn.cpu().numpy(), xg.cpu().numpy()
+    Pa = oracle.proposal_Pa_f32()
+    rp = ((a >> 9).astype(np.float64) + 0.5) / 2 ** 23
+    ref = np.array([oracle.trial_dn(r, float(rate), math.inf, Pa) for r in rp])
+    assert np.max(np.abs(xg / ref[:, 1] - 1)) < 3e-7
+    assert np.max(np.abs(dn / ref[:, 0] - 1)) < 3e-6
+
+
+# ------------------------------------------------------------------ one-step parity
+def _orc_state(d):
+    return {k: (v.astype(np.float64) if v.dtype != np.uint32 else v.copy()) for k, v in d.items()}
+
+
+def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=None, dtype=np.float32,
+                  p_scale=1.0, seed=777, step=3, t=0.4, sampler=0, chunks=None, dn_policy=0,
+                  label=""):
+    K = cfg.n_samples if K is None else K
+    recoil = cfg.recoil if recoil is None else recoil
+    kin_cut = cfg.kin_cut if kin_cut is None else kin_cut
+    st = synth.gen_particles(cfg, n=n)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k].astype(np.float64) * p_scale).astype(np.float32)
+    old = _orc_state(st)
+    dim = cfg.dim
+    if dim == 0:
+        fo = oracle.Field(0, b0=cfg.b0)
+        E = B = None
+        grid = sr.grid_struct(0, b0=cfg.b0)
+        fields = None
+    else:
+        E, B = synth.standing_wave_grid(cfg, t)
+        fo = oracle.Field(dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
+        grid = sr.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
+        fields = sr.Fields(E, B)
+    # oracle
+    orc = _orc_state(st)
+    if dim == 0:
+        orc["x"] = orc["y"] = orc["z"] = None
+    if dim == 2:
+        orc["z"] = None
+    ph_o, led_o, det = oracle.step(orc, fo, cfg.dt, seed, step, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
+                                   n_samples=K, recoil=recoil, kin_cut=kin_cut,
+                                   sampler=1 if sampler else 0, dn_policy=dn_policy,
+                                   push_position=dim != 0, detail=True)
+    # GPU
+    tdtype = torch.float64 if dtype == np.float64 else torch.float32
+    gst = {k: (v if k == "id" else v.astype(dtype)) for k, v in st.items()}
+    parts = sr.Particles.from_numpy(gst, dtype=tdtype, dim=dim if dim else 0)
+    if dim == 0:
+        parts.x = [None, None, None]
+    start = None
+    n_chunks = None
+    if chunks is not None:
+        start = torch.from_numpy(np.asarray(chunks, np.int64)).to("cuda")
+        n_chunks = len(chunks) - 1
+    photons = sr.PhotonBuffer(n, K, n_chunks=n_chunks, dim=dim if dim else 3)
+    ledger = sr.LedgerBuf(4, n_chunks if n_chunks is not None else sr.n_chunks_uniform(n))
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, recoil, dn_policy, kin_cut, dim != 0)
+    _say(f"step {label} n={n} K={K} dim={dim} dtype={np.dtype(dtype).name}")
+    sr.gather_push_emit(parts, fields, grid, cfg.dt, seed, step, prm, table, photons, ledger, 1,
+                        start=start)
+    torch.cuda.synchronize()
+    gs = parts.to_numpy()
+    ph_g = photons.gather(n, start)
+    led_g = ledger.row(1)
+    status = ledger.read_status()
+    xcut_band = None
+    if kin_cut:
+        chi = np.repeat(det["chi"], K)
+        xcut_band = np.abs(1.5 * chi * det["xs"] - 1.0) <= 1e-5
+    box = cfg.box if dim else None
+    rep = parity.compare_step(gs, orc, old, ph_g, ph_o, det, K, box=box, xcut_band=xcut_band)
+    # ledger: remove the energy of flipped trials from the comparison budget
+    flips_e = 0.0
+    if rep["decision_flips"]:
+        flips_e = float(np.abs(ph_o["w"] * ph_o["eps"]).max()) * rep["decision_flips"]
+    parity.compare_ledger(led_g, led_o, flips_e,
+                          cols=(0, 1) + ((2,) if recoil != 0 and abs(led_o[2]) > 0 else ()))
+    assert led_g[5] == ph_g["count"]
+    assert ph_g["count"] == ph_g["stored"]
+    assert status & ~2 == 0, status
+    rep["ledger_gpu"] = led_g
+    rep["ledger_orc"] = led_o
+    return rep
+
+
+def test_step_uniform_field(sr, table, oracle):
+    cfg = synth.config("c1", b0=(0.0, 0.0, 40.0))
+    rep = run_step_case(sr, table, oracle, cfg, 5000, label="uniform B=40")
+    assert rep["photons_oracle"] > 50
+
+
+def test_step_uniform_field_K8_ll(sr, table, oracle):
+    cfg = synth.config("c1", b0=(0.0, 0.0, 40.0))
+    rep = run_step_case(sr, table, oracle, cfg, 3001, K=8, recoil=2, label="uniform K8 LL")
+    assert rep["photons_oracle"] > 100
+
+
+def test_step_2d_grid(sr, table, oracle):
+    cfg = synth.config("c2", grid=(96, 80, 1))
+    rep = run_step_case(sr, table, oracle, cfg, 7777, p_scale=2000.0, label="2d 96x80")
+    assert rep["photons_oracle"] > 500
+
+
+def test_step_3d_grid_K8_cut(sr, table, oracle):
+    cfg = synth.config("c3", grid=(24, 20, 16), slab=None)
+    rep = run_step_case(sr, table, oracle, cfg, 4099, p_scale=3000.0, label="3d 24x20x16 K8")
+    assert rep["photons_oracle"] > 1000
+
+
+def test_step_3d_fp64_path(sr, table, oracle):
+    # FP64 gather + push: without recoil the momenta agree with the oracle to
+    # FP64 rounding; with recoil the FP32 photon energies set the error.
+    cfg = synth.config("c5", grid=(16, 16, 12), n_particles=3000)
+    rep = run_step_case(sr, table, oracle, cfg, 3000, dtype=np.float64, recoil=0,
+                        label="3d fp64 no recoil")
+    assert rep["p_rel_err"] < 1e-12
+    rep = run_step_case(sr, table, oracle, cfg, 3000, dtype=np.float64, label="3d fp64 recoil")
+    assert rep["p_rel_err"] < 1e-6
+
+
+def test_step_dn_above_one_weighting(sr, table, oracle):
+    cfg = synth.config("c1", b0=(0.0, 0.0, 3e4), gamma_range=(200.0, 2000.0))
+    rep = run_step_case(sr, table, oracle, cfg, 2000, K=2, label="dN>=1")
+    assert rep["photons_oracle"] > 1000
+
+
+def test_step_explicit_chunks(sr, table, oracle):
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    chunks = [0, 1, 300, 300, 1000, 1257, 2000]
+    run_step_case(sr, table, oracle, cfg, 2000, p_scale=2000.0, chunks=chunks, label="chunks")
+
+
+def test_step_table_sampler(sr, table, oracle):
+    cfg = synth.config("c1", b0=(0.0, 0.0, 40.0), gamma_range=(1e3, 1e4))
+    rep = run_step_case(sr, table, oracle, cfg, 4000, K=2, sampler=1, kin_cut=True,
+                        label="table sampler")
+    assert rep["photons_oracle"] > 40
