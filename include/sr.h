@@ -69,8 +69,8 @@ enum {
     SR_LEDGER_COLS = 8
 };
 
-/* Particles per chunk when the caller gives no explicit chunking. */
-#define SR_CHUNK 256
+/* Particles per chunk when the caller gives no explicit chunking (one wave). */
+#define SR_CHUNK 64
 
 /* --------------------------------------------------------------- data types */
 /* Macro-electrons, structure of arrays, FP32.  x[a] are positions measured from
@@ -166,8 +166,9 @@ typedef struct {
 } sr_photon_buf;
 
 /* FP64 energy ledger.  rows: device [n_rows][SR_LEDGER_COLS]; partials: device
- * workspace of at least sr_ledger_partials(n_chunks) doubles; status: device
- * uint32 whose bits are OR-ed in by the kernels (the caller zeroes it). */
+ * workspace of at least sr_ledger_partials(n_chunks) doubles (the step writes
+ * one partial row per group of four chunks); status: device uint32 whose bits
+ * are OR-ed in by the kernels (the caller zeroes it). */
 typedef struct {
     double *rows;
     int64_t n_rows;
@@ -228,22 +229,29 @@ int sr_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out, int64_t n, void
  *   K Monte-Carlo trials (the six steps listed at the end of section "Monte
  *   Carlo method"), random words from Philox4x32-10 with counter
  *   (id, step, k/2, 0) and key seed;
- *   photon append into the chunk's segment, recoil, position push;
- *   per-chunk FP64 ledger partials into ledger->partials.
- * Then reduces the partials into ledger->rows[row] (see sr_ledger_reduce).
- * photons may have per_particle == 0 only if nothing is to be stored (every
- * photon is then counted as dropped). */
+ *   photon append into the chunk's segment, recoil, position push.
+ * Writes FP64 ledger partial rows into ledger->partials (sum them into a
+ * ledger row with sr_ledger_reduce, passing the same n_chunks) and ORs condition bits into
+ * ledger->status.  With per_particle == 0 nothing is stored and every photon
+ * is counted as dropped.  Explicit chunk starts are trusted: the caller
+ * guarantees 0 = start[0] <= ... <= start[n_chunks] = n. */
 int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields, const sr_grid *grid,
                         double dt, uint64_t seed, uint64_t step, const sr_params *prm,
                         const sr_table *tab, const sr_chunking *chunks, sr_photon_buf *photons,
-                        sr_ledger *ledger, int64_t row, void *stream);
+                        sr_ledger *ledger, void *stream);
 
 /* The same step with FP64 state, FP64 gather (of the FP32 grid values), FP64
  * Boris push and H_eff; the trials run in FP32 as in the FP32 path. */
 int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields,
                             const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
                             const sr_params *prm, const sr_table *tab, const sr_chunking *chunks,
-                            sr_photon_buf *photons, sr_ledger *ledger, int64_t row, void *stream);
+                            sr_photon_buf *photons, sr_ledger *ledger, void *stream);
+
+/* Sum the partial rows a step over n_chunks chunks wrote into ledger->rows[row]
+ * (FP64, fixed order, so the result is reproducible; column SR_LED_CHI_MAX is
+ * a maximum).  The energy ledger of the section "Comparison and benchmarking":
+ * emitted photon energy against the Landau-Lifshitz loss. */
+int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row, void *stream);
 
 /* Workspace length (doubles) for ledger->partials with n_chunks chunks. */
 int64_t sr_ledger_partials(int64_t n_chunks);

@@ -17,7 +17,7 @@ SR_W_PHOTON_OVERFLOW, SR_W_RECOIL_CLAMP, SR_W_NONFINITE = 1, 2, 4
 (SR_LED_EMITTED, SR_LED_LL, SR_LED_RECOIL, SR_LED_CLAMPED, SR_LED_DROPPED, SR_LED_PHOTONS,
  SR_LED_WEIGHT, SR_LED_CHI_MAX) = range(8)
 SR_LEDGER_COLS = 8
-SR_CHUNK = 256
+SR_CHUNK = 64
 SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP = 0, 1, 2
 SR_RECOIL_NONE, SR_RECOIL_PHOTON, SR_RECOIL_LL = 0, 1, 2
 SR_DN_WEIGHT, SR_DN_CLAMP = 0, 1
@@ -81,11 +81,12 @@ SIGNATURES = {
     "sr_gather_push_emit": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32),
                                       C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,
                                       C.POINTER(Chunking), C.POINTER(PhotonBuf),
-                                      C.POINTER(Ledger), _I64, _P]),
+                                      C.POINTER(Ledger), _P]),
     "sr_gather_push_emit_f64": (C.c_int, [C.POINTER(Particles64), C.POINTER(Fields32),
                                           C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,
                                           C.POINTER(Chunking), C.POINTER(PhotonBuf),
-                                          C.POINTER(Ledger), _I64, _P]),
+                                          C.POINTER(Ledger), _P]),
+    "sr_ledger_reduce": (C.c_int, [C.POINTER(Ledger), _I64, _I64, _P]),
     "sr_ledger_partials": (C.c_int64, [_I64]),
     "sr_energy_ledger": (C.c_int, [C.POINTER(Ledger), _I64, _P, _P]),
     "sr_status": (C.c_int, [C.POINTER(Ledger), C.POINTER(C.c_uint32), _I32, _P]),

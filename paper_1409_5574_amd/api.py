@@ -274,18 +274,27 @@ def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.S
 
 def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, seed: int,
                      step: int, prm: L.Params, table: Table, photons: PhotonBuffer,
-                     ledger: LedgerBuf, row: int, start: torch.Tensor | None = None,
+                     ledger: LedgerBuf, row: int | None, start: torch.Tensor | None = None,
                      structs: tuple | None = None):
-    """One emission step.  `structs` may hold pre-built (parts, fields, chunking,
-    photons, ledger) C structs to avoid rebuilding them every call."""
+    """One emission step; with row set, also reduce the ledger into that row.
+    `structs` may hold pre-built (parts, fields, chunking, photons, ledger) C
+    structs to avoid rebuilding them every call."""
     if structs is None:
         structs = make_structs(parts, fields, photons, ledger, start)
     ps, fs, cs, phs, ls = structs
     fn = lib().sr_gather_push_emit_f64 if parts.dtype == torch.float64 else lib().sr_gather_push_emit
     rc = fn(C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid), float(dt),
             seed & 0xFFFFFFFFFFFFFFFF, int(step), C.byref(prm), table.handle, C.byref(cs),
-            C.byref(phs), C.byref(ls), int(row), _stream())
+            C.byref(phs), C.byref(ls), _stream())
     L.check(rc, "sr_gather_push_emit")
+    if row is not None:
+        ledger_reduce(ledger, cs.n_chunks, row, ls)
+
+
+def ledger_reduce(ledger: "LedgerBuf", n_chunks: int, row: int, ls=None):
+    ls = ledger.struct() if ls is None else ls
+    L.check(lib().sr_ledger_reduce(C.byref(ls), int(n_chunks), int(row), _stream()),
+            "sr_ledger_reduce")
 
 
 def make_structs(parts, fields, photons, ledger, start=None):

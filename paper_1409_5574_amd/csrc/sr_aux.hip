@@ -82,13 +82,39 @@ __global__ void fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Runs of equal keys inside a wave (the input is nearly sorted after the first
+// sort): the first lane of each run updates the counter once for the run.
+struct WaveRun {
+    bool head;
+    int head_lane;   // first lane of this lane's run
+    int len;         // run length (valid on the head lane)
+};
+
+__device__ __forceinline__ WaveRun wave_run(uint32_t k, bool valid) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t kp = (uint32_t)__shfl_up((int)k, 1, 64);
+    WaveRun r;
+    r.head = valid && (lane == 0 || kp != k);
+    const uint64_t hm = __ballot(r.head);
+    const int nvalid = (int)__popcll(__ballot(valid));   // valid lanes form a prefix
+    const uint64_t at_or_below = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t below = hm & at_or_below;
+    r.head_lane = below ? 63 - __clzll(below) : 0;
+    const uint64_t above = hm & ~at_or_below;
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    r.len = min(next, nvalid) - lane;
+    return r;
+}
+
 __global__ void sort_count(const float *x, const float *y, const float *z, int64_t n, SortGeom g,
                            uint32_t *keys, uint32_t *counts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t k = tile_key(g, x[i], y[i], g.dim == 3 ? z[i] : 0.0f);
+    const bool valid = i < n;
+    const uint32_t k = valid ? tile_key(g, x[i], y[i], g.dim == 3 ? z[i] : 0.0f) : 0xFFFFFFFFu;
+    const WaveRun r = wave_run(k, valid);
+    if (!valid) return;
     keys[i] = k;
-    atomicAdd(&counts[k], 1u);
+    if (r.head) atomicAdd(&counts[k], (uint32_t)r.len);
 }
 
 // exclusive scan in blocks of 1024 (256 threads x 4)
@@ -125,37 +151,46 @@ __global__ void scan_add(uint32_t *out, int64_t n, const uint32_t *block_prefix)
 }
 
 __global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const uint32_t *keys,
-                             const uint32_t *offsets, uint32_t *cursor, int dim) {
+                             const uint32_t *offsets, uint32_t *cursor) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= src.n) return;
-    const uint32_t k = keys[i];
-    const int64_t j = (int64_t)offsets[k] + atomicAdd(&cursor[k], 1u);
+    const bool valid = i < src.n;
+    const uint32_t k = valid ? keys[i] : 0xFFFFFFFFu;
+    const WaveRun r = wave_run(k, valid);
+    uint32_t base = 0;
+    if (r.head) base = atomicAdd(&cursor[k], (uint32_t)r.len);
+    base = (uint32_t)__shfl((int)base, r.head_lane, 64);
+    if (!valid) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)offsets[k] + base + (lane - r.head_lane);
     for (int a = 0; a < 3; ++a) {
         if (src.x[a] && dst.x[a]) dst.x[a][j] = src.x[a][i];
         dst.p[a][j] = src.p[a][i];
     }
     dst.w[j] = src.w[i];
     dst.id[j] = src.id[i];
-    (void)dim;
 }
 
 // ------------------------------------------------------------ histogram
 constexpr int kHistBlocks = 512;
 constexpr int kMaxBins = 1024;
 
+// One lane per chunk: each lane walks the stored photons of its chunk and adds
+// them to the block's LDS histogram (FP64 LDS atomics); blocks stride over
+// groups of 256 chunks and flush their histogram to work[block].
 __global__ __launch_bounds__(256) void hist_kernel(sr_photon_buf ph, const int64_t *start,
                                                    int64_t n_chunks, int64_t n, float l2lo,
                                                    float scale, int nbins, double *work) {
     extern __shared__ double sh[];   // [2*nbins]
     for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) sh[b] = 0.0;
     __syncthreads();
-    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-        const int64_t s0 = start ? start[c] : c * (int64_t)kBlock;
-        const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kBlock, n);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s0 = start ? start[c] : c * (int64_t)kChunk;
+        const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kChunk, n);
         const int64_t cap = (e0 - s0) * ph.per_particle;
         const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
         const int64_t base = s0 * ph.per_particle;
-        for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+        for (int64_t q = 0; q < cnt; ++q) {
             const float eps = ph.eps[base + q];
             const float w = ph.w[base + q];
             if (!(eps > 0.0f)) continue;
@@ -171,12 +206,20 @@ __global__ __launch_bounds__(256) void hist_kernel(sr_photon_buf ph, const int64
         work[(int64_t)blockIdx.x * 2 * nbins + b] = sh[b];
 }
 
-__global__ void hist_reduce(const double *work, int nblocks, int nvals, double *hist) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nvals) return;
-    double s = 0.0;
-    for (int k = 0; k < nblocks; ++k) s += work[(int64_t)k * nvals + b];
-    hist[b] += s;
+// hist[b] += sum over blocks of work[block][b]: one block per value, fixed order.
+__global__ __launch_bounds__(256) void hist_reduce(const double *work, int nblocks, int nvals,
+                                                   double *hist) {
+    __shared__ double s[256];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += 256) acc += work[(int64_t)k * nvals + b];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hist[b] += s[0];
 }
 
 }  // namespace
@@ -194,8 +237,8 @@ extern "C" int sr_field_standing_wave(float *e[3], float *b[3], const sr_grid *g
     if (nx < 1 || ny < 1 || nz < 1 || nx > (1 << 24) || !(grid->dx[0] > 0.0)) return SR_E_INVAL;
     const int64_t rows = ny * nz;
     const unsigned bx = (unsigned)((nx + 256 * kWaveXPerThread - 1) / (256 * kWaveXPerThread));
-    // enough blocks to fill the GPU, each writing a band of rows
-    int64_t by = (4096 + bx - 1) / bx;
+    // about 1024 blocks, each writing a band of rows with its x profile reused
+    int64_t by = (1024 + bx - 1) / bx;
     if (by > rows) by = rows;
     if (by > 65535) by = 65535;
     const int rows_per_block = (int)((rows + by - 1) / by);
@@ -277,8 +320,7 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
         }
         scan_add<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(offsets, nt, bpre);
     }
-    sort_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(*src, *dst, keys, offsets, cursor,
-                                                              g.dim);
+    sort_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(*src, *dst, keys, offsets, cursor);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }
@@ -294,16 +336,17 @@ extern "C" int sr_spectrum_histogram(const sr_photon_buf *ph, const sr_chunking 
     if (!ph || !chunks || !hist || !work || n < 0 || n_bins < 1 || n_bins > kMaxBins ||
         !(eps_lo > 0.0) || !(eps_hi > eps_lo) || !ph->seg_count)
         return SR_E_INVAL;
-    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kBlock - 1) / kBlock;
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
     if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
     if (!ph->eps || !ph->w) return SR_E_INVAL;
     const float l2lo = (float)log2(eps_lo);
     const float scale = (float)(n_bins / (log2(eps_hi) - log2(eps_lo)));
-    const int nb = (int)(n_chunks < kHistBlocks ? n_chunks : kHistBlocks);
+    const int64_t groups = (n_chunks + 255) / 256;
+    const int nb = (int)(groups < kHistBlocks ? groups : kHistBlocks);
     hipStream_t st = (hipStream_t)stream;
     hist_kernel<<<nb, 256, sizeof(double) * 2 * n_bins, st>>>(*ph, chunks->start, n_chunks, n,
                                                                l2lo, scale, n_bins, work);
-    hist_reduce<<<(2 * n_bins + 255) / 256, 256, 0, st>>>(work, nb, 2 * n_bins, hist);
+    hist_reduce<<<2 * n_bins, 256, 0, st>>>(work, nb, 2 * n_bins, hist);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }

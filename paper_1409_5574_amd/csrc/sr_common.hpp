@@ -18,7 +18,29 @@ namespace sr {
 
 constexpr int kBlock = 256;     // threads per block, one particle each
 constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = SR_CHUNK; // particles per chunk: one wave
 constexpr int kMaxK = 16;       // largest supported number of trials per step
+
+// Square root and reciprocal: the hardware instructions (1 ulp) in binary32,
+// correctly rounded operations in FP64.
+template <typename R> __device__ __forceinline__ R sqrt_r(R v);
+template <> __device__ __forceinline__ float sqrt_r<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
+template <> __device__ __forceinline__ double sqrt_r<double>(double v) { return sqrt(v); }
+template <typename R> __device__ __forceinline__ R rcp_r(R v);
+template <> __device__ __forceinline__ float rcp_r<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ __forceinline__ double rcp_r<double>(double v) { return 1.0 / v; }
+
+// Element access through a 32-bit byte offset from a base pointer, so the
+// address is formed as (scalar base + vector offset) with no 64-bit arithmetic.
+// Callers keep every array below 4 GiB.
+template <typename T>
+__device__ __forceinline__ T ld(const T *base, uint32_t i) {
+    return *(const T *)((const char *)base + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T *base, uint32_t i, T v) {
+    *(T *)((char *)base + i * (uint32_t)sizeof(T)) = v;
+}
 
 // ---------------------------------------------------------------------------
 // Synchrotron-function table (built in FP64 by the table kernels, read here).
@@ -101,7 +123,7 @@ __device__ __forceinline__ float trial_dn(uint32_t a, float rate, const float4 *
         const float t = 0.75f * __log2f(rp);
         const float L = ftab_eval(tab, t, kFLoJ0, kFLoN, 0);
         // F/(x S) = (3/4) (F / x^{1/3}) / x
-        q = 0.75f * __fdividef(exp2f(L), x);
+        q = 0.75f * exp2f(L) * __builtin_amdgcn_rcpf(x);
     } else {
         const float om = 1.0f - rp;          // exact
         x = -0.69314718055994531f * __log2f(om) - 0.25131442828090605f;  // -ln om - ln(9/7)
@@ -219,26 +241,28 @@ __device__ __forceinline__ void axis_setup(double x, double inv, int n, Axis<dou
 template <typename R, int DIM>
 __device__ __forceinline__ R cic(const float *__restrict__ a, const Axis<R> &X, const Axis<R> &Y,
                                  const Axis<R> &Z, bool sx, bool sy, bool sz, int nx, int ny) {
-    const int ix0 = sx ? X.i1 : X.i0, ix1 = sx ? X.i1p : X.i0p;
+    const uint32_t ix0 = sx ? X.i1 : X.i0, ix1 = sx ? X.i1p : X.i0p;
     const R fx = sx ? X.f1 : X.f0;
-    const int iy0 = sy ? Y.i1 : Y.i0, iy1 = sy ? Y.i1p : Y.i0p;
+    const uint32_t iy0 = sy ? Y.i1 : Y.i0, iy1 = sy ? Y.i1p : Y.i0p;
     const R fy = sy ? Y.f1 : Y.f0;
     const R gx = (R)1 - fx, gy = (R)1 - fy;
     if (DIM == 2) {
-        const int64_t r0 = (int64_t)iy0 * nx, r1 = (int64_t)iy1 * nx;
-        const R v00 = (R)a[r0 + ix0], v01 = (R)a[r0 + ix1];
-        const R v10 = (R)a[r1 + ix0], v11 = (R)a[r1 + ix1];
+        const uint32_t r0 = iy0 * (uint32_t)nx, r1 = iy1 * (uint32_t)nx;
+        const R v00 = (R)ld(a, r0 + ix0), v01 = (R)ld(a, r0 + ix1);
+        const R v10 = (R)ld(a, r1 + ix0), v11 = (R)ld(a, r1 + ix1);
         return gy * (gx * v00 + fx * v01) + fy * (gx * v10 + fx * v11);
     } else {
-        const int iz0 = sz ? Z.i1 : Z.i0, iz1 = sz ? Z.i1p : Z.i0p;
+        const uint32_t iz0 = sz ? Z.i1 : Z.i0, iz1 = sz ? Z.i1p : Z.i0p;
         const R fz = sz ? Z.f1 : Z.f0;
         const R gz = (R)1 - fz;
-        const int64_t p00 = ((int64_t)iz0 * ny + iy0) * nx, p01 = ((int64_t)iz0 * ny + iy1) * nx;
-        const int64_t p10 = ((int64_t)iz1 * ny + iy0) * nx, p11 = ((int64_t)iz1 * ny + iy1) * nx;
-        const R c00 = gx * (R)a[p00 + ix0] + fx * (R)a[p00 + ix1];
-        const R c01 = gx * (R)a[p01 + ix0] + fx * (R)a[p01 + ix1];
-        const R c10 = gx * (R)a[p10 + ix0] + fx * (R)a[p10 + ix1];
-        const R c11 = gx * (R)a[p11 + ix0] + fx * (R)a[p11 + ix1];
+        const uint32_t p00 = (iz0 * (uint32_t)ny + iy0) * (uint32_t)nx;
+        const uint32_t p01 = (iz0 * (uint32_t)ny + iy1) * (uint32_t)nx;
+        const uint32_t p10 = (iz1 * (uint32_t)ny + iy0) * (uint32_t)nx;
+        const uint32_t p11 = (iz1 * (uint32_t)ny + iy1) * (uint32_t)nx;
+        const R c00 = gx * (R)ld(a, p00 + ix0) + fx * (R)ld(a, p00 + ix1);
+        const R c01 = gx * (R)ld(a, p01 + ix0) + fx * (R)ld(a, p01 + ix1);
+        const R c10 = gx * (R)ld(a, p10 + ix0) + fx * (R)ld(a, p10 + ix1);
+        const R c11 = gx * (R)ld(a, p11 + ix0) + fx * (R)ld(a, p11 + ix1);
         return gz * (gy * c00 + fy * c01) + fz * (gy * c10 + fy * c11);
     }
 }
@@ -254,23 +278,19 @@ __device__ __forceinline__ double diff_of_products(double a, double b, double c,
     return a * b - c * d;
 }
 
-template <typename R> __device__ __forceinline__ R sqrt_r(R v);
-template <> __device__ __forceinline__ float sqrt_r<float>(float v) { return sqrtf(v); }
-template <> __device__ __forceinline__ double sqrt_r<double>(double v) { return sqrt(v); }
-
 // ---------------------------------------------------------------------------
 // Wave64 reductions.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
+}  // namespace sr
+// Whole-wave reductions of the device library (DPP row shifts and broadcasts,
+// fixed order); every lane of the wave must be active.
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+extern "C" __device__ __attribute__((const)) float __ockl_wfred_max_f32(float);
+extern "C" __device__ __attribute__((const)) float __ockl_wfred_add_f32(float);
+namespace sr {
+__device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
+__device__ __forceinline__ float wave_max(float v) { return __ockl_wfred_max_f32(v); }
+__device__ __forceinline__ float wave_sum_f(float v) { return __ockl_wfred_add_f32(v); }
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

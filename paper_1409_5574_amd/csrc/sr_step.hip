@@ -13,11 +13,24 @@
 // LDS.  The FP64 ledger is reduced per block and written as one partial row per
 // chunk, then summed in a fixed order by ledger_reduce (deterministic).
 #include <math.h>
+#include <stddef.h>
 
 #include "sr_common.hpp"
 
 namespace sr {
 namespace {
+
+// Outputs written once per wave (photon records, segment counts, ledger
+// partials, status).  The kernel reads these pointers through cold_args() at
+// the point of use so they do not occupy scalar registers for the whole kernel.
+struct PhotonOut {
+    float *eps, *w, *dir[3], *pos[3];
+    uint32_t *parent, *step;
+    uint8_t *k;
+    uint32_t *seg_count;
+    double *partials;
+    uint32_t *status;
+};
 
 template <typename R>
 struct StepArgs {
@@ -28,7 +41,7 @@ struct StepArgs {
     const uint32_t *id;
     const float *f[6];
     GridK g;
-    R dt;
+    R dt, inv_dt;
     uint32_t seed_lo, seed_hi, step;
     int K, recoil, dn_policy, kin_cut, push_position, has_pos;
     R hbar_n;
@@ -37,13 +50,9 @@ struct StepArgs {
     R ll_c;            // (2/3)(alpha/hbar_n) dt        (x chi^2 beta^2 gives the LL loss)
     TableDev tab;
     const int64_t *start;
+    int64_t n_chunks;
     int64_t per_particle;
-    uint32_t *seg_count;
-    float *ph_eps, *ph_w, *ph_dir[3], *ph_pos[3];
-    uint32_t *ph_parent, *ph_step;
-    uint8_t *ph_k;
-    double *partials;
-    uint32_t *status;
+    PhotonOut ph;
 };
 
 template <typename R>
@@ -93,29 +102,46 @@ __device__ __forceinline__ R wrap_pos(R v, R L) {
     return v;
 }
 
+// The output pointers of the kernel arguments, reached through an opaque copy
+// of the argument-segment pointer: the loads happen where they are used.
+template <typename R>
+__device__ __forceinline__ const PhotonOut &cold_args() {
+    const char *kp = (const char *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(kp));
+    return *(const PhotonOut *)(kp + offsetof(StepArgs<R>, ph));
+}
+
 template <typename R, int DIM, int KMAX, int SAMPLER>
 __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) {
-    __shared__ uint32_t s_wave[kWaves];
     __shared__ double s_red[kWaves][7];
     __shared__ float s_chi[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
-    const int64_t s0 = a.start ? a.start[c] : c * (int64_t)kBlock;
-    const int64_t e0 = a.start ? a.start[c + 1] : min(s0 + (int64_t)kBlock, a.n);
-    const int64_t seg_base = s0 * a.per_particle;
-    const int64_t seg_cap = (e0 - s0) * a.per_particle;
+    // one chunk per wave, kWaves consecutive chunks per block (blocks mapped so
+    // that neighbouring chunks share an XCD)
+    const uint32_t blk = (uint32_t)xcd_chunk(blockIdx.x, gridDim.x);
+    const uint32_t c = blk * kWaves + wave;
+    const bool have = c < (uint32_t)a.n_chunks;
+    // particle and photon counts are below 2^31 (checked on the host)
+    uint32_t s0 = 0, e0 = 0;
+    if (have) {
+        s0 = a.start ? (uint32_t)a.start[c] : c * (uint32_t)kChunk;
+        e0 = a.start ? (uint32_t)a.start[c + 1] : min(s0 + (uint32_t)kChunk, (uint32_t)a.n);
+    }
+    const uint32_t pp = (uint32_t)a.per_particle;
+    const uint32_t seg_base = s0 * pp;
+    const uint32_t seg_cap = (e0 - s0) * pp;
     const int K = a.K;
     const float invK = 1.0f / (float)K;
 
-    double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0,
-           acc_w = 0.0;
+    double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0;
+    float acc_w = 0.0f;
     float chi_max = 0.0f;
     uint32_t flags = 0;
-    int64_t run_base = 0;
+    uint32_t run_base = 0;
 
-    for (int64_t base = s0; base < e0; base += kBlock) {
-        const int64_t i = base + tid;
+    for (uint32_t base = s0; base < e0; base += kChunk) {
+        const uint32_t i = base + lane;
         const bool active = i < e0;
         uint32_t bits = 0;
         float xk[KMAX], fk[KMAX];
@@ -123,15 +149,15 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
         float dirf[3] = {0.0f, 0.0f, 0.0f}, posf[3] = {0.0f, 0.0f, 0.0f};
         uint32_t pid = 0;
         if (active) {
-            const R wi = a.w[i];
-            pid = a.id[i];
+            const R wi = ld(a.w, i);
+            pid = ld(a.id, i);
             R pos[3] = {(R)0, (R)0, (R)0};
             if (a.has_pos) {
-                pos[0] = a.x[0][i];
-                if (DIM != 0 || a.x[1]) pos[1] = a.x[1][i];
-                if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = a.x[2][i];
+                pos[0] = ld(a.x[0], i);
+                if (DIM != 0 || a.x[1]) pos[1] = ld(a.x[1], i);
+                if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = ld(a.x[2], i);
             }
-            const R p0[3] = {a.p[0][i], a.p[1][i], a.p[2][i]};
+            const R p0[3] = {ld(a.p[0], i), ld(a.p[1], i), ld(a.p[2], i)};
             R E[3], B[3];
             if (DIM == 0) {
                 for (int q = 0; q < 3; ++q) { E[q] = uniform_e<R>(a.g, q); B[q] = uniform_b<R>(a.g, q); }
@@ -142,10 +168,10 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             const R h = (R)(-0.5) * a.dt;
             const R um[3] = {p0[0] + h * E[0], p0[1] + h * E[1], p0[2] + h * E[2]};
             const R gm = sqrt_r<R>((R)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-            const R hg = h / gm;
+            const R hg = h * rcp_r<R>(gm);
             const R t[3] = {hg * B[0], hg * B[1], hg * B[2]};
             const R t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-            const R sc = (R)2 / ((R)1 + t2);
+            const R sc = (R)2 * rcp_r<R>((R)1 + t2);
             const R sv[3] = {sc * t[0], sc * t[1], sc * t[2]};
             const R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]),
                              um[1] + (um[2] * t[0] - um[0] * t[2]),
@@ -164,14 +190,15 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             const R g_old = sqrt_r<R>((R)1 + p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
             const R g_new = sqrt_r<R>((R)1 + pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
             const R gb = (R)0.5 * (g_old + g_new);
-            R ratio = p2 > (R)0 ? sqrt_r<R>(c2) / p2 : (R)0;
-            if (ratio > (R)1) ratio = (R)1;
-            const R H = gb * ratio / a.dt;
-            const R chi = a.hbar_n * H * gb;
             const R pbm = sqrt_r<R>(p2);
+            const R inv_p2 = p2 > (R)0 ? rcp_r<R>(p2) : (R)0;
+            R ratio = sqrt_r<R>(c2) * inv_p2;
+            if (ratio > (R)1) ratio = (R)1;
+            const R H = gb * ratio * a.inv_dt;
+            const R chi = a.hbar_n * H * gb;
             const float Hf = (float)H, chif = (float)chi, gbf = (float)gb;
             if (pbm > (R)0) {
-                const R inv = (R)1 / pbm;
+                const R inv = rcp_r<R>(pbm);
                 dirf[0] = (float)(pb[0] * inv); dirf[1] = (float)(pb[1] * inv);
                 dirf[2] = (float)(pb[2] * inv);
             }
@@ -191,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             }
             const float cut15 = a.kin_cut ? 1.5f * chif : 0.0f;
             uint4 words = make_uint4(0, 0, 0, 0);
-            float delta_ph = 0.0f, e_emit = 0.0f;
+            float delta_ph = 0.0f;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
                 xk[k] = 0.0f;
@@ -226,25 +253,23 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                         bits |= 1u << k;
                         xk[k] = x;
                         fk[k] = frac;
-                        const float eps = eps_unit * x;
-                        delta_ph += frac * eps;
-                        e_emit += frac * eps;
+                        delta_ph += frac * (eps_unit * x);
                     }
                 }
             }
-            acc_emit += (double)wi_f * (double)e_emit;
+            acc_emit += (double)wi_f * (double)delta_ph;
             // Landau-Lifshitz loss of the step (eq:LLformOfRRForce)
-            const R beta2 = p2 / (gb * gb);
+            const R beta2 = p2 * rcp_r<R>(gb * gb);
             acc_ll += (double)(wi * a.ll_c * chi * chi * beta2);
 
             // ---- recoil along the post-push momentum
             R delta = (R)0;
             if (a.recoil == SR_RECOIL_PHOTON) delta = (R)delta_ph;
-            else if (a.recoil == SR_RECOIL_LL) delta = a.ll_c * chi * chi * pbm / gb;
+            else if (a.recoil == SR_RECOIL_LL) delta = a.ll_c * chi * chi * pbm * rcp_r<R>(gb);
             R g_after = g_new;
             if (delta > (R)0) {
                 const R pm = sqrt_r<R>(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
-                R fac = pm > (R)0 ? (R)1 - delta / pm : (R)-1;
+                R fac = pm > (R)0 ? (R)1 - delta * rcp_r<R>(pm) : (R)-1;
                 R removed = delta;
                 if (fac < (R)0) {
                     acc_clamp += (double)(wi * (delta - pm));
@@ -256,28 +281,29 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 const R pm_after = fac * pm;
                 g_after = sqrt_r<R>((R)1 + pm_after * pm_after);
                 // gamma_after - gamma_before without cancellation
-                acc_de += (double)(-wi * removed * (pm_after + pm) / (g_after + g_new));
+                acc_de += (double)(-wi * removed * (pm_after + pm) * rcp_r<R>(g_after + g_new));
             }
             if (!(isfinite(pn[0]) && isfinite(pn[1]) && isfinite(pn[2]) && isfinite(H)))
                 flags |= SR_W_NONFINITE;
-            a.p[0][i] = pn[0]; a.p[1][i] = pn[1]; a.p[2][i] = pn[2];
+            st(a.p[0], i, pn[0]); st(a.p[1], i, pn[1]); st(a.p[2], i, pn[2]);
             // ---- position push
             if (a.push_position && a.has_pos) {
-                const R vdt = a.dt / g_after;
+                const R vdt = a.dt * rcp_r<R>(g_after);
                 if (DIM == 0) {
-                    a.x[0][i] = pos[0] + vdt * pn[0];
-                    if (a.x[1]) a.x[1][i] = pos[1] + vdt * pn[1];
-                    if (a.x[2]) a.x[2][i] = pos[2] + vdt * pn[2];
+                    st(a.x[0], i, pos[0] + vdt * pn[0]);
+                    if (a.x[1]) st(a.x[1], i, pos[1] + vdt * pn[1]);
+                    if (a.x[2]) st(a.x[2], i, pos[2] + vdt * pn[2]);
                 } else {
-                    a.x[0][i] = wrap_pos<R>(pos[0] + vdt * pn[0], box_len<R>(a.g, 0));
-                    a.x[1][i] = wrap_pos<R>(pos[1] + vdt * pn[1], box_len<R>(a.g, 1));
-                    if (DIM == 3) a.x[2][i] = wrap_pos<R>(pos[2] + vdt * pn[2], box_len<R>(a.g, 2));
+                    st(a.x[0], i, wrap_pos<R>(pos[0] + vdt * pn[0], box_len<R>(a.g, 0)));
+                    st(a.x[1], i, wrap_pos<R>(pos[1] + vdt * pn[1], box_len<R>(a.g, 1)));
+                    if (DIM == 3) st(a.x[2], i, wrap_pos<R>(pos[2] + vdt * pn[2], box_len<R>(a.g, 2)));
                 }
             }
-            acc_w += (double)wi;
+            acc_w += wi_f;
         }
 
-        // ---- photon slots: per trial a ballot, the lane prefix, then wave totals in LDS
+        // ---- photon slots: per trial a ballot and the lane prefix (wave-local:
+        // the chunk's segment belongs to this wave alone)
         uint32_t off[KMAX];
         uint32_t wave_tot = 0;
 #pragma unroll
@@ -289,36 +315,27 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 wave_tot += (uint32_t)__popcll(m);
             }
         }
-        if (lane == 0) s_wave[wave] = wave_tot;
-        __syncthreads();
-        uint32_t wave_base = 0, blk_tot = 0;
-#pragma unroll
-        for (int q = 0; q < kWaves; ++q) {
-            const uint32_t v = s_wave[q];
-            wave_base += q < wave ? v : 0u;
-            blk_tot += v;
-        }
-        __syncthreads();
         if (bits) {
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
                 if (k < K && ((bits >> k) & 1u)) {
-                    const int64_t slot = run_base + wave_base + off[k];
+                    const uint32_t slot = run_base + off[k];
                     const float eps = eps_unit * xk[k];
                     const float wph = wi_f * fk[k];
                     if (slot < seg_cap) {
-                        const int64_t o = seg_base + slot;
-                        a.ph_eps[o] = eps;
-                        a.ph_w[o] = wph;
-                        a.ph_dir[0][o] = dirf[0];
-                        a.ph_dir[1][o] = dirf[1];
-                        a.ph_dir[2][o] = dirf[2];
-                        if (a.ph_pos[0]) a.ph_pos[0][o] = posf[0];
-                        if (a.ph_pos[1]) a.ph_pos[1][o] = posf[1];
-                        if (a.ph_pos[2]) a.ph_pos[2][o] = posf[2];
-                        a.ph_parent[o] = pid;
-                        if (a.ph_k) a.ph_k[o] = (uint8_t)k;
-                        if (a.ph_step) a.ph_step[o] = a.step;
+                        const uint32_t o = seg_base + slot;
+                        const PhotonOut &P = cold_args<R>();
+                        st(P.eps, o, eps);
+                        st(P.w, o, wph);
+                        st(P.dir[0], o, dirf[0]);
+                        st(P.dir[1], o, dirf[1]);
+                        st(P.dir[2], o, dirf[2]);
+                        if (P.pos[0]) st(P.pos[0], o, posf[0]);
+                        if (P.pos[1]) st(P.pos[1], o, posf[1]);
+                        if (P.pos[2]) st(P.pos[2], o, posf[2]);
+                        st(P.parent, o, pid);
+                        if (P.k) st(P.k, o, (uint8_t)k);
+                        if (P.step) st(P.step, o, a.step);
                     } else {
                         acc_drop += (double)wph * (double)eps;
                         flags |= SR_W_PHOTON_OVERFLOW;
@@ -326,78 +343,116 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 }
             }
         }
-        run_base += blk_tot;
+        run_base += wave_tot;
     }
 
-    // ---- per-chunk ledger partials (FP64, fixed reduction order)
-    const double v[7] = {wave_sum(acc_emit), wave_sum(acc_ll), wave_sum(acc_de),
-                         wave_sum(acc_clamp), wave_sum(acc_drop), 0.0, wave_sum(acc_w)};
+    if (have && lane == 0) cold_args<R>().seg_count[c] = run_base;
+
+    // ---- per-block ledger partial (FP64, fixed reduction order).  Clamped and
+    // dropped energy are rare: reduced only when some lane of the wave has them.
+    double v[7];
+    v[0] = wave_sum(acc_emit);
+    v[1] = wave_sum(acc_ll);
+    v[2] = __ballot(acc_de != 0.0) ? wave_sum(acc_de) : 0.0;
+    v[3] = __ballot(acc_clamp != 0.0) ? wave_sum(acc_clamp) : 0.0;
+    v[4] = __ballot(acc_drop != 0.0) ? wave_sum(acc_drop) : 0.0;
+    v[5] = (double)run_base;
+    v[6] = (double)wave_sum_f(acc_w);
     const float cm = wave_max(chi_max);
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) s_red[wave][q] = v[q];
         s_chi[wave] = cm;
     }
-    // latch device-side conditions: one atomic per wave, only when something happened
-    uint32_t wf = flags;
+    // latch device-side conditions.  Same-address atomics serialise across the
+    // whole device, so a wave only issues one when its bits are not yet set.
+    if (__ballot(flags != 0)) {
+        uint32_t wf = flags;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wf |= (uint32_t)__shfl_xor((int)wf, o, 64);
-    if (lane == 0 && wf) atomicOr(a.status, wf);
-    __syncthreads();
-    if (tid == 0) {
-        double* row = a.partials + c * SR_LEDGER_COLS;
-        for (int q = 0; q < 7; ++q) {
-            double sum = 0.0;
-            for (int wv = 0; wv < kWaves; ++wv) sum += s_red[wv][q];
-            row[q] = sum;
+        for (int o = 32; o > 0; o >>= 1) wf |= (uint32_t)__shfl_xor((int)wf, o, 64);
+        if (lane == 0) {
+            uint32_t *status = cold_args<R>().status;
+            if ((__atomic_load_n(status, __ATOMIC_RELAXED) & wf) != wf) atomicOr(status, wf);
         }
-        row[SR_LED_PHOTONS] = (double)run_base;
-        float m = 0.0f;
-        for (int wv = 0; wv < kWaves; ++wv) m = fmaxf(m, s_chi[wv]);
-        row[SR_LED_CHI_MAX] = (double)m;
-        a.seg_count[c] = (uint32_t)min(run_base, (int64_t)0xFFFFFFFF);
+    }
+    __syncthreads();
+    if (tid < 8) {
+        double r;
+        if (tid < 7) {
+            r = s_red[0][tid];
+            for (int wv = 1; wv < kWaves; ++wv) r += s_red[wv][tid];
+        } else {
+            float m = s_chi[0];
+            for (int wv = 1; wv < kWaves; ++wv) m = fmaxf(m, s_chi[wv]);
+            r = (double)m;
+        }
+        cold_args<R>().partials[(size_t)blk * SR_LEDGER_COLS + tid] = r;
     }
 }
 
-// Sum rows [lo, hi) of `in` (column 7 is a maximum) into out[b], fixed order.
+// Sum rows [lo, hi) of `in` (column SR_LED_CHI_MAX is a maximum) into out[b].
+// Each thread keeps all columns of a strided set of rows in registers, then the
+// block combines them with wave shuffles and LDS: a fixed order, so the
+// ledger is bit-reproducible.
 __global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__restrict__ in,
                                                                int64_t n_rows, int64_t per_block,
                                                                double *__restrict__ out) {
-    __shared__ double s[kBlock];
+    __shared__ double s[kWaves][SR_LEDGER_COLS];
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = min(lo + per_block, n_rows);
-    for (int col = 0; col < SR_LEDGER_COLS; ++col) {
-        const bool is_max = col == SR_LED_CHI_MAX;
-        double acc = 0.0;
-        for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-            const double v = in[r * SR_LEDGER_COLS + col];
-            acc = is_max ? fmax(acc, v) : acc + v;
+    double acc[SR_LEDGER_COLS];
+#pragma unroll
+    for (int c = 0; c < SR_LEDGER_COLS; ++c) acc[c] = 0.0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+        const double2 *row = (const double2 *)(in + r * SR_LEDGER_COLS);
+#pragma unroll
+        for (int q = 0; q < SR_LEDGER_COLS / 2; ++q) {
+            const double2 v = row[q];
+            const int c0 = 2 * q, c1 = 2 * q + 1;
+            acc[c0] = c0 == SR_LED_CHI_MAX ? fmax(acc[c0], v.x) : acc[c0] + v.x;
+            acc[c1] = c1 == SR_LED_CHI_MAX ? fmax(acc[c1], v.y) : acc[c1] + v.y;
         }
-        s[threadIdx.x] = acc;
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w)
-                s[threadIdx.x] = is_max ? fmax(s[threadIdx.x], s[threadIdx.x + w])
-                                        : s[threadIdx.x] + s[threadIdx.x + w];
-            __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < SR_LEDGER_COLS; ++c) {
+        double v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) {
+            const double u = __shfl_xor(v, o, 64);
+            v = c == SR_LED_CHI_MAX ? fmax(v, u) : v + u;
         }
-        if (threadIdx.x == 0) out[(int64_t)blockIdx.x * SR_LEDGER_COLS + col] = s[0];
-        __syncthreads();
+        if (lane == 0) s[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < SR_LEDGER_COLS) {
+        const int c = threadIdx.x;
+        double v = s[0][c];
+        for (int w = 1; w < kWaves; ++w) v = c == SR_LED_CHI_MAX ? fmax(v, s[w][c]) : v + s[w][c];
+        out[(int64_t)blockIdx.x * SR_LEDGER_COLS + c] = v;
     }
 }
+
+// partial ledger rows written by one step: one per block of kWaves chunks
+inline int64_t partial_rows(int64_t n_chunks) { return (n_chunks + kWaves - 1) / kWaves; }
 
 __global__ void zero_row_kernel(double *row) {
     if (threadIdx.x < SR_LEDGER_COLS) row[threadIdx.x] = 0.0;
 }
 
 constexpr int64_t kReduceL1Blocks = 1024;
+constexpr int64_t kReduceSingle = 512;     // rows one block sums directly
+constexpr int64_t kReducePerBlock = 64;    // rows per block in the first of two levels
 
-int reduce_ledger(sr_ledger *led, int64_t n_chunks, int64_t row, hipStream_t st) {
+int reduce_ledger(const sr_ledger *led, int64_t n_chunks, int64_t row, hipStream_t st) {
     double *dst = led->rows + row * SR_LEDGER_COLS;
-    if (n_chunks <= 4 * kBlock) {
+    n_chunks = partial_rows(n_chunks);   // the step writes one partial row per block
+    if (n_chunks == 0) {
+        zero_row_kernel<<<1, 64, 0, st>>>(dst);
+    } else if (n_chunks <= kReduceSingle) {
         ledger_reduce_kernel<<<1, kBlock, 0, st>>>(led->partials, n_chunks, n_chunks, dst);
     } else {
-        const int64_t per = (n_chunks + kReduceL1Blocks - 1) / kReduceL1Blocks;
+        int64_t per = (n_chunks + kReduceL1Blocks - 1) / kReduceL1Blocks;
+        if (per < kReducePerBlock) per = kReducePerBlock;
         const int64_t nb = (n_chunks + per - 1) / per;
         double *mid = led->partials + n_chunks * SR_LEDGER_COLS;
         ledger_reduce_kernel<<<(unsigned)nb, kBlock, 0, st>>>(led->partials, n_chunks, per, mid);
@@ -416,8 +471,7 @@ void split_inv(double dx, float &hi, float &lo) {
 template <typename R, typename PARTS>
 int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
                 uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
-                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, int64_t row,
-                void *stream) {
+                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream) {
     if (!parts || !grid || !prm || !tab || !chunks || !ph || !led) return SR_E_INVAL;
     const int64_t n = parts->n;
     if (n < 0 || !(dt > 0.0)) return SR_E_INVAL;
@@ -432,15 +486,18 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
         return SR_E_INVAL;
     if (!(prm->hbar_n > 0.0) || !(prm->alpha > 0.0)) return SR_E_INVAL;
-    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kBlock - 1) / kBlock;
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
     if (chunks->start == nullptr && chunks->n_chunks != n_chunks) return SR_E_INVAL;
     if (n_chunks < 0 || n_chunks > 0x7FFFFFFF) return SR_E_INVAL;
     if (ph->per_particle < 0 || !ph->seg_count) return SR_E_INVAL;
+    // the kernels address every array with 32-bit byte offsets
+    if (n >= ((int64_t)1 << 31) / (int64_t)sizeof(R) ||
+        n * ph->per_particle >= ((int64_t)1 << 30))
+        return SR_E_UNSUPPORTED;
     if (ph->per_particle > 0 &&
         (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2] || !ph->parent))
         return SR_E_INVAL;
-    if (!led->rows || !led->partials || !led->status || row < 0 || row >= led->n_rows)
-        return SR_E_INVAL;
+    if (!led->partials || !led->status) return SR_E_INVAL;
     if (led->partials_len < sr_ledger_partials(n_chunks)) return SR_E_INVAL;
     const bool has_pos = parts->x[0] != nullptr;
     if (dim != 0) {
@@ -452,13 +509,10 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
             if (grid->n[q] < 1 || grid->n[q] > (1 << 24) || !(grid->dx[q] > 0.0)) return SR_E_INVAL;
         if (dim == 2 && grid->n[2] != 1) return SR_E_INVAL;
         const int64_t cells = grid->n[0] * grid->n[1] * (dim == 3 ? grid->n[2] : 1);
-        if (cells <= 0 || cells > ((int64_t)1 << 34)) return SR_E_INVAL;
+        if (cells <= 0) return SR_E_INVAL;
+        if (cells >= ((int64_t)1 << 30)) return SR_E_UNSUPPORTED;
     }
-    if (n_chunks == 0) {
-        zero_row_kernel<<<1, 64, 0, (hipStream_t)stream>>>(led->rows + row * SR_LEDGER_COLS);
-        SR_HIP_CHECK(hipGetLastError());
-        return SR_OK;
-    }
+    if (n_chunks == 0) return SR_OK;
 
     StepArgs<R> a;
     a.n = n;
@@ -485,6 +539,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     }
     if (dim == 2) { g.n[2] = 1; }
     a.dt = (R)dt;
+    a.inv_dt = (R)(1.0 / dt);
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
     a.step = (uint32_t)step;
@@ -503,19 +558,20 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.tab.t1 = tab->t1;
     a.tab.r = tab->r;
     a.start = chunks->start;
+    a.n_chunks = n_chunks;
     a.per_particle = ph->per_particle;
-    a.seg_count = ph->seg_count;
-    a.ph_eps = ph->eps;
-    a.ph_w = ph->w;
-    for (int q = 0; q < 3; ++q) { a.ph_dir[q] = ph->dir[q]; a.ph_pos[q] = ph->pos[q]; }
-    a.ph_parent = ph->parent;
-    a.ph_k = ph->k;
-    a.ph_step = ph->step;
-    a.partials = led->partials;
-    a.status = led->status;
+    a.ph.seg_count = ph->seg_count;
+    a.ph.eps = ph->eps;
+    a.ph.w = ph->w;
+    for (int q = 0; q < 3; ++q) { a.ph.dir[q] = ph->dir[q]; a.ph.pos[q] = ph->pos[q]; }
+    a.ph.parent = ph->parent;
+    a.ph.k = ph->k;
+    a.ph.step = ph->step;
+    a.ph.partials = led->partials;
+    a.ph.status = led->status;
 
     hipStream_t st = (hipStream_t)stream;
-    const dim3 grd((unsigned)n_chunks), blk(kBlock);
+    const dim3 grd((unsigned)partial_rows(n_chunks)), blk(kBlock);
     const int KM = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : 16;
 
 #define SR_LAUNCH(DIMV, KMV, SMP) \
@@ -540,7 +596,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
 #undef SR_BY_K
 #undef SR_LAUNCH
     SR_HIP_CHECK(hipGetLastError());
-    return reduce_ledger(led, n_chunks, row, st);
+    return SR_OK;
 }
 
 }  // namespace
@@ -550,25 +606,33 @@ using namespace sr;
 
 extern "C" int64_t sr_ledger_partials(int64_t n_chunks) {
     if (n_chunks < 0) return 0;
-    return (n_chunks + kReduceL1Blocks + 1) * SR_LEDGER_COLS;
+    return (partial_rows(n_chunks) + kReduceL1Blocks + 1) * SR_LEDGER_COLS;
 }
 
 extern "C" int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields,
                                    const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
                                    const sr_params *prm, const sr_table *tab,
                                    const sr_chunking *chunks, sr_photon_buf *photons,
-                                   sr_ledger *ledger, int64_t row, void *stream) {
+                                   sr_ledger *ledger, void *stream) {
     return launch_step<float>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
-                              ledger, row, stream);
+                              ledger, stream);
 }
 
 extern "C" int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields,
                                        const sr_grid *grid, double dt, uint64_t seed,
                                        uint64_t step, const sr_params *prm, const sr_table *tab,
                                        const sr_chunking *chunks, sr_photon_buf *photons,
-                                       sr_ledger *ledger, int64_t row, void *stream) {
+                                       sr_ledger *ledger, void *stream) {
     return launch_step<double>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
-                               ledger, row, stream);
+                               ledger, stream);
+}
+
+extern "C" int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row,
+                                void *stream) {
+    if (!ledger || !ledger->rows || !ledger->partials || n_chunks < 0 || n_chunks > 0x7FFFFFFF ||
+        row < 0 || row >= ledger->n_rows || ledger->partials_len < sr_ledger_partials(n_chunks))
+        return SR_E_INVAL;
+    return reduce_ledger(ledger, n_chunks, row, (hipStream_t)stream);
 }
 
 extern "C" int sr_energy_ledger(const sr_ledger *led, int64_t row, double *out, void *stream) {

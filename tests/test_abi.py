@@ -77,7 +77,7 @@ def test_step_rejects_bad_arguments_on_host(lib):
     args = dict(dt=0.1, seed=1, step=0)
     # null particle arrays with n > 0
     rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), args["dt"], 1, 0, C.byref(prm),
-                                 None, C.byref(ch), C.byref(ph), C.byref(led), 0, None)
+                                 None, C.byref(ch), C.byref(ph), C.byref(led), None)
     assert rc == L.SR_E_INVAL
     # bad K, bad dt, bad grid dim: all caught before any launch
     dummy = C.c_void_p(16)
@@ -91,7 +91,9 @@ def test_step_rejects_bad_arguments_on_host(lib):
                              (L.Params(0.0, 7.3e-3, 1, 0, 1, 0, 0, 0), 0.1, 0)):
         grid.dim = dim
         rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), dt, 1, 0, C.byref(bad_prm),
-                                     dummy, C.byref(ch), C.byref(ph), C.byref(led), 0, None)
+                                     dummy, C.byref(ch), C.byref(ph), C.byref(led), None)
         assert rc == L.SR_E_INVAL
     assert lib.sr_table_build(None, None) == L.SR_E_INVAL
     assert lib.sr_energy_ledger(None, 0, None, None) == L.SR_E_INVAL
+    assert lib.sr_ledger_reduce(None, 1, 0, None) == L.SR_E_INVAL
+    assert lib.sr_ledger_reduce(C.byref(led), 1, 0, None) == L.SR_E_INVAL

@@ -1,0 +1,299 @@
+"""GPU tests at the workloads' full sizes (sampled against the oracle), the
+helper kernels, edge cases, and the whole config-1 run."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests import parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1409_5574_amd import api
+    api.lib()
+    return api
+
+
+@pytest.fixture(scope="module")
+def table(sr):
+    t = sr.Table()
+    torch.cuda.synchronize()
+    return t
+
+
+def _orc(d, idx=None):
+    out = {}
+    for k, v in d.items():
+        if v is None:
+            out[k] = None
+            continue
+        v = v if idx is None else v[idx]
+        out[k] = v.astype(np.float64) if v.dtype != np.uint32 else v.copy()
+    return out
+
+
+# ------------------------------------------------------------------ helpers
+def test_standing_wave_refresh_matches_generator(sr):
+    cfg = synth.config("c3", grid=(96, 40, 24))
+    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    f = sr.Fields(ncells=int(np.prod(cfg.grid)))
+    for t in (0.0, 0.37, 5.1):
+        _say(f"standing wave t={t}")
+        sr.standing_wave(f, grid, cfg.a0, t)
+        E, B = synth.standing_wave_grid(cfg, t)
+        for got, ref in zip(f.e + f.b, E + B):
+            g = got.cpu().numpy()
+            # both are FP64 values rounded to binary32; allow one ulp either way
+            assert np.all(np.abs(g - ref) <= np.spacing(np.abs(ref).astype(np.float32)) + 1e-30)
+
+
+def test_sort_particles_is_tile_ordered_permutation(sr):
+    cfg = synth.config("c3", grid=(40, 32, 24), slab=None)
+    n = 50001
+    st = synth.gen_particles(cfg, n=n)
+    parts = sr.Particles.from_numpy(st, dim=3)
+    dst = parts.empty_like()
+    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    tile = (8, 8, 4)
+    work = sr.sort_work(grid, tile, n)
+    _say("sort 50001")
+    sr.sort_particles(parts, dst, grid, tile, work)
+    torch.cuda.synchronize()
+    g = dst.to_numpy()
+    assert np.array_equal(np.sort(g["id"]), np.arange(n, dtype=np.uint32))
+    # every particle keeps its own state
+    o = np.argsort(g["id"])
+    for k in ("x", "y", "z", "px", "py", "pz"):
+        assert np.array_equal(g[k][o], st[k].astype(np.float64))
+    cell = [np.clip(np.floor(g[k].astype(np.float32) * np.float32(1 / cfg.dx)).astype(np.int64), 0,
+                    cfg.grid[a] - 1) for a, k in enumerate(("x", "y", "z"))]
+    nt = [-(-cfg.grid[a] // tile[a]) for a in range(3)]
+    key = (cell[0] // tile[0]) + nt[0] * ((cell[1] // tile[1]) + nt[1] * (cell[2] // tile[2]))
+    assert np.all(np.diff(key) >= 0)
+
+
+def _step_for_photons(sr, table, cfg, n, K, p_scale, per_particle=None):
+    st = synth.gen_particles(cfg, n=n)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k] * p_scale).astype(np.float32)
+    E, B = synth.standing_wave_grid(cfg, 0.2)
+    parts = sr.Particles.from_numpy(st, dim=cfg.dim)
+    fields = sr.Fields(E, B)
+    grid = sr.grid_struct(cfg.dim, n=cfg.grid, dx=(cfg.dx,) * 3)
+    pp = K if per_particle is None else per_particle
+    photons = sr.PhotonBuffer(n, pp, dim=cfg.dim)
+    ledger = sr.LedgerBuf(2, sr.n_chunks_uniform(n))
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, kin_cut=cfg.kin_cut)
+    sr.gather_push_emit(parts, fields, grid, cfg.dt, 5, 0, prm, table, photons, ledger, 0)
+    return parts, photons, ledger
+
+
+def test_spectrum_histogram_matches_host(sr, table):
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    n = 20000
+    _say("histogram")
+    parts, photons, ledger = _step_for_photons(sr, table, cfg, n, 2, 2000.0)
+    nb, lo, hi = 48, 1e-6, 1e4
+    hist = torch.zeros(2 * nb, device="cuda", dtype=torch.float64)
+    work = sr.hist_work(nb)
+    sr.spectrum_histogram(photons, n, lo, hi, nb, hist, work)
+    sr.spectrum_histogram(photons, n, lo, hi, nb, hist, work)   # accumulates
+    torch.cuda.synchronize()
+    ph = photons.gather(n)
+    assert ph["count"] > 1000
+    edges = np.exp2(np.log2(lo) + (np.log2(hi) - np.log2(lo)) * np.arange(nb + 1) / nb)
+    e = ph["eps"].astype(np.float64)
+    w = ph["w"].astype(np.float64)
+    he, _ = np.histogram(e, bins=edges, weights=w * e)
+    hw, _ = np.histogram(e, bins=edges, weights=w)
+    h = hist.cpu().numpy() / 2
+    # photons within a float rounding of a bin edge may land in the neighbour bin
+    assert np.abs(h[:nb] - he).sum() <= 1e-5 * he.sum()
+    assert np.abs(h[nb:] - hw).sum() <= 1e-5 * hw.sum() + 2
+
+
+def test_photon_overflow_is_counted_and_ledgered(sr, table):
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    n = 4000
+    _say("overflow full")
+    _, ph_ok, led_ok = _step_for_photons(sr, table, cfg, n, 16, 3000.0)
+    _say("overflow per_particle=1")
+    _, ph_small, led_small = _step_for_photons(sr, table, cfg, n, 16, 3000.0, per_particle=1)
+    _say("overflow per_particle=0")
+    _, ph_none, led_none = _step_for_photons(sr, table, cfg, n, 16, 3000.0, per_particle=0)
+    torch.cuda.synchronize()
+    r_ok, r_small, r_none = led_ok.row(0), led_small.row(0), led_none.row(0)
+    assert r_ok[5] > 1.5 * n        # well above one slot per particle
+    assert r_ok[4] == 0.0 and led_ok.read_status() & 1 == 0
+    assert led_small.read_status() & 1 and led_none.read_status() & 1
+    # the same photons are emitted whatever the capacity; stored + dropped = emitted
+    for r in (r_small, r_none):
+        assert r[5] == r_ok[5]
+        assert r[0] == pytest.approx(r_ok[0], rel=1e-12)
+    stored = ph_small.gather(n)
+    assert stored["stored"] <= n
+    assert r_small[4] == pytest.approx(r_ok[0] - float((stored["w"] * stored["eps"]).astype(np.float64).sum()),
+                                       rel=1e-5)
+    # dropped sums FP32 photon energies; emitted sums the per-particle FP32 totals
+    assert r_none[4] == pytest.approx(r_ok[0], rel=1e-6)
+
+
+def test_empty_particle_set(sr, table):
+    cfg = synth.config("c2", grid=(32, 32, 1))
+    parts = sr.Particles([torch.empty(0, device="cuda")] * 2 + [None],
+                         [torch.empty(0, device="cuda") for _ in range(3)],
+                         torch.empty(0, device="cuda"), torch.empty(0, device="cuda", dtype=torch.int32))
+    E, B = synth.standing_wave_grid(cfg, 0.0)
+    fields = sr.Fields(E, B)
+    grid = sr.grid_struct(2, n=cfg.grid, dx=(cfg.dx,) * 3)
+    photons = sr.PhotonBuffer(0, 1, dim=2)
+    ledger = sr.LedgerBuf(1, 0)
+    ledger.rows.fill_(7.0)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, 1)
+    _say("empty")
+    sr.gather_push_emit(parts, fields, grid, cfg.dt, 1, 0, prm, table, photons, ledger, 0)
+    torch.cuda.synchronize()
+    assert np.all(ledger.row(0) == 0.0)
+
+
+# ------------------------------------------------------------------ config 1, whole run
+def test_config1_full_run(sr, table, oracle):
+    cfg = synth.config("c1")
+    n, steps, seed = cfg.n_particles, cfg.steps, 20240601
+    st = synth.gen_particles(cfg)
+    parts = sr.Particles.from_numpy(st, dim=0)
+    parts.x = [None, None, None]
+    grid = sr.grid_struct(0, b0=cfg.b0)
+    photons = sr.PhotonBuffer(n, 1, dim=3)
+    ledger = sr.LedgerBuf(steps, sr.n_chunks_uniform(n))
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, 1, recoil=cfg.recoil, push_position=False)
+    nb, lo, hi = 64, 1e-3, 1e5
+    hist = torch.zeros(2 * nb, device="cuda", dtype=torch.float64)
+    work = sr.hist_work(nb)
+    _say(f"config 1 full run {n} x {steps}")
+    structs = sr.make_structs(parts, None, photons, ledger)
+    for s in range(steps):
+        sr.gather_push_emit(parts, None, grid, cfg.dt, seed, s, prm, table, photons, ledger, s,
+                            structs=structs)
+        sr.spectrum_histogram(photons, n, lo, hi, nb, hist, work)
+    torch.cuda.synchronize()
+    g = parts.to_numpy()
+    rows = ledger.rows.cpu().numpy()
+    h_gpu = hist.cpu().numpy()[:nb]
+
+    orc = _orc(st)
+    orc["x"] = orc["y"] = orc["z"] = None
+    f = oracle.Field(0, b0=cfg.b0)
+    edges = np.exp2(np.log2(lo) + (np.log2(hi) - np.log2(lo)) * np.arange(nb + 1) / nb)
+    h_orc = np.zeros(nb)
+    led = np.zeros((steps, 5))
+    for s in range(steps):
+        ph, led[s], _ = oracle.step(orc, f, cfg.dt, seed, s, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
+                                    n_samples=1, recoil=cfg.recoil, push_position=False)
+        h, _ = np.histogram(ph["eps"], bins=edges, weights=ph["w"] * ph["eps"])
+        h_orc += h
+    n_ph_gpu, n_ph_orc = rows[:, 5].sum(), None
+    spec_err = float(np.abs(h_gpu - h_orc).sum() / h_orc.sum())
+    e_gpu, e_orc = rows[:, 0].sum(), led[:, 0].sum()
+    ll_gpu, ll_orc = rows[:, 1].sum(), led[:, 1].sum()
+    pg = np.stack([g["px"], g["py"], g["pz"]], 1)[np.argsort(g["id"])]
+    po = np.stack([orc["px"], orc["py"], orc["pz"]], 1)
+    # particles whose recoil was clamped end at p = 0 on both sides
+    rel = np.linalg.norm(pg - po, axis=1) / np.maximum(np.linalg.norm(po, axis=1), 1e-30)
+    print(f"config1: photons gpu {n_ph_gpu:.0f}, spectrum err {spec_err:.2e}, emitted rel "
+          f"{abs(e_gpu / e_orc - 1):.2e}, LL rel {abs(ll_gpu / ll_orc - 1):.2e}, |dp|/p median "
+          f"{np.median(rel):.2e} max {rel.max():.2e}", flush=True)
+    del n_ph_orc
+    assert spec_err <= 1e-3
+    assert abs(e_gpu / e_orc - 1) <= 1e-3
+    assert abs(ll_gpu / ll_orc - 1) <= 1e-4
+    # 1000 FP32 steps: errors accumulate at most linearly from the per-step bound
+    assert np.median(rel) <= 1e-5
+    assert np.quantile(rel, 0.99) <= steps * parity.P_TOL
+
+
+# ------------------------------------------------------------------ full-size, sampled
+def _device_fields(sr, cfg, t):
+    """The generator's field, rounded to binary32, expanded along y and z on the device."""
+    one = synth.config(cfg.name[:2] if cfg.name[:2] in synth.CONFIGS else "c3",
+                       grid=(cfg.grid[0], 1, 1), dx=cfg.dx, a0=cfg.a0)
+    E, B = synth.standing_wave_grid(one, t)
+    nx, ny, nz = cfg.grid[0], cfg.grid[1], (cfg.grid[2] if cfg.dim == 3 else 1)
+    f = sr.Fields(ncells=nx * ny * nz)
+    for dst, prof in zip(f.e + f.b, E + B):
+        dst.view(nz, ny, nx).copy_(torch.from_numpy(prof).to("cuda").view(1, 1, nx))
+    return f, E + B
+
+
+def _host_grid(profiles, cfg):
+    nx, ny, nz = cfg.grid[0], cfg.grid[1], (cfg.grid[2] if cfg.dim == 3 else 1)
+    return [np.ascontiguousarray(np.broadcast_to(p.reshape(1, 1, nx), (nz, ny, nx)).reshape(-1))
+            for p in profiles]
+
+
+@pytest.mark.parametrize("name,sample", [("c2", 20000), ("c3", 6000), ("c5", 4000)])
+def test_full_size_one_step_sampled(sr, table, oracle, name, sample):
+    cfg = synth.config(name)
+    n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
+    seed, step, t = 99, 7, 0.3
+    st = synth.gen_particles(cfg)
+    _say(f"full size {name}: n={n} grid={cfg.grid}")
+    parts = sr.Particles.from_numpy(st, dim=dim)
+    grid = sr.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
+    # the launch configuration the benchmark times: tile-sorted particles, uniform chunks
+    tile = (64, 4, 1) if dim == 2 else (16, 4, 4)
+    work = sr.sort_work(grid, tile, n)
+    sorted_parts = parts.empty_like()
+    sr.sort_particles(parts, sorted_parts, grid, tile, work)
+    del parts, work
+    fields, profiles = _device_fields(sr, cfg, t)
+    photons = sr.PhotonBuffer(n, cfg.photons_per_particle, dim=dim)
+    ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, recoil=cfg.recoil, kin_cut=cfg.kin_cut)
+    sr.gather_push_emit(sorted_parts, fields, grid, cfg.dt, seed, step, prm, table, photons,
+                        ledger, 0)
+    torch.cuda.synchronize()
+    status = ledger.read_status()
+    assert status & ~2 == 0
+    g = sorted_parts.to_numpy()
+    ph_all = photons.gather(n)
+    del sorted_parts, photons, fields
+    torch.cuda.empty_cache()
+
+    rng = np.random.default_rng(3)
+    ids = np.sort(rng.choice(n, size=sample, replace=False)).astype(np.uint32)
+    orc = _orc(st, ids)
+    old = _orc(st, ids)
+    if dim == 2:
+        orc["z"] = None
+    host = _host_grid(profiles, cfg)
+    fo = oracle.Field(dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=host[:3], B=host[3:])
+    ph_o, led_o, det = oracle.step(orc, fo, cfg.dt, seed, step, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
+                                   n_samples=K, recoil=cfg.recoil, kin_cut=cfg.kin_cut, detail=True)
+    del host, fo
+    gi = np.argsort(g["id"])[ids]
+    gs = {k: (v[gi] if v is not None else None) for k, v in g.items()}
+    keep = np.isin(ph_all["parent"], ids)
+    ph_g = {k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in ph_all.items()}
+    xcut = None
+    if cfg.kin_cut:
+        xcut = np.abs(1.5 * np.repeat(det["chi"], K) * det["xs"] - 1.0) <= 1e-5
+    rep = parity.compare_step(gs, orc, old, ph_g, ph_o, det, K, box=cfg.box, xcut_band=xcut)
+    e_gpu = float((ph_g["w"].astype(np.float64) * ph_g["eps"]).sum())
+    assert e_gpu == pytest.approx(led_o[0], rel=parity.LEDGER_TOL) or rep["decision_flips"]
+    print(f"{name}: sampled {sample}, photons {rep['photons_oracle']}, flips "
+          f"{rep['decision_flips']}, |dp|/p {rep['p_rel_err']:.2e}", flush=True)
