@@ -134,6 +134,10 @@ typedef struct {
                                SR_DN_CLAMP: dN >= 1 emits with weight w/K           */
     int32_t kin_cut;        /* 1: no photon above the emitter's energy (x > 2/(3 chi)) */
     int32_t push_position;  /* 1: advance positions by dt p/gamma after the push    */
+    const void *mlp_params; /* SR_SAMPLER_MLP: device bfloat16[SR_MLP_PARAMS]        */
+    const uint8_t *mlp_fallback; /* SR_SAMPLER_MLP: device uint8[SR_MLP_FALLBACK_BINS]:
+                               1 sends the trials of that log10 chi bin on
+                               [-4, 2) (and any chi outside it) to the table       */
 } sr_params;
 
 /* Chunking of the particle array.  Chunk c covers particles
@@ -286,6 +290,43 @@ int sr_field_standing_wave(float *e[3], float *b[3], const sr_grid *grid, double
 int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *dst, const sr_grid *grid,
                       const int32_t tile[3], void *work, void *stream);
 int64_t sr_sort_work(const sr_grid *grid, const int32_t tile[3], int64_t n);
+
+/* ------------------------------------------------- MLP surrogate (direct sampler)
+ * A 2 -> 64 -> 64 -> 64 -> 1 SiLU network mapping (f0, f1) = ((log10 chi + 1)/3,
+ * logit(u)/16) to log2 x, x = inverse photon-number CDF at u (with the kinematic cut
+ * when trained so).  Parameters: flat [SR_MLP_PARAMS] in the order W1[64][2],
+ * b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[64], b4; bfloat16 copies
+ * are what the kernels read, FP32 masters what Adam updates.  The 64x64 layers
+ * run on the matrix cores (bfloat16 in, FP32 accumulate).  Not from the paper:
+ * a learned stand-in for the inverse CDF of the spectrum of section "Monte Carlo
+ * method", judged against the tables. */
+#define SR_MLP_PARAMS 8577
+#define SR_MLP_FALLBACK_BINS 24
+
+/* out[i] = network(feats[i]) for M samples; feats device [M][2], out device [M]. */
+int sr_mlp_forward(const void *params_bf16, const float *feats, float *out, int64_t M,
+                   void *stream);
+/* grads = gradient of (1/M) sum (network(feats[i]) - target[i])^2 (device FP32
+ * [SR_MLP_PARAMS]); work: device FP32 workspace of sr_mlp_grad_work() floats. */
+int sr_mlp_mse_grad(const void *params_bf16, const float *feats, const float *target, int64_t M,
+                    float *grads, float *work, void *stream);
+int64_t sr_mlp_grad_work(void);
+/* One Adam step (bias-corrected, step t >= 1) on the FP32 masters, refreshing
+ * the bfloat16 copies.  All arrays device [SR_MLP_PARAMS]. */
+int sr_mlp_adam(float *master, void *params_bf16, const float *grads, float *m, float *v,
+                int64_t t, float lr, float beta1, float beta2, float eps, void *stream);
+/* params_bf16 = round(master). */
+int sr_mlp_cast(const float *master, void *params_bf16, void *stream);
+/* M training pairs from the tables: log10 chi uniform on [lo, hi], u a 23-bit
+ * midpoint (Philox, key seed, counter (i, batch, 3)), target log2 x clipped
+ * below at -24.  feats device [M][2], target device [M]. */
+int sr_mlp_make_batch(const sr_table *tab, uint64_t seed, uint64_t batch, int32_t kin_cut,
+                      double log10chi_lo, double log10chi_hi, float *feats, float *target,
+                      int64_t M, void *stream);
+/* Table-direct sample: x for uniform words a (23-bit midpoints) at chi, the
+ * device function of SR_SAMPLER_TABLE.  All arrays device [n]. */
+int sr_eval_direct(const sr_table *tab, const uint32_t *a, const float *chi, int32_t kin_cut,
+                   float *out_x, int64_t n, void *stream);
 
 /* Human-readable text for a code. */
 const char *sr_strerror(int code);

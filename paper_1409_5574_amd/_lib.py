@@ -21,6 +21,8 @@ SR_CHUNK = 64
 SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP = 0, 1, 2
 SR_RECOIL_NONE, SR_RECOIL_PHOTON, SR_RECOIL_LL = 0, 1, 2
 SR_DN_WEIGHT, SR_DN_CLAMP = 0, 1
+SR_MLP_PARAMS = 8577
+SR_MLP_FALLBACK_BINS = 24
 
 P3 = C.c_void_p * 3
 
@@ -45,7 +47,8 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("hbar_n", C.c_double), ("alpha", C.c_double), ("n_samples", C.c_int32),
                 ("sampler", C.c_int32), ("recoil", C.c_int32), ("dn_policy", C.c_int32),
-                ("kin_cut", C.c_int32), ("push_position", C.c_int32)]
+                ("kin_cut", C.c_int32), ("push_position", C.c_int32),
+                ("mlp_params", C.c_void_p), ("mlp_fallback", C.c_void_p)]
 
 
 class Chunking(C.Structure):
@@ -98,6 +101,14 @@ SIGNATURES = {
                                     C.POINTER(Grid), C.POINTER(C.c_int32), _P, _P]),
     "sr_sort_work": (C.c_int64, [C.POINTER(Grid), C.POINTER(C.c_int32), _I64]),
     "sr_strerror": (C.c_char_p, [C.c_int]),
+    "sr_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
+    "sr_mlp_mse_grad": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
+    "sr_mlp_grad_work": (C.c_int64, []),
+    "sr_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, C.c_float, C.c_float,
+                              C.c_float, _P]),
+    "sr_mlp_cast": (C.c_int, [_P, _P, _P]),
+    "sr_mlp_make_batch": (C.c_int, [_P, _U64, _U64, _I32, _D, _D, _P, _P, _I64, _P]),
+    "sr_eval_direct": (C.c_int, [_P, _P, _P, _I32, _P, _I64, _P]),
 }
 
 _lib = None

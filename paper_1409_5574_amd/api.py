@@ -267,9 +267,117 @@ class LedgerBuf:
 
 
 def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.SR_RECOIL_PHOTON,
-                  dn_policy=L.SR_DN_WEIGHT, kin_cut=False, push_position=True) -> L.Params:
+                  dn_policy=L.SR_DN_WEIGHT, kin_cut=False, push_position=True,
+                  mlp: "Mlp | None" = None) -> L.Params:
     return L.Params(float(hbar_n), float(alpha), int(n_samples), int(sampler), int(recoil),
-                    int(dn_policy), int(bool(kin_cut)), int(bool(push_position)))
+                    int(dn_policy), int(bool(kin_cut)), int(bool(push_position)),
+                    None if mlp is None else mlp.params.data_ptr(),
+                    None if mlp is None else mlp.fallback.data_ptr())
+
+
+def eval_direct(table: Table, a: torch.Tensor, chi: torch.Tensor, kin_cut: bool) -> torch.Tensor:
+    a = a.contiguous().to(DEV, torch.int32)
+    chi = chi.contiguous().to(DEV, torch.float32)
+    out = torch.empty_like(chi)
+    L.check(lib().sr_eval_direct(table.handle, _ptr(a), _ptr(chi), int(kin_cut), _ptr(out),
+                                 a.numel(), _stream()), "sr_eval_direct")
+    return out
+
+
+class Mlp:
+    """The MLP surrogate: FP32 master weights, Adam moments and the bfloat16
+    copy the kernels read, all on the device."""
+
+    def __init__(self, master: np.ndarray):
+        assert master.size == L.SR_MLP_PARAMS
+        self.master = torch.from_numpy(np.asarray(master, np.float32)).to(DEV)
+        self.params = torch.empty(L.SR_MLP_PARAMS, device=DEV, dtype=torch.bfloat16)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grads = torch.zeros_like(self.master)
+        self.work = torch.empty(int(lib().sr_mlp_grad_work()), device=DEV, dtype=torch.float32)
+        self.fallback = torch.zeros(L.SR_MLP_FALLBACK_BINS, device=DEV, dtype=torch.uint8)
+        self.t = 0
+        L.check(lib().sr_mlp_cast(_ptr(self.master), _ptr(self.params), _stream()), "sr_mlp_cast")
+
+    def forward(self, feats: torch.Tensor) -> torch.Tensor:
+        feats = feats.contiguous().to(DEV, torch.float32)
+        out = torch.empty(feats.shape[0], device=DEV, dtype=torch.float32)
+        L.check(lib().sr_mlp_forward(_ptr(self.params), _ptr(feats), _ptr(out), feats.shape[0],
+                                     _stream()), "sr_mlp_forward")
+        return out
+
+    def mse_grad(self, feats: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+        L.check(lib().sr_mlp_mse_grad(_ptr(self.params), _ptr(feats), _ptr(target),
+                                      feats.shape[0], _ptr(self.grads), _ptr(self.work),
+                                      _stream()), "sr_mlp_mse_grad")
+        return self.grads
+
+    def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        L.check(lib().sr_mlp_adam(_ptr(self.master), _ptr(self.params), _ptr(self.grads),
+                                  _ptr(self.m), _ptr(self.v), self.t, lr, beta1, beta2, eps,
+                                  _stream()), "sr_mlp_adam")
+
+    def train(self, table: Table, steps: int, batch: int, lr: float, seed: int = 0x5A11,
+              kin_cut: bool = True, lo: float = -4.0, hi: float = 2.0, lr_final: float | None = None):
+        """Adam on fresh batches of table-generated pairs; cosine-decayed learning rate."""
+        feats = torch.empty((batch, 2), device=DEV, dtype=torch.float32)
+        target = torch.empty(batch, device=DEV, dtype=torch.float32)
+        lr_final = lr * 0.01 if lr_final is None else lr_final
+        for s_ in range(steps):
+            L.check(lib().sr_mlp_make_batch(table.handle, seed, s_, int(kin_cut), lo, hi,
+                                            _ptr(feats), _ptr(target), batch, _stream()),
+                    "sr_mlp_make_batch")
+            self.mse_grad(feats, target)
+            frac = s_ / max(steps - 1, 1)
+            cur = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * frac))
+            self.adam(float(cur))
+
+    def judge(self, table: Table, kin_cut: bool = True, n_u: int = 1 << 14, chi_per_bin: int = 8,
+              x_lo: float = 1e-4, x_hi: float = 16.4, n_xbins: int = 64, tol: float = 1e-3):
+        """Binned-spectrum error of the network against the table sampler, per bin
+        of log10 chi of the fallback map, on a stratified grid of u (23-bit
+        midpoints) and chi_per_bin values of chi per bin.  The error of a bin is
+        sum |h_mlp - h_table| / sum h_table over n_xbins log bins of x in
+        [x_lo, x_hi], each sample weighted by its energy (proportional to x).
+        Bins above `tol` are switched to the table.  Returns the errors."""
+        nb = L.SR_MLP_FALLBACK_BINS
+        lo, hi = -4.0, 2.0
+        width = (hi - lo) / nb
+        m = ((np.arange(n_u) + 0.5) * (2 ** 23 / n_u)).astype(np.uint64)
+        words = (m << np.uint64(9)).astype(np.uint32)
+        u = (2.0 * m.astype(np.float64) + 1.0) * 2.0 ** -24
+        lchi = lo + width * (np.arange(nb)[:, None] + (np.arange(chi_per_bin)[None, :] + 0.5)
+                             / chi_per_bin)
+        lchi = lchi.reshape(-1)
+        L_ = np.repeat(lchi, n_u)
+        U_ = np.tile(u, lchi.size)
+        A_ = np.tile(words, lchi.size)
+        chi = torch.from_numpy((10.0 ** L_).astype(np.float32))
+        x_tab = eval_direct(table, torch.from_numpy(A_.view(np.int32)), chi, kin_cut)
+        feats = torch.from_numpy(np.stack([(L_ + 1.0) / 3.0, (np.log(U_) - np.log1p(-U_)) / 16.0],
+                                          1).astype(np.float32))
+        x_mlp = torch.exp2(self.forward(feats))
+        edges = np.geomspace(x_lo, x_hi, n_xbins + 1)
+        xt = x_tab.cpu().numpy().astype(np.float64).reshape(nb, -1)
+        xm = x_mlp.cpu().numpy().astype(np.float64).reshape(nb, -1)
+        err = np.zeros(nb)
+        for b in range(nb):
+            ht, _ = np.histogram(xt[b], bins=edges, weights=xt[b])
+            hm, _ = np.histogram(xm[b], bins=edges, weights=xm[b])
+            err[b] = np.abs(hm - ht).sum() / max(ht.sum(), 1e-300)
+        self.fallback.copy_(torch.from_numpy((err > tol).astype(np.uint8)))
+        return err
+
+    def make_batch(self, table: Table, seed: int, batch_index: int, M: int, kin_cut=True,
+                   lo=-4.0, hi=2.0):
+        feats = torch.empty((M, 2), device=DEV, dtype=torch.float32)
+        target = torch.empty(M, device=DEV, dtype=torch.float32)
+        L.check(lib().sr_mlp_make_batch(table.handle, seed, batch_index, int(kin_cut), lo, hi,
+                                        _ptr(feats), _ptr(target), M, _stream()),
+                "sr_mlp_make_batch")
+        return feats, target
 
 
 def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, seed: int,

@@ -1,0 +1,429 @@
+// sr_mlp.hip -- the MLP surrogate of the inverse number-CDF: inference,
+// training (mean-squared error on log2 x, gradients on the matrix cores), Adam,
+// and the generation of training triples from the FP64-built tables.
+#include <math.h>
+
+#include "sr_mlp.hpp"
+
+namespace sr {
+namespace {
+
+// ------------------------------------------------------------------ inference
+__global__ __launch_bounds__(kBlock) void mlp_forward_kernel(const __bf16 *__restrict__ params,
+                                                             const float2 *__restrict__ feats,
+                                                             float *__restrict__ out, int64_t M) {
+    __shared__ MlpSmem s;
+    __shared__ alignas(16) __bf16 tbuf[kWaves][2 * 16 * kH];
+    mlp_load(s, params, threadIdx.x, blockDim.x);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15;
+    for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile * 16 < M;
+         tile += (int64_t)gridDim.x * kWaves) {
+        const int64_t idx = tile * 16 + r;
+        const bool valid = idx < M;
+        const float2 f = valid ? feats[idx] : make_float2(0.f, 0.f);
+        const float y = mlp_tile16(s, tbuf[wave], f.x, f.y);
+        if (valid && lane < 16) out[idx] = y;
+    }
+}
+
+// ------------------------------------------------------------------ training
+__device__ __forceinline__ float dsilu(float z) {
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+    return sg * (1.0f + z * (1.0f - sg));
+}
+
+struct alignas(16) TrainSmem {
+    MlpSmem m;
+    alignas(16) __bf16 W2T[kH * kH];   // W2T[k][j] = W2[j][k]
+    alignas(16) __bf16 W3T[kH * kH];
+};
+
+// Gradient of L = (1/M) sum w (y - t)^2, w = x / E[x] (the energy weighting of
+// the binned spectrum the network is judged on), for this kernel's tiles.
+// Each wave accumulates its own gradient and writes it to work[wave_global][...]
+// (summed in a fixed order by grad_reduce).
+__global__ __launch_bounds__(kBlock) void mlp_train_kernel(const __bf16 *__restrict__ params,
+                                                           const float2 *__restrict__ feats,
+                                                           const float *__restrict__ target,
+                                                           int64_t M, float inv_m,
+                                                           float *__restrict__ work) {
+    __shared__ TrainSmem s;
+    __shared__ alignas(16) __bf16 tbuf[kWaves][2 * 16 * kH];
+    mlp_load(s.m, params, threadIdx.x, blockDim.x);
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
+        const int j = i / kH, k = i % kH;
+        s.W2T[k * kH + j] = params[kOffW2 + i];
+        s.W3T[k * kH + j] = params[kOffW3 + i];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+    __bf16 *tb = tbuf[wave];
+
+    f32x4 gW2[4][4], gW3[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            gW2[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            gW3[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+    float gW1[4][2], gb1[4], gb2[4], gb3[4], gW4[4], gb4 = 0.f;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        gW1[n][0] = gW1[n][1] = gb1[n] = gb2[n] = gb3[n] = gW4[n] = 0.f;
+    }
+
+    for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile * 16 < M;
+         tile += (int64_t)gridDim.x * kWaves) {
+        const int64_t idx = tile * 16 + r;
+        const bool valid = idx < M;
+        const float2 f = valid ? feats[idx] : make_float2(0.f, 0.f);
+        const float tgt = valid ? target[idx] : 0.f;
+        // features of the samples of the D-layout rows 4g+q
+        float fq0[4], fq1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            fq0[q] = __shfl(f.x, 4 * g + q, 64);
+            fq1[q] = __shfl(f.y, 4 * g + q, 64);
+        }
+        // ---- forward, keeping pre-activations in the D layout
+        Split8 a[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 32 * kb + 8 * g + e;
+                split_set(a[kb], e, silu(fmaf(s.m.W1[2 * k], f.x, fmaf(s.m.W1[2 * k + 1], f.y, s.m.b1[k]))));
+            }
+        float z1[4][4];   // z1[n][q]: sample 4g+q, feature 16n+r
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int k = 16 * n + r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                z1[n][q] = fmaf(s.m.W1[2 * k], fq0[q], fmaf(s.m.W1[2 * k + 1], fq1[q], s.m.b1[k]));
+        }
+        f32x4 z2[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            z2[n] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 b = *(const bf16x8 *)&s.m.W2[(16 * n + r) * kH + 32 * kb + 8 * g];
+                z2[n] = mfma_split(a[kb], b, z2[n]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) z2[n][q] += s.m.b2[16 * n + r];
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float v = silu(z2[n][q]);
+                const __bf16 h = (__bf16)v;
+                tb[(4 * g + q) * kH + 16 * n + r] = h;
+                tb[16 * kH + (4 * g + q) * kH + 16 * n + r] = (__bf16)(v - (float)h);
+            }
+        wave_lds_sync();
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            a[kb].hi = *(const bf16x8 *)&tb[r * kH + 32 * kb + 8 * g];
+            a[kb].lo = *(const bf16x8 *)&tb[16 * kH + r * kH + 32 * kb + 8 * g];
+        }
+        wave_lds_sync();
+        f32x4 z3[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            z3[n] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 b = *(const bf16x8 *)&s.m.W3[(16 * n + r) * kH + 32 * kb + 8 * g];
+                z3[n] = mfma_split(a[kb], b, z3[n]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) z3[n][q] += s.m.b3[16 * n + r];
+        }
+        float sq[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sq[q] = fmaf(s.m.W4[16 * n + r], silu(z3[n][q]), sq[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) sq[q] += __shfl_xor(sq[q], o, 64);
+        // dL/dy of the rows 4g+q (zero for padding samples)
+        float dyq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float tq = __shfl(tgt, 4 * g + q, 64);
+            const bool vq = tile * 16 + 4 * g + q < M;
+            // energy weighting: each sample counts with x / E[x] (E[x] = 8/(15 sqrt3) ...)
+            const float wq = exp2f(tq) * 3.2475953f;
+            dyq[q] = vq ? 2.0f * inv_m * wq * (sq[q] + s.m.b4 - tq) : 0.f;
+        }
+        if (r == 0) gb4 += dyq[0] + dyq[1] + dyq[2] + dyq[3];
+        // ---- layer 4 and 3
+        f32x4 dz3[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const float w4 = s.m.W4[16 * n + r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                gW4[n] = fmaf(dyq[q], silu(z3[n][q]), gW4[n]);
+                dz3[n][q] = dyq[q] * w4 * dsilu(z3[n][q]);
+                gb3[n] += dz3[n][q];
+            }
+        }
+        // h2 in the D layout (the B operand of dW3 = dZ3^T H2)
+        bf16x4 h2b[4], dz3b[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h2b[n][q] = (__bf16)silu(z2[n][q]);
+                dz3b[n][q] = (__bf16)dz3[n][q];
+            }
+#pragma unroll
+        for (int nj = 0; nj < 4; ++nj)
+#pragma unroll
+            for (int nk = 0; nk < 4; ++nk)
+                gW3[nj][nk] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dz3b[nj], h2b[nk], gW3[nj][nk], 0, 0, 0);
+        // dh2 = dZ3 W3: dZ3 to the A layout through LDS, B from W3T
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tb[(4 * g + q) * kH + 16 * n + r] = dz3b[n][q];
+        wave_lds_sync();
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) a[kb].hi = *(const bf16x8 *)&tb[r * kH + 32 * kb + 8 * g];
+        wave_lds_sync();
+        f32x4 dz2[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            dz2[n] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 b = *(const bf16x8 *)&s.W3T[(16 * n + r) * kH + 32 * kb + 8 * g];
+                dz2[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kb].hi, b, dz2[n], 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dz2[n][q] *= dsilu(z2[n][q]);
+                gb2[n] += dz2[n][q];
+            }
+        }
+        // dW2 = dZ2^T H1 with H1 in the D layout
+        bf16x4 h1b[4], dz2b[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h1b[n][q] = (__bf16)silu(z1[n][q]);
+                dz2b[n][q] = (__bf16)dz2[n][q];
+            }
+#pragma unroll
+        for (int nj = 0; nj < 4; ++nj)
+#pragma unroll
+            for (int nk = 0; nk < 4; ++nk)
+                gW2[nj][nk] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dz2b[nj], h1b[nk], gW2[nj][nk], 0, 0, 0);
+        // dh1 = dZ2 W2
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tb[(4 * g + q) * kH + 16 * n + r] = dz2b[n][q];
+        wave_lds_sync();
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) a[kb].hi = *(const bf16x8 *)&tb[r * kH + 32 * kb + 8 * g];
+        wave_lds_sync();
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            f32x4 dh1 = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 b = *(const bf16x8 *)&s.W2T[(16 * n + r) * kH + 32 * kb + 8 * g];
+                dh1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kb].hi, b, dh1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float dz1 = dh1[q] * dsilu(z1[n][q]);
+                gb1[n] += dz1;
+                gW1[n][0] = fmaf(dz1, fq0[q], gW1[n][0]);
+                gW1[n][1] = fmaf(dz1, fq1[q], gW1[n][1]);
+            }
+        }
+    }
+
+    // ---- this wave's gradient -> work[wave_global][kNParams]
+    float *out = work + ((int64_t)blockIdx.x * kWaves + wave) * kNParams;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        float v[6] = {gW1[n][0], gW1[n][1], gb1[n], gb2[n], gb3[n], gW4[n]};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            v[c] += __shfl_xor(v[c], 16, 64);
+            v[c] += __shfl_xor(v[c], 32, 64);
+        }
+        if (g == 0) {
+            const int j = 16 * n + r;
+            out[kOffW1 + 2 * j] = v[0];
+            out[kOffW1 + 2 * j + 1] = v[1];
+            out[kOffB1 + j] = v[2];
+            out[kOffB2 + j] = v[3];
+            out[kOffB3 + j] = v[4];
+            out[kOffW4 + j] = v[5];
+        }
+    }
+    float b4 = gb4;
+    b4 += __shfl_xor(b4, 16, 64);
+    b4 += __shfl_xor(b4, 32, 64);
+    if (l == 0) out[kOffB4] = b4;
+#pragma unroll
+    for (int nj = 0; nj < 4; ++nj)
+#pragma unroll
+        for (int nk = 0; nk < 4; ++nk)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = 16 * nj + 4 * g + q, k = 16 * nk + r;
+                out[kOffW2 + j * kH + k] = gW2[nj][nk][q];
+                out[kOffW3 + j * kH + k] = gW3[nj][nk][q];
+            }
+}
+
+// grads[p] = sum over waves of work[wave][p] (fixed order).
+__global__ void grad_reduce_kernel(const float *__restrict__ work, int nwaves,
+                                   float *__restrict__ grads) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    float sum = 0.f;
+    for (int w = 0; w < nwaves; ++w) sum += work[(int64_t)w * kNParams + p];
+    grads[p] = sum;
+}
+
+__global__ void adam_kernel(float *__restrict__ master, __bf16 *__restrict__ params,
+                            const float *__restrict__ grads, float *__restrict__ m,
+                            float *__restrict__ v, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    const float gr = grads[p];
+    const float mm = b1 * m[p] + (1.f - b1) * gr;
+    const float vv = b2 * v[p] + (1.f - b2) * gr * gr;
+    m[p] = mm;
+    v[p] = vv;
+    const float w = master[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    master[p] = w;
+    params[p] = (__bf16)w;
+}
+
+__global__ void cast_kernel(const float *__restrict__ master, __bf16 *__restrict__ params) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kNParams) params[p] = (__bf16)master[p];
+}
+
+// Training triples: log10 chi uniform on [lo, hi], u a 23-bit midpoint, target
+// log2 x from the tables (x = T1(u r(chi)), r = 1 without the cut), clipped
+// below at x = 1e-5 where photons carry no measurable energy.
+__global__ void make_batch_kernel(TableDev tab, uint32_t k0, uint32_t k1, uint32_t batch,
+                                  int kin_cut, float lo, float hi, float2 *__restrict__ feats,
+                                  float *__restrict__ target, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), batch, 3u), k0, k1);
+    const float lchi = lo + (hi - lo) * ((float)(w.x >> 8) * 0x1p-24f);
+    const float chi = exp2f(lchi * 3.3219280948873623f);
+    const float2 rr = kin_cut ? r_lookup(tab.r, chi) : make_float2(1.0f, 0.0f);
+    float lnU, ln1mU;
+    direct_u(w.y, rr, lnU, ln1mU);
+    const float y = fmaxf(t1_log2x(tab.t1, lnU, ln1mU), kMlpLog2xFloor);
+    feats[i] = make_float2((lchi + 1.0f) * (1.0f / 3.0f), mlp_feature_u(w.y));
+    target[i] = y;
+}
+
+__global__ void eval_direct_kernel(TableDev tab, const uint32_t *__restrict__ a,
+                                   const float *__restrict__ chi, int kin_cut,
+                                   float *__restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 rr = kin_cut ? r_lookup(tab.r, chi[i]) : make_float2(1.0f, 0.0f);
+    float lnU, ln1mU;
+    direct_u(a[i], rr, lnU, ln1mU);
+    out[i] = exp2f(t1_log2x(tab.t1, lnU, ln1mU));
+}
+
+constexpr int kTrainBlocks = 128;
+
+}  // namespace
+}  // namespace sr
+
+using namespace sr;
+
+extern "C" int sr_mlp_forward(const void *params, const float *feats, float *out, int64_t M,
+                              void *stream) {
+    if (!params || M < 0 || (M > 0 && (!feats || !out))) return SR_E_INVAL;
+    if (M == 0) return SR_OK;
+    int64_t tiles = (M + 15) / 16;
+    int64_t blocks = (tiles + kWaves - 1) / kWaves;
+    if (blocks > 4096) blocks = 4096;
+    mlp_forward_kernel<<<(unsigned)blocks, kBlock, 0, (hipStream_t)stream>>>(
+        (const __bf16 *)params, (const float2 *)feats, out, M);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int64_t sr_mlp_grad_work(void) { return (int64_t)kTrainBlocks * kWaves * kNParams; }
+
+extern "C" int sr_mlp_mse_grad(const void *params, const float *feats, const float *target,
+                               int64_t M, float *grads, float *work, void *stream) {
+    if (!params || !grads || !work || M <= 0 || !feats || !target) return SR_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    mlp_train_kernel<<<kTrainBlocks, kBlock, 0, st>>>((const __bf16 *)params, (const float2 *)feats,
+                                                     target, M, 1.0f / (float)M, work);
+    grad_reduce_kernel<<<(kNParams + 255) / 256, 256, 0, st>>>(work, kTrainBlocks * kWaves, grads);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_mlp_adam(float *master, void *params, const float *grads, float *m, float *v,
+                           int64_t t, float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!master || !params || !grads || !m || !v || t < 1) return SR_E_INVAL;
+    const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)t)));
+    const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)t)));
+    adam_kernel<<<(kNParams + 255) / 256, 256, 0, (hipStream_t)stream>>>(
+        master, (__bf16 *)params, grads, m, v, lr, beta1, beta2, eps, c1, c2);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_mlp_cast(const float *master, void *params, void *stream) {
+    if (!master || !params) return SR_E_INVAL;
+    cast_kernel<<<(kNParams + 255) / 256, 256, 0, (hipStream_t)stream>>>(master, (__bf16 *)params);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_mlp_make_batch(const sr_table *tab, uint64_t seed, uint64_t batch,
+                                 int32_t kin_cut, double log10chi_lo, double log10chi_hi,
+                                 float *feats, float *target, int64_t M, void *stream) {
+    if (!tab || M < 0 || (M > 0 && (!feats || !target)) || !(log10chi_hi > log10chi_lo))
+        return SR_E_INVAL;
+    if (M == 0) return SR_OK;
+    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r};
+    make_batch_kernel<<<(unsigned)((M + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+        td, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)batch, kin_cut, (float)log10chi_lo,
+        (float)log10chi_hi, (float2 *)feats, target, M);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_eval_direct(const sr_table *tab, const uint32_t *a, const float *chi,
+                              int32_t kin_cut, float *out_x, int64_t n, void *stream) {
+    if (!tab || n < 0 || (n > 0 && (!a || !chi || !out_x))) return SR_E_INVAL;
+    if (n == 0) return SR_OK;
+    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r};
+    eval_direct_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+        td, a, chi, kin_cut, out_x, n);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}

@@ -15,7 +15,7 @@
 #include <math.h>
 #include <stddef.h>
 
-#include "sr_common.hpp"
+#include "sr_mlp.hpp"
 
 namespace sr {
 namespace {
@@ -49,6 +49,8 @@ struct StepArgs {
     float direct_c;    // dt 5/(2 sqrt3) alpha          (x H r gives the direct rate)
     R ll_c;            // (2/3)(alpha/hbar_n) dt        (x chi^2 beta^2 gives the LL loss)
     TableDev tab;
+    const __bf16 *mlp;              // network parameters (MLP sampler)
+    const uint8_t *mlp_fallback;    // per-chi-bin fallback map (MLP sampler)
     const int64_t *start;
     int64_t n_chunks;
     int64_t per_particle;
@@ -111,12 +113,30 @@ __device__ __forceinline__ const PhotonOut &cold_args() {
     return *(const PhotonOut *)(kp + offsetof(StepArgs<R>, ph));
 }
 
+// LDS of the MLP sampler: the network, and per wave the compacted inputs of
+// the emitted trials and a 16x64 transpose buffer.
+template <int KMAX, int SAMPLER>
+struct alignas(16) StepSmem {
+    MlpSmem m;
+    alignas(16) float2 io[kWaves][64 * KMAX];
+    alignas(16) __bf16 tb[kWaves][2 * 16 * kH];
+};
+template <int KMAX>
+struct StepSmem<KMAX, SR_SAMPLER_S> {};
+template <int KMAX>
+struct StepSmem<KMAX, SR_SAMPLER_TABLE> {};
+
 template <typename R, int DIM, int KMAX, int SAMPLER>
 __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) {
     __shared__ double s_red[kWaves][7];
     __shared__ float s_chi[kWaves];
+    __shared__ StepSmem<KMAX, SAMPLER> sm;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if constexpr (SAMPLER == SR_SAMPLER_MLP) {
+        mlp_load(sm.m, a.mlp, tid, kBlock);
+        __syncthreads();
+    }
     // one chunk per wave, kWaves consecutive chunks per block (blocks mapped so
     // that neighbouring chunks share an XCD)
     const uint32_t blk = (uint32_t)xcd_chunk(blockIdx.x, gridDim.x);
@@ -145,13 +165,16 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
         const bool active = i < e0;
         uint32_t bits = 0;
         float xk[KMAX], fk[KMAX];
-        float eps_unit = 0.0f, wi_f = 0.0f;
+        float eps_unit = 0.0f, wi_f = 0.0f, chif = 0.0f;
         float dirf[3] = {0.0f, 0.0f, 0.0f}, posf[3] = {0.0f, 0.0f, 0.0f};
         uint32_t pid = 0;
+        float2 rr = make_float2(1.0f, 0.0f);
+        // state carried from the push to the recoil
+        R wi = (R)0, pos[3] = {(R)0, (R)0, (R)0}, pn[3] = {(R)0, (R)0, (R)0};
+        R chi = (R)0, gb = (R)1, g_new = (R)1, p2 = (R)0, pbm = (R)0;
         if (active) {
-            const R wi = ld(a.w, i);
+            wi = ld(a.w, i);
             pid = ld(a.id, i);
-            R pos[3] = {(R)0, (R)0, (R)0};
             if (a.has_pos) {
                 pos[0] = ld(a.x[0], i);
                 if (DIM != 0 || a.x[1]) pos[1] = ld(a.x[1], i);
@@ -179,24 +202,26 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             const R d[3] = {(up[1] * sv[2] - up[2] * sv[1]) + (R)2 * h * E[0],
                             (up[2] * sv[0] - up[0] * sv[2]) + (R)2 * h * E[1],
                             (up[0] * sv[1] - up[1] * sv[0]) + (R)2 * h * E[2]};
-            R pn[3] = {p0[0] + d[0], p0[1] + d[1], p0[2] + d[2]};
+            pn[0] = p0[0] + d[0]; pn[1] = p0[1] + d[1]; pn[2] = p0[2] + d[2];
             // ---- H_eff (eq:effective_H) from the mean momentum and d, limited
             const R pb[3] = {p0[0] + (R)0.5 * d[0], p0[1] + (R)0.5 * d[1], p0[2] + (R)0.5 * d[2]};
-            const R p2 = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2];
+            p2 = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2];
             const R cx = diff_of_products(pb[1], d[2], pb[2], d[1]);
             const R cy = diff_of_products(pb[2], d[0], pb[0], d[2]);
             const R cz = diff_of_products(pb[0], d[1], pb[1], d[0]);
             const R c2 = cx * cx + cy * cy + cz * cz;
             const R g_old = sqrt_r<R>((R)1 + p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
-            const R g_new = sqrt_r<R>((R)1 + pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
-            const R gb = (R)0.5 * (g_old + g_new);
-            const R pbm = sqrt_r<R>(p2);
+            g_new = sqrt_r<R>((R)1 + pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+            gb = (R)0.5 * (g_old + g_new);
+            pbm = sqrt_r<R>(p2);
             const R inv_p2 = p2 > (R)0 ? rcp_r<R>(p2) : (R)0;
             R ratio = sqrt_r<R>(c2) * inv_p2;
             if (ratio > (R)1) ratio = (R)1;
             const R H = gb * ratio * a.inv_dt;
-            const R chi = a.hbar_n * H * gb;
-            const float Hf = (float)H, chif = (float)chi, gbf = (float)gb;
+            chi = a.hbar_n * H * gb;
+            const float Hf = (float)H, gbf = (float)gb;
+            chif = (float)chi;
+            if (!isfinite(H)) flags |= SR_W_NONFINITE;
             if (pbm > (R)0) {
                 const R inv = rcp_r<R>(pbm);
                 dirf[0] = (float)(pb[0] * inv); dirf[1] = (float)(pb[1] * inv);
@@ -209,7 +234,6 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
 
             // ---- K trials
             float rate;
-            float2 rr = make_float2(1.0f, 0.0f);
             if (SAMPLER == SR_SAMPLER_S) {
                 rate = a.rate_c * Hf;
             } else {
@@ -218,7 +242,6 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             }
             const float cut15 = a.kin_cut ? 1.5f * chif : 0.0f;
             uint4 words = make_uint4(0, 0, 0, 0);
-            float delta_ph = 0.0f;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
                 xk[k] = 0.0f;
@@ -245,18 +268,80 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                         emit = wb < (uint32_t)(dn * 4294967296.0f);
                     }
                     if (emit) {
-                        if (SAMPLER != SR_SAMPLER_S) {
+                        if (SAMPLER == SR_SAMPLER_TABLE) {
                             float lnU, ln1mU;
                             direct_u(wa, rr, lnU, ln1mU);
                             x = exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                        } else if (SAMPLER == SR_SAMPLER_MLP) {
+                            x = __uint_as_float(wa);       // the word, resolved below
                         }
                         bits |= 1u << k;
                         xk[k] = x;
                         fk[k] = frac;
-                        delta_ph += frac * (eps_unit * x);
                     }
                 }
             }
+        }
+
+        // ---- photon slots: per trial a ballot and the lane prefix (wave-local:
+        // the chunk's segment belongs to this wave alone)
+        uint32_t off[KMAX];
+        uint32_t wave_tot = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            off[k] = 0;
+            if (k < K) {
+                const uint64_t m = __ballot((bits >> k) & 1u);
+                off[k] = wave_tot + lane_prefix(m);
+                wave_tot += (uint32_t)__popcll(m);
+            }
+        }
+
+        if constexpr (SAMPLER == SR_SAMPLER_MLP) {
+            // The network maps (log10 chi, u) of the emitted trials to log2 x, as
+            // dense 16-sample tiles on the matrix cores; trials whose chi falls in
+            // a bin of the fallback map take the table instead.
+            float2 *io = sm.io[wave];
+            const float lchi = (__log2f(fmaxf(chif, 1e-30f)) * 0.30102999566398120f);
+            const float fbin = (lchi - kMlpChiLo) * (kMlpFallbackBins / (kMlpChiHi - kMlpChiLo));
+            const bool use_table = !(fbin >= 0.0f && fbin < (float)kMlpFallbackBins) ||
+                                   a.mlp_fallback[(int)fbin];
+            const float f0 = (lchi + 1.0f) * (1.0f / 3.0f);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < K && ((bits >> k) & 1u)) {
+                    const uint32_t wa = __float_as_uint(xk[k]);
+                    io[off[k]] = make_float2(f0, mlp_feature_u(wa));
+                    if (use_table) {
+                        float lnU, ln1mU;
+                        direct_u(wa, rr, lnU, ln1mU);
+                        xk[k] = exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                    }
+                }
+            }
+            wave_lds_sync();
+            const int r16 = lane & 15;
+            for (uint32_t t0 = 0; t0 < wave_tot; t0 += 16) {
+                const uint32_t e = t0 + r16;
+                const float2 f = e < wave_tot ? io[e] : make_float2(0.0f, 0.0f);
+                const float y = mlp_tile16(sm.m, sm.tb[wave], f.x, f.y);
+                wave_lds_sync();
+                if (lane < 16 && e < wave_tot) io[e].x = y;
+                wave_lds_sync();
+            }
+            if (!use_table) {
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (k < K && ((bits >> k) & 1u)) xk[k] = exp2f(io[off[k]].x);
+            }
+            wave_lds_sync();
+        }
+
+        if (active) {
+            float delta_ph = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < K && ((bits >> k) & 1u)) delta_ph += fk[k] * (eps_unit * xk[k]);
             acc_emit += (double)wi_f * (double)delta_ph;
             // Landau-Lifshitz loss of the step (eq:LLformOfRRForce)
             const R beta2 = p2 * rcp_r<R>(gb * gb);
@@ -283,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 // gamma_after - gamma_before without cancellation
                 acc_de += (double)(-wi * removed * (pm_after + pm) * rcp_r<R>(g_after + g_new));
             }
-            if (!(isfinite(pn[0]) && isfinite(pn[1]) && isfinite(pn[2]) && isfinite(H)))
+            if (!(isfinite(pn[0]) && isfinite(pn[1]) && isfinite(pn[2])))
                 flags |= SR_W_NONFINITE;
             st(a.p[0], i, pn[0]); st(a.p[1], i, pn[1]); st(a.p[2], i, pn[2]);
             // ---- position push
@@ -302,19 +387,6 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             acc_w += wi_f;
         }
 
-        // ---- photon slots: per trial a ballot and the lane prefix (wave-local:
-        // the chunk's segment belongs to this wave alone)
-        uint32_t off[KMAX];
-        uint32_t wave_tot = 0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            off[k] = 0;
-            if (k < K) {
-                const uint64_t m = __ballot((bits >> k) & 1u);
-                off[k] = wave_tot + lane_prefix(m);
-                wave_tot += (uint32_t)__popcll(m);
-            }
-        }
         if (bits) {
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
@@ -481,8 +553,9 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     if (dim != 0 && dim != 2 && dim != 3) return SR_E_INVAL;
     const int K = prm->n_samples;
     if (K < 1 || K > kMaxK) return SR_E_INVAL;
-    if (prm->sampler != SR_SAMPLER_S && prm->sampler != SR_SAMPLER_TABLE)
-        return prm->sampler == SR_SAMPLER_MLP ? SR_E_UNSUPPORTED : SR_E_INVAL;
+    if (prm->sampler < SR_SAMPLER_S || prm->sampler > SR_SAMPLER_MLP) return SR_E_INVAL;
+    if (prm->sampler == SR_SAMPLER_MLP && (!prm->mlp_params || !prm->mlp_fallback))
+        return SR_E_INVAL;
     if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
         return SR_E_INVAL;
     if (!(prm->hbar_n > 0.0) || !(prm->alpha > 0.0)) return SR_E_INVAL;
@@ -557,6 +630,8 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.tab.pa = tab->pa;
     a.tab.t1 = tab->t1;
     a.tab.r = tab->r;
+    a.mlp = (const __bf16 *)prm->mlp_params;
+    a.mlp_fallback = prm->mlp_fallback;
     a.start = chunks->start;
     a.n_chunks = n_chunks;
     a.per_particle = ph->per_particle;
@@ -591,7 +666,8 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
         default: SR_BY_K(3, SMP); break;               \
     }
     if (prm->sampler == SR_SAMPLER_S) { SR_BY_DIM(SR_SAMPLER_S); }
-    else { SR_BY_DIM(SR_SAMPLER_TABLE); }
+    else if (prm->sampler == SR_SAMPLER_TABLE) { SR_BY_DIM(SR_SAMPLER_TABLE); }
+    else { SR_BY_DIM(SR_SAMPLER_MLP); }
 #undef SR_BY_DIM
 #undef SR_BY_K
 #undef SR_LAUNCH

@@ -1,0 +1,205 @@
+"""The MLP surrogate on the GPU: forward and gradients against the FP64
+reference, training on the GPU, the spectrum judge and fallback map, and the
+emission step driven by the network."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as omlp
+from tests import parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1409_5574_amd import api
+    api.lib()
+    return api
+
+
+@pytest.fixture(scope="module")
+def table(sr):
+    t = sr.Table()
+    torch.cuda.synchronize()
+    return t
+
+
+def test_mlp_forward_matches_oracle(sr):
+    flat = omlp.bf16_round(omlp.init(5))
+    net = sr.Mlp(flat.astype(np.float32))
+    rng = np.random.default_rng(2)
+    f = rng.uniform(-1.3, 1.3, (5003, 2)).astype(np.float32)
+    _say("mlp forward 5003")
+    y = net.forward(torch.from_numpy(f)).cpu().numpy().astype(np.float64)
+    ref = omlp.forward(flat, f.astype(np.float64))
+    # activations enter the matrix cores as bfloat16 pairs (~16 bits)
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 1e-3 * scale
+    assert np.corrcoef(y, ref)[0, 1] > 0.9999
+
+
+def test_mlp_gradients_match_oracle(sr):
+    flat = omlp.bf16_round(omlp.init(6))
+    net = sr.Mlp(flat.astype(np.float32))
+    rng = np.random.default_rng(3)
+    M = 4111
+    f = rng.uniform(-1.2, 1.2, (M, 2)).astype(np.float32)
+    t = rng.normal(-2.0, 1.5, M).astype(np.float32)
+    _say("mlp grads 4111")
+    g = net.mse_grad(torch.from_numpy(f).cuda(), torch.from_numpy(t).cuda()).cpu().numpy()
+    _, ref = omlp.mse_grad(flat, f.astype(np.float64), t.astype(np.float64), energy_weight=True)
+    cos = float(g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref)))
+    assert cos > 0.999, cos
+    o = 0
+    for name, shape in omlp.SIZES:
+        k = int(np.prod(shape))
+        gg, rr = g[o:o + k], ref[o:o + k]
+        assert np.abs(gg - rr).max() <= 2e-2 * np.abs(rr).max() + 1e-12, name
+        o += k
+
+
+@pytest.fixture(scope="module")
+def trained(sr, table):
+    net = sr.Mlp(omlp.init(11).astype(np.float32))
+    feats, target = net.make_batch(table, 0xE7A1, 0, 1 << 16)
+    w = torch.exp2(target) / (8.0 / (15.0 * math.sqrt(3.0)))
+    y0 = net.forward(feats)
+    loss0 = float((w * (y0 - target) ** 2).mean())
+    _say("mlp training 4000 x 65536")
+    import time
+    t0 = time.perf_counter()
+    net.train(table, steps=4000, batch=1 << 16, lr=3e-3)
+    torch.cuda.synchronize()
+    print(f"mlp training: {time.perf_counter() - t0:.2f} s for 4000 x 65536 samples", flush=True)
+    torch.cuda.synchronize()
+    y1 = net.forward(feats)
+    loss1 = float((w * (y1 - target) ** 2).mean())
+    _say("mlp judge")
+    err = net.judge(table)
+    print(f"mlp: loss {loss0:.3e} -> {loss1:.3e}; spectrum error per chi bin "
+          f"min {err.min():.2e} median {np.median(err):.2e} max {err.max():.2e}; "
+          f"bins on the table {int((err > 1e-3).sum())}/{err.size}", flush=True)
+    return net, loss0, loss1, err
+
+
+def test_mlp_training_reduces_loss(trained):
+    net, loss0, loss1, err = trained
+    assert loss1 < loss0 / 20
+    assert np.all(np.isfinite(err))
+
+
+def test_step_mlp_sampler_against_oracle(sr, table, oracle, trained):
+    net, _, _, err = trained
+    cfg = synth.config("c1", b0=(0.0, 0.0, 40.0), gamma_range=(1e3, 1e4))
+    n, K, seed, step = 3000, 2, 77, 3
+    st = synth.gen_particles(cfg, n=n)
+    orc = {k: (v.astype(np.float64) if v.dtype != np.uint32 else v.copy()) for k, v in st.items()}
+    orc["x"] = orc["y"] = orc["z"] = None
+    ph_o, led_o, det = oracle.step(orc, oracle.Field(0, b0=cfg.b0), cfg.dt, seed, step,
+                                   hbar_n=cfg.hbar_n, alpha=cfg.alpha, n_samples=K,
+                                   sampler=oracle.SAMPLER_DIRECT, kin_cut=True, push_position=False,
+                                   detail=True)
+    parts = sr.Particles.from_numpy(st, dim=0)
+    parts.x = [None, None, None]
+    photons = sr.PhotonBuffer(n, K, dim=3)
+    ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler=2, kin_cut=True, push_position=False,
+                           mlp=net)
+    _say("step with the MLP sampler")
+    sr.gather_push_emit(parts, None, sr.grid_struct(0, b0=cfg.b0), cfg.dt, seed, step, prm, table,
+                        photons, ledger, 0)
+    torch.cuda.synchronize()
+    ph = photons.gather(n)
+    key_o = ph_o["parent"].astype(np.int64) * K + ph_o["k"]
+    key_g = ph["parent"].astype(np.int64) * K + ph["k"]
+    assert ph_o["eps"].size > 40
+    # decisions use the same cut rate as the table sampler: identical off threshold
+    near = parity.near_threshold(det["dn"], det["bword"])
+    row = np.empty(n, np.int64)
+    row[orc["id"]] = np.arange(n)
+    flips = set(key_o.tolist()) ^ set(key_g.tolist())
+    for kk in flips:
+        assert near[row[kk // K] * K + kk % K]
+    common = np.intersect1d(key_o, key_g)
+    io = np.searchsorted(key_o, common)
+    og = np.argsort(key_g)
+    ig = og[np.searchsorted(key_g[og], common)]
+    x_o = det["xs"][row[ph_o["parent"][io]] * K + ph_o["k"][io]]
+    unit = 1.5 * det["chi"][row[ph_o["parent"][io]]] * det["gamma_bar"][row[ph_o["parent"][io]]]
+    x_g = ph["eps"][ig] / unit
+    lchi = np.log10(det["chi"][row[ph_o["parent"][io]]])
+    b = np.floor((lchi + 4.0) / 0.25).astype(int)
+    on_table = (b < 0) | (b >= 24) | (err[np.clip(b, 0, 23)] > 1e-3)
+    rel = np.abs(x_g / x_o - 1.0)
+    if on_table.any():
+        assert rel[on_table].max() < 1e-4
+    if (~on_table).any():
+        # the network's own accuracy, bounded by the judge that admitted it
+        assert np.median(rel[~on_table]) < 2e-2
+    print(f"mlp step: photons {common.size}, on table {int(on_table.sum())}, network "
+          f"median rel err {np.median(rel[~on_table]) if (~on_table).any() else float('nan'):.2e}",
+          flush=True)
+
+
+def test_step_network_path_matches_standalone_forward(sr, table, oracle, trained):
+    """With the fallback map cleared the emission kernel evaluates the network on
+    the matrix cores for every emitted trial; its x must equal the standalone
+    forward pass of the same network at the same (chi, u)."""
+    net, _, _, err = trained
+    saved = net.fallback.clone()
+    net.fallback.zero_()
+    try:
+        cfg = synth.config("c1", b0=(0.0, 0.0, 40.0), gamma_range=(1e3, 1e4))
+        n, K, seed, step = 5000, 4, 91, 2
+        st = synth.gen_particles(cfg, n=n)
+        orc = {k: (v.astype(np.float64) if v.dtype != np.uint32 else v.copy()) for k, v in st.items()}
+        orc["x"] = orc["y"] = orc["z"] = None
+        _, _, det = oracle.step(orc, oracle.Field(0, b0=cfg.b0), cfg.dt, seed, step, hbar_n=cfg.hbar_n,
+                                alpha=cfg.alpha, n_samples=K, sampler=oracle.SAMPLER_DIRECT,
+                                kin_cut=True, push_position=False, detail=True)
+        parts = sr.Particles.from_numpy(st, dim=0)
+        parts.x = [None, None, None]
+        photons = sr.PhotonBuffer(n, K, dim=3)
+        ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
+        prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler=2, kin_cut=True,
+                               push_position=False, mlp=net)
+        _say("step through the network")
+        sr.gather_push_emit(parts, None, sr.grid_struct(0, b0=cfg.b0), cfg.dt, seed, step, prm,
+                            table, photons, ledger, 0)
+        torch.cuda.synchronize()
+        ph = photons.gather(n)
+        assert ph["eps"].size > 100
+        row = np.empty(n, np.int64)
+        row[orc["id"]] = np.arange(n)
+        r = row[ph["parent"]]
+        s = r * K + ph["k"].astype(np.int64)
+        chi, gb = det["chi"][r], det["gamma_bar"][r]
+        x_gpu = ph["eps"] / (1.5 * chi * gb)
+        u = det["rp"][s]
+        feats = np.stack([(np.log10(chi) + 1.0) / 3.0, (np.log(u) - np.log1p(-u)) / 16.0],
+                         1).astype(np.float32)
+        y = net.forward(torch.from_numpy(feats)).cpu().numpy().astype(np.float64)
+        rel = np.abs(x_gpu / np.exp2(y) - 1.0)
+        # chi enters through binary32 on both sides; x is smooth in chi
+        assert np.quantile(rel, 0.99) < 1e-4, rel.max()
+        # and the network's samples agree with the exact inverse CDF as well as
+        # the judge said they would
+        x_exact = det["xs"][s]
+        print(f"network path: {x_gpu.size} photons, median |x/x_exact - 1| "
+              f"{np.median(np.abs(x_gpu / x_exact - 1)):.2e}", flush=True)
+    finally:
+        net.fallback.copy_(saved)
