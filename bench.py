@@ -95,20 +95,6 @@ def run(args):
     parts, alt = alt, parts
     torch.cuda.synchronize()
 
-    # ---------------- spectrum check: step 0 from the initial state, kept for the CPU leg
-    check = None
-    if not args.no_cpu_baseline:
-        probe = parts.empty_like()
-        for a, b in zip(probe.x + probe.p + [probe.w, probe.id], parts.x + parts.p + [parts.w, parts.id]):
-            if a is not None:
-                a.copy_(b)
-        api.gather_push_emit(probe, fields, grid, cfg.dt, seed, 0, prm, table, photons, ledger, 0)
-        torch.cuda.synchronize()
-        ph = photons.gather(n)
-        sel = ph["parent"] < args.cpu_sample
-        check = {"eps": ph["eps"][sel], "w": ph["w"][sel], "count": int(sel.sum())}
-        del probe
-
     structs = {id(parts): api.make_structs(parts, fields, photons, ledger),
                id(alt): api.make_structs(alt, fields, photons, ledger)}
     stream = torch.cuda.current_stream()
@@ -141,6 +127,32 @@ def run(args):
     for i in range(1, args.warmup + 1):
         one_step(i)
     torch.cuda.synchronize()
+
+    # ---------------- spectrum check, kept for the CPU leg: the first timed step
+    # (index warmup+1) run once on a copy of the warm state, its photons of the
+    # sampled ids, and those particles' state before the step
+    check = None
+    if not args.no_cpu_baseline:
+        i_chk = args.warmup + 1
+        api.standing_wave(fields, grid, cfg.a0, i_chk * cfg.dt)
+        probe = parts.empty_like()
+        for a, b in zip(probe.x + probe.p + [probe.w, probe.id], parts.x + parts.p + [parts.w, parts.id]):
+            if a is not None:
+                a.copy_(b)
+        sel = torch.nonzero(parts.id.view(torch.int32) < args.cpu_sample).squeeze(1)
+        order = torch.argsort(parts.id.view(torch.int32)[sel])
+        sel = sel[order]
+        state = {k: (t[sel].cpu().numpy() if t is not None else None)
+                 for k, t in zip(("x", "y", "z", "px", "py", "pz", "w"), parts.x + parts.p + [parts.w])}
+        state["id"] = parts.id[sel].cpu().numpy().view(np.uint32)
+        api.gather_push_emit(probe, fields, grid, cfg.dt, seed, i_chk, prm, table, photons, ledger, 0)
+        torch.cuda.synchronize()
+        ph = photons.gather(n)
+        keep = ph["parent"] < args.cpu_sample
+        check = {"eps": ph["eps"][keep], "w": ph["w"][keep], "count": int(keep.sum()),
+                 "state": state, "step": i_chk}
+        del probe, sel, order
+        torch.cuda.synchronize()
     hist.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,18 +207,128 @@ def run(args):
         "status_bits": int(status),
     }
     if check is not None:
-        out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, st0, check, seed, args)
+        out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, check, seed, args)
+    if not args.no_samplers:
+        del parts, alt, photons, fields, sort_work
+        torch.cuda.empty_cache()
+        out["samplers"] = samplers_leg(args)
     return out
 
 
-def cpu_leg(cfg, st0, check, seed, args):
-    """The FP64 oracle on the first `cpu_sample` ids: timed for about
-    --cpu-seconds, and compared on step 0 with the GPU's photons of those ids."""
+def samplers_leg(args):
+    """Plain vs surrogate: the 3D K=8 workload (512^3 grid, a0 = 500, 16M
+    electrons in a 2-lambda slab, kinematic cut) run from the same sorted
+    initial state with each sampler for --sampler-steps steps:
+      s_proposal      the S(x) proposal with the tabulated F (the paper's scheme),
+      table_direct    cut-rate decision + tabulated inverse number-CDF,
+      mlp_direct      the same decisions, x from the network where the judge
+                      admitted it and from the table elsewhere,
+      mlp_network     the same with every emitted trial through the network.
+    Each run's energy spectrum (accumulated over its steps) is compared with the
+    table_direct run's; s_proposal draws other random numbers, so its error is
+    the Monte-Carlo noise floor of that comparison."""
+    import torch
+
+    from paper_1409_5574_amd import api
+    from paper_1409_5574_amd import _lib as L
+
+    cfg = synth.config("c3")
+    n, K, dim = cfg.n_particles, cfg.n_samples, 3
+    grid = api.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
+    ncells = int(np.prod(cfg.grid))
+    tile = (16, 4, 4)
+    table = api.Table()
+
+    t0 = time.perf_counter()
+    net = api.Mlp(api.mlp_init(11))
+    net.train(table, steps=args.mlp_steps, batch=1 << 16, lr=2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    err = net.judge(table, kin_cut=cfg.kin_cut)
+    judged = net.fallback.clone()
+
+    st0 = synth.gen_particles(cfg)
+    init = api.Particles.from_numpy(st0, dim=dim)
+    del st0
+    parts = init.empty_like()
+    fields = api.Fields(ncells=ncells)
+    sw = api.sort_work(grid, tile, n)
+    api.standing_wave(fields, grid, cfg.a0, 0.0)
+    api.sort_particles(init, parts, grid, tile, sw)
+    init, parts = parts, init
+    del sw
+    photons = api.PhotonBuffer(n, cfg.photons_per_particle, dim=dim)
+    n_chunks = api.n_chunks_uniform(n)
+    steps = args.sampler_steps
+    ledger = api.LedgerBuf(steps, n_chunks)
+    hwork = api.hist_work(SPEC_BINS)
+    stream = torch.cuda.current_stream()
+    seed = 0x5A3B1E
+    variants = [("s_proposal", 0, None), ("table_direct", 1, None),
+                ("mlp_direct", 2, judged), ("mlp_network", 2, torch.zeros_like(judged))]
+    res, hists = {}, {}
+    for name, sampler, fb in variants:
+        if fb is not None:
+            net.fallback.copy_(fb)
+        prm = api.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, cfg.recoil, 0, cfg.kin_cut,
+                                True, mlp=net if sampler == 2 else None)
+        for a, b in zip(parts.x + parts.p + [parts.w, parts.id], init.x + init.p + [init.w, init.id]):
+            a.copy_(b)
+        ledger.rows.zero_()
+        hist = torch.zeros(2 * SPEC_BINS, device="cuda", dtype=torch.float64)
+        structs = api.make_structs(parts, fields, photons, ledger)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(steps):
+            api.standing_wave(fields, grid, cfg.a0, i * cfg.dt)
+            ev[i][0].record(stream)
+            api.gather_push_emit(parts, fields, grid, cfg.dt, seed, i, prm, table, photons,
+                                 ledger, None, structs=structs)
+            ev[i][1].record(stream)
+            api.ledger_reduce(ledger, n_chunks, i, structs[4])
+            api.spectrum_histogram(photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist, hwork)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        k_ms = np.array([a.elapsed_time(b) for a, b in ev])[1:]
+        rows = ledger.rows.cpu().numpy()
+        hists[name] = hist[:SPEC_BINS].cpu().numpy()
+        res[name] = {"particle_steps_per_s": n / (float(k_ms.mean()) * 1e-3),
+                     "kernel_ms": float(k_ms.mean()),
+                     "step_ms": wall * 1e3 / steps,
+                     "photons_per_step": float(rows[:, L.SR_LED_PHOTONS].mean()),
+                     "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300))}
+    ref = hists["table_direct"]
+    for name in res:
+        res[name]["spectrum_error_vs_table_direct"] = float(
+            np.abs(hists[name] - ref).sum() / max(ref.sum(), 1e-300))
+    base = res["s_proposal"]["particle_steps_per_s"]
+    for name in res:
+        res[name]["speedup_vs_s_proposal"] = res[name]["particle_steps_per_s"] / base
+    net_bins = err <= 1e-3
+    return {"workload": f"{cfg.name}: 512^3 Yee grid, standing wave a0={cfg.a0:g}, {n} electrons "
+                        f"in a 2-lambda slab, K={K}, kinematic cut, {steps} steps per sampler",
+            "results": res,
+            "mlp": {"train_steps": args.mlp_steps, "train_batch": 1 << 16, "train_s": train_s,
+                    "bins_on_network": int(net_bins.sum()), "bins": int(err.size),
+                    "judge_error_max_on_network": float(err[net_bins].max()) if net_bins.any()
+                    else None,
+                    "judge_error_median": float(np.median(err))},
+            "spectrum": f"{SPEC_BINS} log bins of photon energy in [{SPEC_LO:g}, {SPEC_HI:g}] mc^2, "
+                        f"energy-weighted, summed over the steps"}
+
+
+def cpu_leg(cfg, check, seed, args):
+    """The FP64 oracle on the first `cpu_sample` ids, started from their warm GPU
+    state before the first timed step: compared on that step with the GPU's
+    photons of those ids, then timed for about --cpu-seconds of further steps."""
     from oracle import oracle as O
 
     m = args.cpu_sample
-    sub = {k: (v[:m].astype(np.float64) if v.dtype != np.uint32 else v[:m].copy())
-           for k, v in st0.items()}
+    i0 = check["step"]
+    sub = {k: (None if v is None else (v.astype(np.float64) if v.dtype != np.uint32 else v.copy()))
+           for k, v in check["state"].items()}
     if cfg.dim == 2:
         sub["z"] = None
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -217,17 +339,17 @@ def cpu_leg(cfg, st0, check, seed, args):
         E, B = synth.standing_wave_grid(cfg, i * cfg.dt)
         return O.Field(cfg.dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
 
-    f0 = field_at_step(0)
+    f0 = field_at_step(i0)
     t0 = time.perf_counter()
-    ph0, led0, _ = O.step(sub, f0, cfg.dt, seed, 0, **kw)
+    ph0, led0, _ = O.step(sub, f0, cfg.dt, seed, i0, **kw)
     spent = time.perf_counter() - t0
     steps = 1
     per_step = spent
     target = max(args.cpu_seconds, per_step)
     while spent + per_step <= target and steps < 10000:
-        f = field_at_step(steps)
+        f = field_at_step(i0 + steps)
         t0 = time.perf_counter()
-        O.step(sub, f, cfg.dt, seed, steps, **kw)
+        O.step(sub, f, cfg.dt, seed, i0 + steps, **kw)
         spent += time.perf_counter() - t0
         steps += 1
     edges = np.geomspace(SPEC_LO, SPEC_HI, SPEC_BINS + 1)
@@ -236,9 +358,10 @@ def cpu_leg(cfg, st0, check, seed, args):
     err = float(np.abs(h_g - h_o).sum() / max(h_o.sum(), 1e-300))
     base = {"value": m * steps / spent, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{m} of the {cfg.n_particles} electrons (ids 0..{m - 1}), {steps} steps, "
-                      f"same grid and fields; FP64 C oracle with OpenMP, {spent:.1f} s"}
-    spec = {"step": 0, "particles": m, "photons_gpu": check["count"],
+            "sample": f"{m} of the {cfg.n_particles} electrons (ids 0..{m - 1}) from the warm "
+                      f"state at step {i0}, {steps} steps, same grid and fields; FP64 C oracle "
+                      f"with OpenMP, {spent:.1f} s"}
+    spec = {"step": i0, "particles": m, "photons_gpu": check["count"],
             "photons_oracle": int(ph0["eps"].size), "energy_spectrum_error": err,
             "bins": f"{SPEC_BINS} log bins of photon energy in [{SPEC_LO:g}, {SPEC_HI:g}] mc^2"}
     return base, spec
@@ -255,6 +378,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-samplers", action="store_true",
+                    help="skip the plain-vs-surrogate sampler comparison on the 3D K=8 workload")
+    ap.add_argument("--sampler-steps", type=int, default=12)
+    ap.add_argument("--mlp-steps", type=int, default=30000)
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
     args = ap.parse_args()

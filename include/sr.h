@@ -106,7 +106,9 @@ typedef struct {
 
 /* Grid.  dim 0: uniform fields e0, b0 (no grid, positions not wrapped);
  * dim 2: n[2] == 1, positions x, y; dim 3: x, y, z.  Periodic in every axis;
- * the lower corner is the origin of the positions. */
+ * the lower corner is the origin of the positions.  The emission step needs
+ * n[0] >= 2 (SR_E_INVAL otherwise), fewer than 2^24 rows n[1] n[2] and fewer
+ * than 2^30 cells (SR_E_UNSUPPORTED otherwise). */
 typedef struct {
     int32_t dim;
     int32_t reserved;
@@ -188,8 +190,11 @@ typedef struct sr_table sr_table;
 
 /* Build the device tables (the "spectrum-table construction" of the FP64 split):
  *  - the synchrotron function F(x) = x int_x^inf K_{5/3} (section "Modelling
- *    the relativistic case"), as piecewise cubics in log2 x for the proposal
- *    sampler of section "Monte Carlo method";
+ *    the relativistic case"), as piecewise cubics in log2 x;
+ *  - the trial density F(x)/(x S(x)) of the proposal sampler of section "Monte
+ *    Carlo method" as piecewise cubics of its logarithm in log2 R' (lower
+ *    branch) and log2(1 - R') (upper branch), so that a trial reads it directly
+ *    from the uniform R';
  *  - the branch point P(a) of the proposal S(x), a^{4/3} + (7/9)e^{-a} = 1;
  *  - the inverse CDF of the photon-number spectrum F(x)/x with the optional
  *    kinematic cut, on a (log chi, u) grid, and the cut rate integral, for the
@@ -207,17 +212,18 @@ typedef struct {
     int32_t t1_pieces;      /* cubic pieces of the uncut inverse number-CDF        */
     int32_t r_nodes;        /* nodes of the cut fraction r(chi)                     */
     double r_log10chi_lo, r_log10chi_hi;
+    int32_t g_pieces;       /* cubic pieces of the trial density log2 F/(x S) in R' */
 } sr_table_info;
 int sr_table_query(const sr_table *tab, sr_table_info *info);
 
-/* Evaluate the table's F at n device points x (device out).  The same device
- * function the emission kernel uses. */
+/* Evaluate the table's F at n device points x (device out). */
 int sr_eval_synchrotron_F(const sr_table *tab, const float *x, float *out, int64_t n, void *stream);
 
 /* dN of one proposal trial for n device (uniform word a, rate, chi) triples:
  * out_dn = rate F(x)/(x S(x)) (0 above the cut when kin_cut), out_x = x.
- * The same device function the emission kernel uses (steps 3-5 of the list at
- * the end of section "Monte Carlo method"). */
+ * The same device functions the emission kernel uses (steps 3-5 of the list at
+ * the end of section "Monte Carlo method"): F/(x S) is read from a table of
+ * log2 F/(x S) built in FP64 as a function of R' itself. */
 int sr_eval_trial(const sr_table *tab, const uint32_t *a, const float *rate, const float *chi,
                   int32_t kin_cut, float *out_dn, float *out_x, int64_t n, void *stream);
 

@@ -69,7 +69,7 @@ class Ledger(C.Structure):
 class TableInfo(C.Structure):
     _fields_ = [("proposal_pa", C.c_float), ("f_pieces", C.c_int32), ("proposal_a", C.c_double),
                 ("t1_pieces", C.c_int32), ("r_nodes", C.c_int32), ("r_log10chi_lo", C.c_double),
-                ("r_log10chi_hi", C.c_double)]
+                ("r_log10chi_hi", C.c_double), ("g_pieces", C.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol include/sr.h declares

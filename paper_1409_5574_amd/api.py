@@ -284,6 +284,21 @@ def eval_direct(table: Table, a: torch.Tensor, chi: torch.Tensor, kin_cut: bool)
     return out
 
 
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial FP32 parameters in the flat sr_mlp layout (W1[64][2], b1, W2[64][64],
+    b2, W3[64][64], b3, W4[64], b4): normal weights with variance 2/fan_in
+    (1/fan_in for the linear output layer), zero biases."""
+    rng = np.random.default_rng(seed)
+    h = 64
+    parts = [rng.normal(0.0, 1.0, h * 2), np.zeros(h),
+             rng.normal(0.0, np.sqrt(2.0 / h), h * h), np.zeros(h),
+             rng.normal(0.0, np.sqrt(2.0 / h), h * h), np.zeros(h),
+             rng.normal(0.0, np.sqrt(1.0 / h), h), np.zeros(1)]
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == L.SR_MLP_PARAMS
+    return flat
+
+
 class Mlp:
     """The MLP surrogate: FP32 master weights, Adam moments and the bfloat16
     copy the kernels read, all on the device."""

@@ -69,11 +69,25 @@ constexpr double kRLogChiLo = -6.0;     // below: r = 1 to binary32 precision
 constexpr double kRLogChiHi = 4.0;      // above: r ~ chi^{-1/3} (small-x form of N)
 constexpr int kRN = (int)((kRLogChiHi - kRLogChiLo) * kRPerDecade) + 1;
 
+// Trial-density table of the proposal, for the emission kernel: the density
+// q = F(x)/(x S(x)) of one trial as a function of the uniform R' itself, so a
+// trial costs one logarithm, one cubic and one exponential.  Cubic pieces of
+// log2 q with 32 pieces per unit of the argument:
+//   lower family (R' <= P(a)):  argument u = log2 R',       x = 2^{3u/4}
+//   upper family:               argument v = -log2(1 - R'), x = v ln2 - ln(9/7)
+constexpr int kGPerUnit = 32;
+constexpr int kGLoJ0 = -768;    // u from -24 (R' = 2^-24) ...
+constexpr int kGLoN = 768;      // ... to 0
+constexpr int kGUpJ0 = 32;      // v from 1 ...
+constexpr int kGUpN = 736;      // ... to 24 (1 - R' = 2^-24)
+constexpr int kGTotal = kGLoN + kGUpN;
+
 struct TableDev {
     const float4 *ftab;     // [kFTotal]
     float pa;               // binary32 branch point P(a)
     const float4 *t1;       // [kT1N]
     const float2 *r;        // [kRN] (r, 1 - r)
+    const float4 *gtab;     // [kGTotal]
 };
 
 // ---------------------------------------------------------------------------
@@ -108,31 +122,54 @@ __device__ __forceinline__ float ftab_eval(const float4 *__restrict__ tab, float
     return fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
 }
 
-// One Monte-Carlo trial with the proposal S(x) (steps 3-5 of the recipe at the
-// end of section "Monte Carlo method").  `a` is the uniform word for R' (23-bit
-// midpoint, never 0 or 1).  Returns dN = rate F(x)/(x S(x)) and writes x.
-//   lower branch (R' <= P(a)):  x = R'^{3/4},  x S = (4/3) R'
-//   upper branch:               x = -ln((9/7)(1-R')),  S = 1 - R' = (7/9) e^{-x}
-__device__ __forceinline__ float trial_dn(uint32_t a, float rate, const float4 *__restrict__ tab,
-                                          float pa, float &x) {
+// One trial with the proposal S(x), through the trial-density table: returns
+// q = F(x)/(x S(x)) at the R' of word a (a 23-bit midpoint, never 0 or 1), and
+// lg = log2 R' on the lower branch or log2(1 - R') on the upper one, from which
+// trial_x gives x.  dN = rate q (the dN of the recipe at the end of section
+// "Monte Carlo method", per unit x).
+__device__ __forceinline__ float trial_q(uint32_t a, const float4 *__restrict__ gtab, float pa,
+                                         float &lg, bool &lower) {
     const float rp = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
-    float q;
-    if (rp <= pa) {
-        const float s = sqrtf(rp);
-        x = s * sqrtf(s);
-        const float t = 0.75f * __log2f(rp);
-        const float L = ftab_eval(tab, t, kFLoJ0, kFLoN, 0);
-        // F/(x S) = (3/4) (F / x^{1/3}) / x
-        q = 0.75f * exp2f(L) * __builtin_amdgcn_rcpf(x);
-    } else {
-        const float om = 1.0f - rp;          // exact
-        x = -0.69314718055994531f * __log2f(om) - 0.25131442828090605f;  // -ln om - ln(9/7)
-        const float t = __log2f(x);
-        const float L = ftab_eval(tab, t, kFUpJ0, kFUpN, kFLoN);
-        // F/(x S) = (9/7) F e^{x} / x = (9/7) 2^{L} x^{-2/3}
-        q = 1.2857142857142857f * exp2f(L - 0.66666666666666667f * t);
+    lower = rp <= pa;
+    lg = __builtin_amdgcn_logf(lower ? rp : 1.0f - rp);   // 1 - rp is exact
+    const float u = (lower ? lg : -lg) * (float)kGPerUnit;
+    const int j0 = lower ? kGLoJ0 : kGUpJ0;
+    int j = (int)floorf(u) - j0;
+    j = min(max(j, 0), (lower ? kGLoN : kGUpN) - 1);
+    const float s = u - (float)(j + j0);
+    const float4 c = gtab[(lower ? 0 : kGLoN) + j];
+    return __builtin_amdgcn_exp2f(fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x));
+}
+
+// x of a trial (word a, trial_q's lg): R'^{3/4} as sqrt(R') sqrt(sqrt(R'))
+// (a few ulp, where 2^{3 lg/4} would lose ~1e-6 to the rounding of lg), or
+// -ln((9/7)(1 - R')).
+__device__ __forceinline__ float trial_x(uint32_t a, float lg, bool lower) {
+    if (lower) {
+        const float rp = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
+        const float s = __builtin_amdgcn_sqrtf(rp);
+        return s * __builtin_amdgcn_sqrtf(s);
     }
-    return rate * q;
+    return fmaf(-0.69314718055994531f, lg, -0.25131442828090605f);
+}
+
+// Kinematic cut x > xc = 2/(3 chi) expressed on lg: on the lower branch
+// lg > (4/3) log2 xc, on the upper one lg < -(xc + ln(9/7))/ln2.  Without the
+// cut (or chi = 0) nothing is cut.
+struct TrialCut {
+    float lo, hi;
+};
+__device__ __forceinline__ TrialCut trial_cut(bool on, float chi) {
+    TrialCut c{__builtin_inff(), -__builtin_inff()};
+    if (on && chi > 0.0f) {
+        const float xc = __builtin_amdgcn_rcpf(1.5f * chi);
+        c.lo = -1.3333333333333333f * __builtin_amdgcn_logf(1.5f * chi);
+        c.hi = -(xc + 0.25131442828090605f) * 1.4426950408889634f;
+    }
+    return c;
+}
+__device__ __forceinline__ bool trial_is_cut(const TrialCut &c, float lg, bool lower) {
+    return lower ? lg > c.lo : lg < c.hi;
 }
 
 // r(chi) and 1 - r(chi), linear in log10 chi; r ~ chi^{-1/3} above the table.
@@ -236,33 +273,67 @@ __device__ __forceinline__ void axis_setup(double x, double inv, int n, Axis<dou
     ax.f1 = f1;
 }
 
+// Two consecutive grid values of a row from one 8-byte load (4-byte aligned).
+typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+__device__ __forceinline__ float2 ld2(const float *base, uint32_t i) {
+    const f32x2_a4 v = *(const f32x2_a4 *)((const char *)base + i * 4u);
+    return make_float2(v.x, v.y);
+}
+
+// The two x-neighbours (ix, ix+1 periodic) of every row of a component, read
+// as pairs: rows need nx >= 2; the pair starts at min(ix, nx-2), and the lanes
+// at ix = nx-1 (whose right neighbour wraps to 0) fix theirs up with one more
+// load, issued only when some lane of the wave wraps.
+struct XPair {
+    uint32_t start;   // first element of the loaded pair
+    bool wrap;        // ix == nx - 1
+    bool any_wrap;    // some lane of the wave wraps (wave-uniform)
+};
+__device__ __forceinline__ XPair x_pair(uint32_t ix, int nx) {
+    XPair p;
+    p.wrap = ix == (uint32_t)(nx - 1);
+    p.start = p.wrap ? (uint32_t)(nx - 2) : ix;
+    p.any_wrap = __ballot(p.wrap) != 0;
+    return p;
+}
+template <typename R>
+__device__ __forceinline__ R row_lerp(const float *__restrict__ a, uint32_t row, const XPair &p,
+                                      R gx, R fx) {
+    const float2 v = ld2(a, row + p.start);
+    float lo = v.x, hi = v.y;
+    if (p.any_wrap && p.wrap) {
+        lo = v.y;
+        hi = ld(a, row);
+    }
+    return gx * (R)lo + fx * (R)hi;
+}
+
 // Bilinear (2D) / trilinear (3D) interpolation of one component.  sx, sy, sz
-// select offset 0 (false) or 1/2 (true) on each axis.
+// select offset 0 (false) or 1/2 (true) on each axis; P0 / P1 are the x pairs
+// of the two offsets.
 template <typename R, int DIM>
 __device__ __forceinline__ R cic(const float *__restrict__ a, const Axis<R> &X, const Axis<R> &Y,
-                                 const Axis<R> &Z, bool sx, bool sy, bool sz, int nx, int ny) {
-    const uint32_t ix0 = sx ? X.i1 : X.i0, ix1 = sx ? X.i1p : X.i0p;
+                                 const Axis<R> &Z, const XPair &P0, const XPair &P1, bool sx,
+                                 bool sy, bool sz, int nx, int ny) {
+    const XPair &P = sx ? P1 : P0;
     const R fx = sx ? X.f1 : X.f0;
     const uint32_t iy0 = sy ? Y.i1 : Y.i0, iy1 = sy ? Y.i1p : Y.i0p;
     const R fy = sy ? Y.f1 : Y.f0;
     const R gx = (R)1 - fx, gy = (R)1 - fy;
     if (DIM == 2) {
-        const uint32_t r0 = iy0 * (uint32_t)nx, r1 = iy1 * (uint32_t)nx;
-        const R v00 = (R)ld(a, r0 + ix0), v01 = (R)ld(a, r0 + ix1);
-        const R v10 = (R)ld(a, r1 + ix0), v11 = (R)ld(a, r1 + ix1);
-        return gy * (gx * v00 + fx * v01) + fy * (gx * v10 + fx * v11);
+        const uint32_t r0 = __umul24(iy0, (uint32_t)nx), r1 = __umul24(iy1, (uint32_t)nx);
+        return gy * row_lerp<R>(a, r0, P, gx, fx) + fy * row_lerp<R>(a, r1, P, gx, fx);
     } else {
         const uint32_t iz0 = sz ? Z.i1 : Z.i0, iz1 = sz ? Z.i1p : Z.i0p;
         const R fz = sz ? Z.f1 : Z.f0;
         const R gz = (R)1 - fz;
-        const uint32_t p00 = (iz0 * (uint32_t)ny + iy0) * (uint32_t)nx;
-        const uint32_t p01 = (iz0 * (uint32_t)ny + iy1) * (uint32_t)nx;
-        const uint32_t p10 = (iz1 * (uint32_t)ny + iy0) * (uint32_t)nx;
-        const uint32_t p11 = (iz1 * (uint32_t)ny + iy1) * (uint32_t)nx;
-        const R c00 = gx * (R)ld(a, p00 + ix0) + fx * (R)ld(a, p00 + ix1);
-        const R c01 = gx * (R)ld(a, p01 + ix0) + fx * (R)ld(a, p01 + ix1);
-        const R c10 = gx * (R)ld(a, p10 + ix0) + fx * (R)ld(a, p10 + ix1);
-        const R c11 = gx * (R)ld(a, p11 + ix0) + fx * (R)ld(a, p11 + ix1);
+        // rows (ny nz) and nx below 2^24, cells below 2^30: the 24-bit
+        // products are exact
+        const uint32_t z0 = __umul24(iz0, (uint32_t)ny), z1 = __umul24(iz1, (uint32_t)ny);
+        const uint32_t p00 = __umul24(z0 + iy0, (uint32_t)nx), p01 = __umul24(z0 + iy1, (uint32_t)nx);
+        const uint32_t p10 = __umul24(z1 + iy0, (uint32_t)nx), p11 = __umul24(z1 + iy1, (uint32_t)nx);
+        const R c00 = row_lerp<R>(a, p00, P, gx, fx), c01 = row_lerp<R>(a, p01, P, gx, fx);
+        const R c10 = row_lerp<R>(a, p10, P, gx, fx), c11 = row_lerp<R>(a, p11, P, gx, fx);
         return gz * (gy * c00 + fy * c01) + fz * (gy * c10 + fy * c11);
     }
 }
@@ -309,6 +380,7 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t G) {
 // Host-side table object.
 struct sr_table {
     float4 *ftab = nullptr;
+    float4 *gtab = nullptr;
     float4 *t1 = nullptr;
     float2 *r = nullptr;
     float pa = 0.0f;

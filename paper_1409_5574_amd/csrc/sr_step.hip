@@ -77,13 +77,14 @@ __device__ __forceinline__ void gather_grid(const StepArgs<R> &a, const R pos[3]
     if (DIM == 3) setup_axis<R>(a.g, 2, pos[2], Z);
     else Z = Y;
     const int nx = a.g.n[0], ny = a.g.n[1];
+    const XPair P0 = x_pair(X.i0, nx), P1 = x_pair(X.i1, nx);
     // Yee offsets: Ex(1/2,0,0) Ey(0,1/2,0) Ez(0,0,1/2) Bx(0,1/2,1/2) By(1/2,0,1/2) Bz(1/2,1/2,0)
-    E[0] = cic<R, DIM>(a.f[0], X, Y, Z, true, false, false, nx, ny);
-    E[1] = cic<R, DIM>(a.f[1], X, Y, Z, false, true, false, nx, ny);
-    E[2] = cic<R, DIM>(a.f[2], X, Y, Z, false, false, true, nx, ny);
-    B[0] = cic<R, DIM>(a.f[3], X, Y, Z, false, true, true, nx, ny);
-    B[1] = cic<R, DIM>(a.f[4], X, Y, Z, true, false, true, nx, ny);
-    B[2] = cic<R, DIM>(a.f[5], X, Y, Z, true, true, false, nx, ny);
+    E[0] = cic<R, DIM>(a.f[0], X, Y, Z, P0, P1, true, false, false, nx, ny);
+    E[1] = cic<R, DIM>(a.f[1], X, Y, Z, P0, P1, false, true, false, nx, ny);
+    E[2] = cic<R, DIM>(a.f[2], X, Y, Z, P0, P1, false, false, true, nx, ny);
+    B[0] = cic<R, DIM>(a.f[3], X, Y, Z, P0, P1, false, true, true, nx, ny);
+    B[1] = cic<R, DIM>(a.f[4], X, Y, Z, P0, P1, true, false, true, nx, ny);
+    B[2] = cic<R, DIM>(a.f[5], X, Y, Z, P0, P1, true, true, false, nx, ny);
 }
 
 template <typename R> __device__ __forceinline__ R box_len(const GridK &g, int q);
@@ -113,23 +114,58 @@ __device__ __forceinline__ const PhotonOut &cold_args() {
     return *(const PhotonOut *)(kp + offsetof(StepArgs<R>, ph));
 }
 
-// LDS of the MLP sampler: the network, and per wave the compacted inputs of
-// the emitted trials and a 16x64 transpose buffer.
+// One photon record into slot o of the buffer (section "The field setup":
+// photons become particles; direction along the emitter's mean momentum).
+__device__ __forceinline__ void store_photon(const PhotonOut &P, uint32_t o, float eps, float w,
+                                             const float dir[3], const float pos[3], uint32_t pid,
+                                             uint32_t k, uint32_t step) {
+    st(P.eps, o, eps);
+    st(P.w, o, w);
+    st(P.dir[0], o, dir[0]);
+    st(P.dir[1], o, dir[1]);
+    st(P.dir[2], o, dir[2]);
+    if (P.pos[0]) st(P.pos[0], o, pos[0]);
+    if (P.pos[1]) st(P.pos[1], o, pos[1]);
+    if (P.pos[2]) st(P.pos[2], o, pos[2]);
+    st(P.parent, o, pid);
+    if (P.k) st(P.k, o, (uint8_t)k);
+    if (P.step) st(P.step, o, step);
+}
+
+// LDS of the end-of-kernel ledger reduction: every thread's sums.
+struct LedgerSmem {
+    double d[5][kBlock];
+    float f[2][kBlock];
+    uint32_t cnt[kWaves];
+};
+
+// LDS of the kernel.  With the MLP sampler: the network, and per wave the
+// compacted inputs of the emitted trials and a 16x64 transpose buffer, which
+// the ledger reduction reuses after the last round.
 template <int KMAX, int SAMPLER>
 struct alignas(16) StepSmem {
-    MlpSmem m;
-    alignas(16) float2 io[kWaves][64 * KMAX];
-    alignas(16) __bf16 tb[kWaves][2 * 16 * kH];
+    union {
+        struct {
+            MlpSmem m;
+            alignas(16) float2 io[kWaves][64 * KMAX];
+            alignas(16) __bf16 tb[kWaves][2 * 16 * kH];
+        };
+        LedgerSmem led;
+    };
 };
 template <int KMAX>
-struct StepSmem<KMAX, SR_SAMPLER_S> {};
+struct StepSmem<KMAX, SR_SAMPLER_S> {
+    LedgerSmem led;
+};
 template <int KMAX>
-struct StepSmem<KMAX, SR_SAMPLER_TABLE> {};
+struct StepSmem<KMAX, SR_SAMPLER_TABLE> {
+    LedgerSmem led;
+};
+template <typename S>
+__device__ __forceinline__ LedgerSmem &ledger_smem(S &s) { return s.led; }
 
 template <typename R, int DIM, int KMAX, int SAMPLER>
 __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) {
-    __shared__ double s_red[kWaves][7];
-    __shared__ float s_chi[kWaves];
     __shared__ StepSmem<KMAX, SAMPLER> sm;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -163,12 +199,9 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
     for (uint32_t base = s0; base < e0; base += kChunk) {
         const uint32_t i = base + lane;
         const bool active = i < e0;
-        uint32_t bits = 0;
-        float xk[KMAX], fk[KMAX];
-        float eps_unit = 0.0f, wi_f = 0.0f, chif = 0.0f;
+        float eps_unit = 0.0f, wi_f = 0.0f, chif = 0.0f, Hf = 0.0f;
         float dirf[3] = {0.0f, 0.0f, 0.0f}, posf[3] = {0.0f, 0.0f, 0.0f};
         uint32_t pid = 0;
-        float2 rr = make_float2(1.0f, 0.0f);
         // state carried from the push to the recoil
         R wi = (R)0, pos[3] = {(R)0, (R)0, (R)0}, pn[3] = {(R)0, (R)0, (R)0};
         R chi = (R)0, gb = (R)1, g_new = (R)1, p2 = (R)0, pbm = (R)0;
@@ -219,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             if (ratio > (R)1) ratio = (R)1;
             const R H = gb * ratio * a.inv_dt;
             chi = a.hbar_n * H * gb;
-            const float Hf = (float)H, gbf = (float)gb;
+            Hf = (float)H;
             chif = (float)chi;
             if (!isfinite(H)) flags |= SR_W_NONFINITE;
             if (pbm > (R)0) {
@@ -229,119 +262,159 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             }
             posf[0] = (float)pos[0]; posf[1] = (float)pos[1]; posf[2] = (float)pos[2];
             chi_max = fmaxf(chi_max, chif);
-            eps_unit = 1.5f * chif * gbf;          // hbar omega_c: photon energy per unit x
+            eps_unit = 1.5f * chif * (float)gb;    // hbar omega_c: photon energy per unit x
             wi_f = (float)wi;
+        }
 
-            // ---- K trials
-            float rate;
-            if (SAMPLER == SR_SAMPLER_S) {
-                rate = a.rate_c * Hf;
-            } else {
-                if (a.kin_cut) rr = r_lookup(a.tab.r, chif);
-                rate = a.direct_c * Hf * rr.x;      // total (cut) photon rate per trial
-            }
-            const float cut15 = a.kin_cut ? 1.5f * chif : 0.0f;
+        // ---- K trials.  Inactive lanes take part in the wave-wide steps with a
+        // zero rate, so they never emit.  Photon slots: per trial a ballot and the
+        // lane prefix (mbcnt); the chunk's segment belongs to this wave alone.
+        float delta_ph = 0.0f;                 // sum over trials of frac * eps
+        uint32_t wave_tot = 0;
+        float2 rr = make_float2(1.0f, 0.0f);
+        if (SAMPLER != SR_SAMPLER_S && active && a.kin_cut) rr = r_lookup(a.tab.r, chif);
+        const float rate = !active ? 0.0f
+                         : (SAMPLER == SR_SAMPLER_S ? a.rate_c * Hf : a.direct_c * Hf * rr.x);
+        if constexpr (SAMPLER != SR_SAMPLER_MLP) {
+            const TrialCut cut = trial_cut(SAMPLER == SR_SAMPLER_S && a.kin_cut != 0, chif);
             uint4 words = make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                xk[k] = 0.0f;
-                fk[k] = 0.0f;
-                if (k < K) {
-                    if ((k & 1) == 0)
-                        words = philox4x32_10(make_uint4(pid, a.step, (uint32_t)(k >> 1), 0u),
-                                              a.seed_lo, a.seed_hi);
-                    const uint32_t wa = (k & 1) ? words.z : words.x;
-                    const uint32_t wb = (k & 1) ? words.w : words.y;
-                    float x = 0.0f, dn;
-                    if (SAMPLER == SR_SAMPLER_S) {
-                        dn = trial_dn(wa, rate, a.tab.ftab, a.tab.pa, x);
-                        if (cut15 * x > 1.0f) dn = 0.0f;
-                    } else {
-                        dn = rate;
-                    }
-                    bool emit;
-                    float frac = invK;
-                    if (dn >= 1.0f) {
-                        emit = true;
-                        if (a.dn_policy == SR_DN_WEIGHT) frac = dn * invK;
-                    } else {
-                        emit = wb < (uint32_t)(dn * 4294967296.0f);
-                    }
+                if (k >= K) break;
+                if ((k & 1) == 0)
+                    words = philox4x32_10(make_uint4(pid, a.step, (uint32_t)(k >> 1), 0u),
+                                          a.seed_lo, a.seed_hi);
+                const uint32_t wa = (k & 1) ? words.z : words.x;
+                const uint32_t wb = (k & 1) ? words.w : words.y;
+                float dn = rate, lg = 0.0f;
+                bool lower = true;
+                if (SAMPLER == SR_SAMPLER_S) {
+                    dn = rate * trial_q(wa, a.tab.gtab, a.tab.pa, lg, lower);
+                    if (trial_is_cut(cut, lg, lower)) dn = 0.0f;
+                }
+                bool emit;
+                float frac = invK;
+                if (dn >= 1.0f) {
+                    emit = true;
+                    if (a.dn_policy == SR_DN_WEIGHT) frac = dn * invK;
+                } else {
+                    emit = wb < (uint32_t)(dn * 4294967296.0f);
+                }
+                const uint64_t m = __ballot(emit);
+                if (m) {
                     if (emit) {
-                        if (SAMPLER == SR_SAMPLER_TABLE) {
+                        float x;
+                        if (SAMPLER == SR_SAMPLER_S) {
+                            x = trial_x(wa, lg, lower);
+                        } else {
                             float lnU, ln1mU;
                             direct_u(wa, rr, lnU, ln1mU);
-                            x = exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
-                        } else if (SAMPLER == SR_SAMPLER_MLP) {
-                            x = __uint_as_float(wa);       // the word, resolved below
+                            x = __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
                         }
-                        bits |= 1u << k;
-                        xk[k] = x;
-                        fk[k] = frac;
+                        const float eps = eps_unit * x;
+                        const float wph = wi_f * frac;
+                        delta_ph += frac * eps;
+                        const uint32_t slot = run_base + wave_tot + lane_prefix(m);
+                        if (slot < seg_cap) {
+                            store_photon(cold_args<R>(), seg_base + slot, eps, wph, dirf, posf, pid,
+                                         (uint32_t)k, a.step);
+                        } else {
+                            acc_drop += (double)wph * (double)eps;
+                            flags |= SR_W_PHOTON_OVERFLOW;
+                        }
                     }
+                    wave_tot += (uint32_t)__popcll(m);
                 }
             }
-        }
-
-        // ---- photon slots: per trial a ballot and the lane prefix (wave-local:
-        // the chunk's segment belongs to this wave alone)
-        uint32_t off[KMAX];
-        uint32_t wave_tot = 0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            off[k] = 0;
-            if (k < K) {
-                const uint64_t m = __ballot((bits >> k) & 1u);
-                off[k] = wave_tot + lane_prefix(m);
-                wave_tot += (uint32_t)__popcll(m);
-            }
-        }
-
-        if constexpr (SAMPLER == SR_SAMPLER_MLP) {
-            // The network maps (log10 chi, u) of the emitted trials to log2 x, as
-            // dense 16-sample tiles on the matrix cores; trials whose chi falls in
-            // a bin of the fallback map take the table instead.
+        } else {
+            // Learned sampler: decisions with the cut rate as for the table; x of
+            // the emitted trials from the network, as dense 16-sample tiles on the
+            // matrix cores over the wave's compacted trials, except where chi falls
+            // in a bin of the fallback map (table instead).
             float2 *io = sm.io[wave];
             const float lchi = (__log2f(fmaxf(chif, 1e-30f)) * 0.30102999566398120f);
             const float fbin = (lchi - kMlpChiLo) * (kMlpFallbackBins / (kMlpChiHi - kMlpChiLo));
-            const bool use_table = !(fbin >= 0.0f && fbin < (float)kMlpFallbackBins) ||
+            const bool use_table = !active || !(fbin >= 0.0f && fbin < (float)kMlpFallbackBins) ||
                                    a.mlp_fallback[(int)fbin];
             const float f0 = (lchi + 1.0f) * (1.0f / 3.0f);
+            uint32_t bits = 0, net_tot = 0;
+            float xk[KMAX], fk[KMAX];
+            uint32_t off[KMAX], net_off[KMAX];
+            uint4 words = make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                if (k < K && ((bits >> k) & 1u)) {
-                    const uint32_t wa = __float_as_uint(xk[k]);
-                    io[off[k]] = make_float2(f0, mlp_feature_u(wa));
+                xk[k] = 0.0f; fk[k] = 0.0f; off[k] = 0; net_off[k] = 0;
+                if (k >= K) continue;
+                if ((k & 1) == 0)
+                    words = philox4x32_10(make_uint4(pid, a.step, (uint32_t)(k >> 1), 0u),
+                                          a.seed_lo, a.seed_hi);
+                const uint32_t wa = (k & 1) ? words.z : words.x;
+                const uint32_t wb = (k & 1) ? words.w : words.y;
+                const float dn = rate;
+                bool emit;
+                float frac = invK;
+                if (dn >= 1.0f) {
+                    emit = true;
+                    if (a.dn_policy == SR_DN_WEIGHT) frac = dn * invK;
+                } else {
+                    emit = wb < (uint32_t)(dn * 4294967296.0f);
+                }
+                const uint64_t m = __ballot(emit);
+                off[k] = wave_tot + lane_prefix(m);
+                wave_tot += (uint32_t)__popcll(m);
+                const uint64_t mn = __ballot(emit && !use_table);
+                net_off[k] = net_tot + lane_prefix(mn);
+                net_tot += (uint32_t)__popcll(mn);
+                if (emit) {
+                    bits |= 1u << k;
+                    fk[k] = frac;
                     if (use_table) {
                         float lnU, ln1mU;
                         direct_u(wa, rr, lnU, ln1mU);
-                        xk[k] = exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                        xk[k] = __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                    } else {
+                        io[net_off[k]] = make_float2(f0, mlp_feature_u(wa));
                     }
                 }
             }
-            wave_lds_sync();
-            const int r16 = lane & 15;
-            for (uint32_t t0 = 0; t0 < wave_tot; t0 += 16) {
-                const uint32_t e = t0 + r16;
-                const float2 f = e < wave_tot ? io[e] : make_float2(0.0f, 0.0f);
-                const float y = mlp_tile16(sm.m, sm.tb[wave], f.x, f.y);
+            if (net_tot) {
                 wave_lds_sync();
-                if (lane < 16 && e < wave_tot) io[e].x = y;
-                wave_lds_sync();
-            }
-            if (!use_table) {
+                const int r16 = lane & 15;
+                for (uint32_t t0 = 0; t0 < net_tot; t0 += 16) {
+                    const uint32_t e = t0 + r16;
+                    const float2 f = e < net_tot ? io[e] : make_float2(0.0f, 0.0f);
+                    const float y = mlp_tile16(sm.m, sm.tb[wave], f.x, f.y);
+                    wave_lds_sync();
+                    if (lane < 16 && e < net_tot) io[e].x = y;
+                    wave_lds_sync();
+                }
+                if (!use_table) {
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (k < K && ((bits >> k) & 1u)) xk[k] = exp2f(io[off[k]].x);
+                    for (int k = 0; k < KMAX; ++k)
+                        if (k < K && ((bits >> k) & 1u))
+                            xk[k] = __builtin_amdgcn_exp2f(io[net_off[k]].x);
+                }
+                wave_lds_sync();
             }
-            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < K && ((bits >> k) & 1u)) {
+                    const float eps = eps_unit * xk[k];
+                    const float wph = wi_f * fk[k];
+                    delta_ph += fk[k] * eps;
+                    const uint32_t slot = run_base + off[k];
+                    if (slot < seg_cap) {
+                        store_photon(cold_args<R>(), seg_base + slot, eps, wph, dirf, posf, pid,
+                                     (uint32_t)k, a.step);
+                    } else {
+                        acc_drop += (double)wph * (double)eps;
+                        flags |= SR_W_PHOTON_OVERFLOW;
+                    }
+                }
+            }
         }
 
         if (active) {
-            float delta_ph = 0.0f;
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < K && ((bits >> k) & 1u)) delta_ph += fk[k] * (eps_unit * xk[k]);
             acc_emit += (double)wi_f * (double)delta_ph;
             // Landau-Lifshitz loss of the step (eq:LLformOfRRForce)
             const R beta2 = p2 * rcp_r<R>(gb * gb);
@@ -386,56 +459,11 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             }
             acc_w += wi_f;
         }
-
-        if (bits) {
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (k < K && ((bits >> k) & 1u)) {
-                    const uint32_t slot = run_base + off[k];
-                    const float eps = eps_unit * xk[k];
-                    const float wph = wi_f * fk[k];
-                    if (slot < seg_cap) {
-                        const uint32_t o = seg_base + slot;
-                        const PhotonOut &P = cold_args<R>();
-                        st(P.eps, o, eps);
-                        st(P.w, o, wph);
-                        st(P.dir[0], o, dirf[0]);
-                        st(P.dir[1], o, dirf[1]);
-                        st(P.dir[2], o, dirf[2]);
-                        if (P.pos[0]) st(P.pos[0], o, posf[0]);
-                        if (P.pos[1]) st(P.pos[1], o, posf[1]);
-                        if (P.pos[2]) st(P.pos[2], o, posf[2]);
-                        st(P.parent, o, pid);
-                        if (P.k) st(P.k, o, (uint8_t)k);
-                        if (P.step) st(P.step, o, a.step);
-                    } else {
-                        acc_drop += (double)wph * (double)eps;
-                        flags |= SR_W_PHOTON_OVERFLOW;
-                    }
-                }
-            }
-        }
         run_base += wave_tot;
     }
 
     if (have && lane == 0) cold_args<R>().seg_count[c] = run_base;
 
-    // ---- per-block ledger partial (FP64, fixed reduction order).  Clamped and
-    // dropped energy are rare: reduced only when some lane of the wave has them.
-    double v[7];
-    v[0] = wave_sum(acc_emit);
-    v[1] = wave_sum(acc_ll);
-    v[2] = __ballot(acc_de != 0.0) ? wave_sum(acc_de) : 0.0;
-    v[3] = __ballot(acc_clamp != 0.0) ? wave_sum(acc_clamp) : 0.0;
-    v[4] = __ballot(acc_drop != 0.0) ? wave_sum(acc_drop) : 0.0;
-    v[5] = (double)run_base;
-    v[6] = (double)wave_sum_f(acc_w);
-    const float cm = wave_max(chi_max);
-    if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 7; ++q) s_red[wave][q] = v[q];
-        s_chi[wave] = cm;
-    }
     // latch device-side conditions.  Same-address atomics serialise across the
     // whole device, so a wave only issues one when its bits are not yet set.
     if (__ballot(flags != 0)) {
@@ -447,18 +475,48 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             if ((__atomic_load_n(status, __ATOMIC_RELAXED) & wf) != wf) atomicOr(status, wf);
         }
     }
+
+    // ---- per-block ledger partial (FP64, fixed reduction order).  The lanes'
+    // sums go to LDS; then each wave reduces its share of the columns over the
+    // whole block (four values per lane, then one wave reduction), so the block
+    // pays for each column's wave reduction once.  Clamped and dropped energy
+    // are rare: reduced only when some lane has them.
+    if constexpr (SAMPLER == SR_SAMPLER_MLP) __syncthreads();   // LDS shared with the sampler
+    LedgerSmem &rs = ledger_smem(sm);
+    rs.d[0][tid] = acc_emit;
+    rs.d[1][tid] = acc_ll;
+    rs.d[2][tid] = acc_de;
+    rs.d[3][tid] = acc_clamp;
+    rs.d[4][tid] = acc_drop;
+    rs.f[0][tid] = acc_w;
+    rs.f[1][tid] = chi_max;
+    if (lane == 0) rs.cnt[wave] = run_base;
     __syncthreads();
-    if (tid < 8) {
-        double r;
-        if (tid < 7) {
-            r = s_red[0][tid];
-            for (int wv = 1; wv < kWaves; ++wv) r += s_red[wv][tid];
-        } else {
-            float m = s_chi[0];
-            for (int wv = 1; wv < kWaves; ++wv) m = fmaxf(m, s_chi[wv]);
-            r = (double)m;
+    double *row = cold_args<R>().partials + (size_t)blk * SR_LEDGER_COLS;
+    const auto dsum = [&](int q) {
+        const double v = ((rs.d[q][lane] + rs.d[q][lane + 64]) + rs.d[q][lane + 128]) +
+                         rs.d[q][lane + 192];
+        return __ballot(v != 0.0) ? wave_sum(v) : 0.0;
+    };
+    if (wave == 0) {
+        const double e = dsum(0), dr = dsum(4);
+        if (lane == 0) { row[SR_LED_EMITTED] = e; row[SR_LED_DROPPED] = dr; }
+    } else if (wave == 1) {
+        const double l = dsum(1);
+        const float m = wave_max(fmaxf(fmaxf(rs.f[1][lane], rs.f[1][lane + 64]),
+                                       fmaxf(rs.f[1][lane + 128], rs.f[1][lane + 192])));
+        if (lane == 0) { row[SR_LED_LL] = l; row[SR_LED_CHI_MAX] = (double)m; }
+    } else if (wave == 2) {
+        const double de = dsum(2);
+        const float w = wave_sum_f(((rs.f[0][lane] + rs.f[0][lane + 64]) + rs.f[0][lane + 128]) +
+                                   rs.f[0][lane + 192]);
+        if (lane == 0) { row[SR_LED_RECOIL] = de; row[SR_LED_WEIGHT] = (double)w; }
+    } else {
+        const double cl = dsum(3);
+        if (lane == 0) {
+            row[SR_LED_CLAMPED] = cl;
+            row[SR_LED_PHOTONS] = (double)((rs.cnt[0] + rs.cnt[1]) + (rs.cnt[2] + rs.cnt[3]));
         }
-        cold_args<R>().partials[(size_t)blk * SR_LEDGER_COLS + tid] = r;
     }
 }
 
@@ -580,6 +638,8 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
         if (!parts->x[0] || !parts->x[1] || (dim == 3 && !parts->x[2])) return SR_E_INVAL;
         for (int q = 0; q < dim; ++q)
             if (grid->n[q] < 1 || grid->n[q] > (1 << 24) || !(grid->dx[q] > 0.0)) return SR_E_INVAL;
+        if (grid->n[0] < 2) return SR_E_INVAL;   // rows are read as pairs
+        if (grid->n[1] * (dim == 3 ? grid->n[2] : 1) >= ((int64_t)1 << 24)) return SR_E_UNSUPPORTED;
         if (dim == 2 && grid->n[2] != 1) return SR_E_INVAL;
         const int64_t cells = grid->n[0] * grid->n[1] * (dim == 3 ? grid->n[2] : 1);
         if (cells <= 0) return SR_E_INVAL;
@@ -630,6 +690,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.tab.pa = tab->pa;
     a.tab.t1 = tab->t1;
     a.tab.r = tab->r;
+    a.tab.gtab = tab->gtab;
     a.mlp = (const __bf16 *)prm->mlp_params;
     a.mlp_fallback = prm->mlp_fallback;
     a.start = chunks->start;

@@ -90,6 +90,39 @@ __global__ void build_f_table(float4 *out) {
     out[p] = hermite_piece(y0, d0, y1, d1, h);
 }
 
+// Node of the trial-density table: y = log2 q, q = F(x)/(x S(x)), and dy/darg.
+//   lower (arg u = log2 R', x = 2^{3u/4}, x S = (4/3) R'):
+//       y = log2(3/4) + log2 F - u,           dy/du = (3/4)(1 - x^2 K/F) - 1
+//   upper (arg v = -log2(1-R'), x = v ln2 - ln(9/7), S = 1 - R' = 2^{-v}):
+//       y = log2 F - log2 x + v,              dy/dv = 1 - x K/F
+// (x F'/F = 1 - x^2 K_{5/3}/F as above).
+__device__ void g_node(double arg, bool upper, double &y, double &dy) {
+    double x, F, K;
+    if (!upper) {
+        x = exp2(0.75 * arg);
+        synch_FK(x, F, K);
+        y = log2(0.75) + log2(F) - arg;
+        dy = 0.75 * (1.0 - x * x * K / F) - 1.0;
+    } else {
+        x = arg * 0.69314718055994531 - log(9.0 / 7.0);
+        synch_FK(x, F, K);
+        y = log2(F) - log2(x) + arg;
+        dy = 1.0 - x * K / F;
+    }
+}
+
+__global__ void build_g_table(float4 *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kGTotal) return;
+    const bool upper = p >= kGLoN;
+    const int j = upper ? (p - kGLoN + kGUpJ0) : (p + kGLoJ0);
+    const double h = 1.0 / kGPerUnit;
+    double y0, d0, y1, d1;
+    g_node(j * h, upper, y0, d0);
+    g_node((j + 1) * h, upper, y1, d1);
+    out[p] = hermite_piece(y0, d0, y1, d1, h);
+}
+
 // x with N(x) = U N(inf), given U and 1-U (both accurate); bisection in log2 x.
 __device__ double inv_number(double one_minus_u) {
     const double target = one_minus_u * kNInf;   // = Ntail(x)
@@ -166,17 +199,18 @@ __global__ void eval_F_kernel(const float4 *__restrict__ tab, const float *__res
     }
 }
 
-__global__ void eval_trial_kernel(const float4 *__restrict__ tab, float pa,
+__global__ void eval_trial_kernel(const float4 *__restrict__ gtab, float pa,
                                   const uint32_t *__restrict__ a, const float *__restrict__ rate,
                                   const float *__restrict__ chi, int kin_cut,
                                   float *__restrict__ dn, float *__restrict__ xo, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float x;
-    float d = trial_dn(a[i], rate[i], tab, pa, x);
-    if (kin_cut && 1.5f * chi[i] * x > 1.0f) d = 0.0f;
+    float lg;
+    bool lower;
+    float d = rate[i] * trial_q(a[i], gtab, pa, lg, lower);
+    if (trial_is_cut(trial_cut(kin_cut != 0, chi[i]), lg, lower)) d = 0.0f;
     dn[i] = d;
-    xo[i] = x;
+    xo[i] = trial_x(a[i], lg, lower);
 }
 
 __global__ void philox_kernel(const uint4 *__restrict__ ctr, uint32_t k0, uint32_t k1,
@@ -200,6 +234,7 @@ extern "C" int sr_table_build(sr_table **out, void *stream) {
     double *aux = nullptr;
     auto fail = [&](int code) {
         if (t->ftab) (void)hipFree(t->ftab);
+        if (t->gtab) (void)hipFree(t->gtab);
         if (t->t1) (void)hipFree(t->t1);
         if (t->r) (void)hipFree(t->r);
         if (aux) (void)hipFree(aux);
@@ -208,10 +243,12 @@ extern "C" int sr_table_build(sr_table **out, void *stream) {
     };
     if (hipGetDevice(&t->device) != hipSuccess) return fail(SR_E_HIP);
     if (hipMalloc(&t->ftab, sizeof(float4) * kFTotal) != hipSuccess) return fail(SR_E_NOMEM);
+    if (hipMalloc(&t->gtab, sizeof(float4) * kGTotal) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&t->t1, sizeof(float4) * kT1N) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&t->r, sizeof(float2) * kRN) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&aux, sizeof(double) * 2) != hipSuccess) return fail(SR_E_NOMEM);
     build_f_table<<<(kFTotal + 63) / 64, 64, 0, st>>>(t->ftab);
+    build_g_table<<<(kGTotal + 63) / 64, 64, 0, st>>>(t->gtab);
     build_t1_table<<<(kT1N + 63) / 64, 64, 0, st>>>(t->t1);
     build_r_table<<<(kRN + 63) / 64, 64, 0, st>>>(t->r);
     solve_proposal<<<1, 64, 0, st>>>(aux);
@@ -231,6 +268,7 @@ extern "C" int sr_table_build(sr_table **out, void *stream) {
 extern "C" void sr_table_free(sr_table *t) {
     if (!t) return;
     if (t->ftab) (void)hipFree(t->ftab);
+    if (t->gtab) (void)hipFree(t->gtab);
     if (t->t1) (void)hipFree(t->t1);
     if (t->r) (void)hipFree(t->r);
     delete t;
@@ -240,6 +278,7 @@ extern "C" int sr_table_query(const sr_table *t, sr_table_info *info) {
     if (!t || !info) return SR_E_INVAL;
     info->proposal_pa = t->pa;
     info->f_pieces = kFTotal;
+    info->g_pieces = kGTotal;
     info->proposal_a = t->a;
     info->t1_pieces = kT1N;
     info->r_nodes = kRN;
@@ -263,7 +302,7 @@ extern "C" int sr_eval_trial(const sr_table *t, const uint32_t *a, const float *
     if (!t || n < 0 || (n > 0 && (!a || !rate || !chi || !out_dn || !out_x))) return SR_E_INVAL;
     if (n == 0) return SR_OK;
     eval_trial_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-        t->ftab, t->pa, a, rate, chi, kin_cut, out_dn, out_x, n);
+        t->gtab, t->pa, a, rate, chi, kin_cut, out_dn, out_x, n);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }
