@@ -7,10 +7,13 @@ A step is one pass of the whole hot path over the particle ensemble:
   gather + Boris + H_eff + Monte-Carlo emission + photon append + recoil +
   position push (sr_gather_push_emit), the FP64 energy ledger reduction, and
   the photon-spectrum histogram that drains the photon buffer.
-`value` is particle-steps/s over the timed steps (wall clock between device
-synchronisations).  The emission kernel is also timed alone with HIP events on
-the stream it runs on, for the roofline figure.  The CPU baseline is the FP64
-oracle on a bounded sample of the same workload.
+The K timed steps run twice from the same warm state: once as eager launches,
+with HIP events around every emission-kernel launch on its stream (the
+roofline figure), and once captured into a HIP graph and run as one graph
+launch.  `value` is particle-steps/s of the graph pass (wall clock between
+device synchronisations; --no-graph reports the eager pass); both passes are
+in `timing`.  The CPU baseline is the FP64 oracle on a bounded sample of the
+same workload.
 
 Prints one JSON line.
 """
@@ -34,6 +37,45 @@ import synth  # noqa: E402
 METRIC = "particle-steps/s with emission (plain vs surrogate) at ≤1e-3 spectrum error"
 HBM_PEAK_GBS = 8000.0
 SPEC_BINS, SPEC_LO, SPEC_HI = 64, 1e-8, 1e5
+
+
+# HBM traffic of the emission kernel from hardware counters: a summary under
+# profiles/ records FETCH_SIZE and WRITE_SIZE per dispatch (scaled by a plain
+# copy of known size) together with a digest of the sources the kernel is built
+# from.  The figure is reported only while those sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_emit_c2_traffic.md")
+KERNEL_SOURCES = ["paper_1409_5574_amd/csrc/sr_step.hip", "paper_1409_5574_amd/csrc/sr_common.hpp",
+                  "paper_1409_5574_amd/csrc/sr_mlp.hpp", "include/sr.h",
+                  "paper_1409_5574_amd/build.py"]
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """Bytes per launch from the committed counter summary, or None when there
+    is none or the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources_sha256") != kernel_sources_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def photon_bytes(dim: int) -> int:
@@ -153,17 +195,54 @@ def run(args):
                  "state": state, "step": i_chk}
         del probe, sel, order
         torch.cuda.synchronize()
+    # the warm state, restored before the graph pass so that both timed passes
+    # run the same K steps from the same particles
+    snap_bufs = (parts, alt)
+    snap = [None if t is None else t.clone() for t in parts.x + parts.p + [parts.w, parts.id]]
+
+    # ---------------- timed pass 1, eager launches: HIP events around every
+    # emission-kernel launch (the roofline) and every field refresh
     hist.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for j in range(args.steps):
         one_step(args.warmup + 1 + j, j)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall_eager = time.perf_counter() - t0
+    wall = wall_eager
+
+    # ---------------- timed pass 2: the next K steps captured once into a HIP
+    # graph (the same kernels and arguments the eager loop launches, without
+    # the per-launch host overhead) and run as one graph launch
+    graph_info = None
+    rows = ledger.rows.cpu().numpy()[args.warmup + 1: args.warmup + 1 + args.steps]
+    if not args.no_graph:
+        parts, alt = snap_bufs
+        for dst, src in zip(parts.x + parts.p + [parts.w, parts.id], snap):
+            if dst is not None:
+                dst.copy_(src)
+        base = args.warmup + 1
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=cap):
+            for j in range(args.steps):
+                one_step(base + j)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rows_g = ledger.rows.cpu().numpy()[base: base + args.steps]
+        graph_info = {"steps": [base, base + args.steps - 1], "ms_per_step": wall * 1e3 / args.steps,
+                      "photons_per_step": float(rows_g[:, L.SR_LED_PHOTONS].mean()),
+                      "ledger_rel_diff_vs_eager": float(np.max(np.abs(rows_g - rows) /
+                                                               np.maximum(np.abs(rows), 1e-300)))}
+        del g
+    del snap
 
     k1_ms = np.array([a.elapsed_time(b) for a, b in ev])
     k9_ms = np.array([a.elapsed_time(b) for a, b in ev_wave])
-    rows = ledger.rows.cpu().numpy()[args.warmup + 1: args.warmup + 1 + args.steps]
     status = ledger.read_status()
     photons_per_step = rows[:, L.SR_LED_PHOTONS].mean()
     rd, wr = particle_bytes(dim)
@@ -196,7 +275,8 @@ def run(args):
                    "particles": n, "grid": list(cfg.grid[:dim]), "trials_per_step": K,
                    "dt": cfg.dt, "sort_every": args.sort_every, "tile": list(tile[:dim])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic() if args.config == "c2" else None,
                      "kernel": "push_emit_kernel<float,%d,%d,0>" % (dim, 1 if K <= 1 else K),
                      "kernel_ms": k1_mean, "algorithmic_bytes_per_launch": bytes_per_launch},
         "push_emit_particle_steps_per_s": n / (k1_mean * 1e-3),
@@ -205,6 +285,14 @@ def run(args):
         "ledger_emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300)),
         "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
         "status_bits": int(status),
+        "timing": {"value_from": "hip_graph" if graph_info else "eager",
+                   "eager": {"value": n * args.steps / wall_eager,
+                             "ms_per_step": wall_eager * 1e3 / args.steps,
+                             "steps": [args.warmup + 1, args.warmup + args.steps]},
+                   "note": "both passes run the same K steps from the same warm state",
+                   "hip_graph": graph_info,
+                   "kernel_ms_from": "HIP events around each emission-kernel launch of the "
+                                     "eager pass, on its stream"},
     }
     if check is not None:
         out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, check, seed, args)
@@ -378,6 +466,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="report the eager-launch pass as the value (no HIP-graph pass)")
     ap.add_argument("--no-samplers", action="store_true",
                     help="skip the plain-vs-surrogate sampler comparison on the 3D K=8 workload")
     ap.add_argument("--sampler-steps", type=int, default=12)

@@ -312,8 +312,12 @@ int64_t sr_sort_work(const sr_grid *grid, const int32_t tile[3], int64_t n);
 /* out[i] = network(feats[i]) for M samples; feats device [M][2], out device [M]. */
 int sr_mlp_forward(const void *params_bf16, const float *feats, float *out, int64_t M,
                    void *stream);
-/* grads = gradient of (1/M) sum (network(feats[i]) - target[i])^2 (device FP32
- * [SR_MLP_PARAMS]); work: device FP32 workspace of sr_mlp_grad_work() floats. */
+/* grads = gradient of the energy-weighted squared error
+ *   (1/M) sum_i w_i (network(feats[i]) - target[i])^2,  w_i = 2^target[i] / E[x],
+ * E[x] = 8/(15 sqrt 3) the mean x of the photon-number spectrum (targets are
+ * log2 x, so w_i is the sample's share of the radiated energy), as device FP32
+ * [SR_MLP_PARAMS]; work: device FP32 workspace of sr_mlp_grad_work() floats.
+ * The sum is taken in a fixed order (reproducible). */
 int sr_mlp_mse_grad(const void *params_bf16, const float *feats, const float *target, int64_t M,
                     float *grads, float *work, void *stream);
 int64_t sr_mlp_grad_work(void);

@@ -292,13 +292,17 @@ __global__ __launch_bounds__(kBlock) void mlp_train_kernel(const __bf16 *__restr
 }
 
 // grads[p] = sum over waves of work[wave][p] (fixed order).
-__global__ void grad_reduce_kernel(const float *__restrict__ work, int nwaves,
-                                   float *__restrict__ grads) {
+// Sum of the per-wave gradient rows, in two fixed-order stages: blockIdx.y
+// sums rows [y * per, (y + 1) * per) into out row y.
+__global__ void grad_reduce_kernel(const float *__restrict__ work, int nrows, int per,
+                                   float *__restrict__ out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kNParams) return;
+    const int r0 = blockIdx.y * per, r1 = min(r0 + per, nrows);
     float sum = 0.f;
-    for (int w = 0; w < nwaves; ++w) sum += work[(int64_t)w * kNParams + p];
-    grads[p] = sum;
+#pragma unroll 8
+    for (int w = r0; w < r1; ++w) sum += work[(int64_t)w * kNParams + p];
+    out[(int64_t)blockIdx.y * kNParams + p] = sum;
 }
 
 __global__ void adam_kernel(float *__restrict__ master, __bf16 *__restrict__ params,
@@ -352,7 +356,8 @@ __global__ void eval_direct_kernel(TableDev tab, const uint32_t *__restrict__ a,
     out[i] = exp2f(t1_log2x(tab.t1, lnU, ln1mU));
 }
 
-constexpr int kTrainBlocks = 128;
+constexpr int kTrainBlocks = 256;      // one block (four waves, one per SIMD) per CU
+constexpr int kGradGroups = 32;        // first-stage row groups of the gradient sum
 
 }  // namespace
 }  // namespace sr
@@ -372,7 +377,9 @@ extern "C" int sr_mlp_forward(const void *params, const float *feats, float *out
     return SR_OK;
 }
 
-extern "C" int64_t sr_mlp_grad_work(void) { return (int64_t)kTrainBlocks * kWaves * kNParams; }
+extern "C" int64_t sr_mlp_grad_work(void) {
+    return ((int64_t)kTrainBlocks * kWaves + kGradGroups) * kNParams;
+}
 
 extern "C" int sr_mlp_mse_grad(const void *params, const float *feats, const float *target,
                                int64_t M, float *grads, float *work, void *stream) {
@@ -380,7 +387,12 @@ extern "C" int sr_mlp_mse_grad(const void *params, const float *feats, const flo
     hipStream_t st = (hipStream_t)stream;
     mlp_train_kernel<<<kTrainBlocks, kBlock, 0, st>>>((const __bf16 *)params, (const float2 *)feats,
                                                      target, M, 1.0f / (float)M, work);
-    grad_reduce_kernel<<<(kNParams + 255) / 256, 256, 0, st>>>(work, kTrainBlocks * kWaves, grads);
+    const int rows = kTrainBlocks * kWaves, per = rows / kGradGroups;
+    float *mid = work + (int64_t)rows * kNParams;
+    grad_reduce_kernel<<<dim3((kNParams + 255) / 256, kGradGroups), 256, 0, st>>>(work, rows, per,
+                                                                                  mid);
+    grad_reduce_kernel<<<dim3((kNParams + 255) / 256, 1), 256, 0, st>>>(mid, kGradGroups,
+                                                                        kGradGroups, grads);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }
