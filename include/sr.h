@@ -227,6 +227,22 @@ int sr_eval_synchrotron_F(const sr_table *tab, const float *x, float *out, int64
 int sr_eval_trial(const sr_table *tab, const uint32_t *a, const float *rate, const float *chi,
                   int32_t kin_cut, float *out_dn, float *out_x, int64_t n, void *stream);
 
+/* Gather, Boris push and H_eff of every particle, exactly as the emission step
+ * computes them (section "Numerical implementation": E and B interpolated to
+ * the particle, the Boris scheme, and eq:effective_H from the momenta of the two
+ * neighbouring steps with dp_perp/p limited to 1), without emission and
+ * without writing the particles: out_heff = H_eff, out_chi = hbar_n H_eff
+ * gamma_bar, out_gamma_bar = the mean gamma of the step (device FP64 arrays of
+ * parts->n).  Only prm->hbar_n and prm->alpha are read.  The _f64 variant runs
+ * the FP64 gather and push of sr_gather_push_emit_f64.  For the per-result
+ * precision report of the FP32 / FP64 split. */
+int sr_eval_push(const sr_particles_f32 *parts, const sr_fields_f32 *fields, const sr_grid *grid,
+                 double dt, const sr_params *prm, double *out_heff, double *out_chi,
+                 double *out_gamma_bar, void *stream);
+int sr_eval_push_f64(const sr_particles_f64 *parts, const sr_fields_f32 *fields,
+                     const sr_grid *grid, double dt, const sr_params *prm, double *out_heff,
+                     double *out_chi, double *out_gamma_bar, void *stream);
+
 /* Philox4x32-10 (Salmon et al., SC'11) as used by the kernels: n counters
  * ctr[i][4] (device) with key (seed low, seed high) -> out[i][4] (device). */
 int sr_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out, int64_t n, void *stream);

@@ -89,6 +89,10 @@ SIGNATURES = {
                                           C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,
                                           C.POINTER(Chunking), C.POINTER(PhotonBuf),
                                           C.POINTER(Ledger), _P]),
+    "sr_eval_push": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32), C.POINTER(Grid), _D,
+                               C.POINTER(Params), _P, _P, _P, _P]),
+    "sr_eval_push_f64": (C.c_int, [C.POINTER(Particles64), C.POINTER(Fields32), C.POINTER(Grid),
+                                   _D, C.POINTER(Params), _P, _P, _P, _P]),
     "sr_ledger_reduce": (C.c_int, [C.POINTER(Ledger), _I64, _I64, _P]),
     "sr_ledger_partials": (C.c_int64, [_I64]),
     "sr_energy_ledger": (C.c_int, [C.POINTER(Ledger), _I64, _P, _P]),

@@ -414,6 +414,23 @@ def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: 
         ledger_reduce(ledger, cs.n_chunks, row, ls)
 
 
+def eval_push(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, hbar_n: float,
+              alpha: float) -> dict:
+    """H_eff, chi and the mean gamma of one push of every particle (the step's
+    own gather / Boris / H_eff code), FP64 device arrays; particles untouched."""
+    n = parts.n
+    out = {k: torch.empty(max(n, 1), device=DEV, dtype=torch.float64)
+           for k in ("heff", "chi", "gamma_bar")}
+    prm = params_struct(hbar_n, alpha)
+    ps = parts.struct()
+    fs = fields.struct() if fields is not None else None
+    fn = lib().sr_eval_push_f64 if parts.dtype == torch.float64 else lib().sr_eval_push
+    L.check(fn(C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid), float(dt),
+               C.byref(prm), _ptr(out["heff"]), _ptr(out["chi"]), _ptr(out["gamma_bar"]),
+               _stream()), "sr_eval_push")
+    return {k: v[:n] for k, v in out.items()}
+
+
 def ledger_reduce(ledger: "LedgerBuf", n_chunks: int, row: int, ls=None):
     ls = ledger.struct() if ls is None else ls
     L.check(lib().sr_ledger_reduce(C.byref(ls), int(n_chunks), int(row), _stream()),

@@ -97,6 +97,67 @@ template <> __device__ __forceinline__ double uniform_e<double>(const GridK &g, 
 template <> __device__ __forceinline__ float uniform_b<float>(const GridK &g, int q) { return g.b0[q]; }
 template <> __device__ __forceinline__ double uniform_b<double>(const GridK &g, int q) { return g.b0d[q]; }
 
+// Gather, Boris push and H_eff of one particle (section "Numerical
+// implementation"; eq:effective_H with the limiter dp_perp/p <= 1), shared by
+// the emission step and the evaluation entry point.
+template <typename R>
+struct Pushed {
+    R pn[3];      // p^{n+1/2}
+    R pb[3];      // mean momentum of the step
+    R p2;         // |pb|^2
+    R gb;         // mean gamma of the step
+    R g_new;      // gamma(p^{n+1/2})
+    R pbm;        // |pb|
+    R H;          // H_eff
+    R chi;        // hbar_n H_eff gamma_bar
+};
+
+template <typename R, int DIM>
+__device__ __forceinline__ Pushed<R> push_heff(const StepArgs<R> &a, const R pos[3],
+                                               const R p0[3]) {
+    Pushed<R> o;
+    R E[3], B[3];
+    if (DIM == 0) {
+        for (int q = 0; q < 3; ++q) { E[q] = uniform_e<R>(a.g, q); B[q] = uniform_b<R>(a.g, q); }
+    } else {
+        gather_grid<R, DIM>(a, pos, E, B);
+    }
+    // ---- Boris push (q = -1), keeping the momentum increment d explicitly
+    const R h = (R)(-0.5) * a.dt;
+    const R um[3] = {p0[0] + h * E[0], p0[1] + h * E[1], p0[2] + h * E[2]};
+    const R gm = sqrt_r<R>((R)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    const R hg = h * rcp_r<R>(gm);
+    const R t[3] = {hg * B[0], hg * B[1], hg * B[2]};
+    const R t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    const R sc = (R)2 * rcp_r<R>((R)1 + t2);
+    const R sv[3] = {sc * t[0], sc * t[1], sc * t[2]};
+    const R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]),
+                     um[1] + (um[2] * t[0] - um[0] * t[2]),
+                     um[2] + (um[0] * t[1] - um[1] * t[0])};
+    const R d[3] = {(up[1] * sv[2] - up[2] * sv[1]) + (R)2 * h * E[0],
+                    (up[2] * sv[0] - up[0] * sv[2]) + (R)2 * h * E[1],
+                    (up[0] * sv[1] - up[1] * sv[0]) + (R)2 * h * E[2]};
+    o.pn[0] = p0[0] + d[0]; o.pn[1] = p0[1] + d[1]; o.pn[2] = p0[2] + d[2];
+    // ---- H_eff (eq:effective_H) from the mean momentum and d, limited
+    o.pb[0] = p0[0] + (R)0.5 * d[0]; o.pb[1] = p0[1] + (R)0.5 * d[1]; o.pb[2] = p0[2] + (R)0.5 * d[2];
+    o.p2 = o.pb[0] * o.pb[0] + o.pb[1] * o.pb[1] + o.pb[2] * o.pb[2];
+    const R cx = diff_of_products(o.pb[1], d[2], o.pb[2], d[1]);
+    const R cy = diff_of_products(o.pb[2], d[0], o.pb[0], d[2]);
+    const R cz = diff_of_products(o.pb[0], d[1], o.pb[1], d[0]);
+    const R c2 = cx * cx + cy * cy + cz * cz;
+    const R g_old = sqrt_r<R>((R)1 + p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
+    o.g_new = sqrt_r<R>((R)1 + o.pn[0] * o.pn[0] + o.pn[1] * o.pn[1] + o.pn[2] * o.pn[2]);
+    o.gb = (R)0.5 * (g_old + o.g_new);
+    o.pbm = sqrt_r<R>(o.p2);
+    const R inv_p2 = o.p2 > (R)0 ? rcp_r<R>(o.p2) : (R)0;
+    R ratio = sqrt_r<R>(c2) * inv_p2;
+    if (ratio > (R)1) ratio = (R)1;
+    o.H = o.gb * ratio * a.inv_dt;
+    o.chi = a.hbar_n * o.H * o.gb;
+    return o;
+}
+
+
 template <typename R>
 __device__ __forceinline__ R wrap_pos(R v, R L) {
     if (v >= L) v -= L;
@@ -214,44 +275,15 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = ld(a.x[2], i);
             }
             const R p0[3] = {ld(a.p[0], i), ld(a.p[1], i), ld(a.p[2], i)};
-            R E[3], B[3];
-            if (DIM == 0) {
-                for (int q = 0; q < 3; ++q) { E[q] = uniform_e<R>(a.g, q); B[q] = uniform_b<R>(a.g, q); }
-            } else {
-                gather_grid<R, DIM>(a, pos, E, B);
-            }
-            // ---- Boris push (q = -1), keeping the momentum increment d explicitly
-            const R h = (R)(-0.5) * a.dt;
-            const R um[3] = {p0[0] + h * E[0], p0[1] + h * E[1], p0[2] + h * E[2]};
-            const R gm = sqrt_r<R>((R)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-            const R hg = h * rcp_r<R>(gm);
-            const R t[3] = {hg * B[0], hg * B[1], hg * B[2]};
-            const R t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-            const R sc = (R)2 * rcp_r<R>((R)1 + t2);
-            const R sv[3] = {sc * t[0], sc * t[1], sc * t[2]};
-            const R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]),
-                             um[1] + (um[2] * t[0] - um[0] * t[2]),
-                             um[2] + (um[0] * t[1] - um[1] * t[0])};
-            const R d[3] = {(up[1] * sv[2] - up[2] * sv[1]) + (R)2 * h * E[0],
-                            (up[2] * sv[0] - up[0] * sv[2]) + (R)2 * h * E[1],
-                            (up[0] * sv[1] - up[1] * sv[0]) + (R)2 * h * E[2]};
-            pn[0] = p0[0] + d[0]; pn[1] = p0[1] + d[1]; pn[2] = p0[2] + d[2];
-            // ---- H_eff (eq:effective_H) from the mean momentum and d, limited
-            const R pb[3] = {p0[0] + (R)0.5 * d[0], p0[1] + (R)0.5 * d[1], p0[2] + (R)0.5 * d[2]};
-            p2 = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2];
-            const R cx = diff_of_products(pb[1], d[2], pb[2], d[1]);
-            const R cy = diff_of_products(pb[2], d[0], pb[0], d[2]);
-            const R cz = diff_of_products(pb[0], d[1], pb[1], d[0]);
-            const R c2 = cx * cx + cy * cy + cz * cz;
-            const R g_old = sqrt_r<R>((R)1 + p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
-            g_new = sqrt_r<R>((R)1 + pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
-            gb = (R)0.5 * (g_old + g_new);
-            pbm = sqrt_r<R>(p2);
-            const R inv_p2 = p2 > (R)0 ? rcp_r<R>(p2) : (R)0;
-            R ratio = sqrt_r<R>(c2) * inv_p2;
-            if (ratio > (R)1) ratio = (R)1;
-            const R H = gb * ratio * a.inv_dt;
-            chi = a.hbar_n * H * gb;
+            const Pushed<R> q = push_heff<R, DIM>(a, pos, p0);
+            pn[0] = q.pn[0]; pn[1] = q.pn[1]; pn[2] = q.pn[2];
+            p2 = q.p2;
+            gb = q.gb;
+            g_new = q.g_new;
+            pbm = q.pbm;
+            const R H = q.H;
+            chi = q.chi;
+            const R pb[3] = {q.pb[0], q.pb[1], q.pb[2]};
             Hf = (float)H;
             chif = (float)chi;
             if (!isfinite(H)) flags |= SR_W_NONFINITE;
@@ -598,44 +630,28 @@ void split_inv(double dx, float &hi, float &lo) {
     lo = (float)(inv - (double)hi);
 }
 
+// Validation and kernel arguments shared by the step and the push evaluation:
+// particles, grid, fields, dt and the physical constants of prm.
 template <typename R, typename PARTS>
-int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
-                uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
-                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream) {
-    if (!parts || !grid || !prm || !tab || !chunks || !ph || !led) return SR_E_INVAL;
+int particle_args(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                  const sr_params *prm, StepArgs<R> &a) {
+    if (!parts || !grid || !prm) return SR_E_INVAL;
     const int64_t n = parts->n;
     if (n < 0 || !(dt > 0.0)) return SR_E_INVAL;
-    if (!parts->p[0] || !parts->p[1] || !parts->p[2] || !parts->w || !parts->id)
-        return n == 0 ? SR_OK : SR_E_INVAL;
+    if (!(prm->hbar_n > 0.0) || !(prm->alpha > 0.0)) return SR_E_INVAL;
     const int dim = grid->dim;
     if (dim != 0 && dim != 2 && dim != 3) return SR_E_INVAL;
-    const int K = prm->n_samples;
-    if (K < 1 || K > kMaxK) return SR_E_INVAL;
-    if (prm->sampler < SR_SAMPLER_S || prm->sampler > SR_SAMPLER_MLP) return SR_E_INVAL;
-    if (prm->sampler == SR_SAMPLER_MLP && (!prm->mlp_params || !prm->mlp_fallback))
-        return SR_E_INVAL;
-    if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
-        return SR_E_INVAL;
-    if (!(prm->hbar_n > 0.0) || !(prm->alpha > 0.0)) return SR_E_INVAL;
-    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
-    if (chunks->start == nullptr && chunks->n_chunks != n_chunks) return SR_E_INVAL;
-    if (n_chunks < 0 || n_chunks > 0x7FFFFFFF) return SR_E_INVAL;
-    if (ph->per_particle < 0 || !ph->seg_count) return SR_E_INVAL;
     // the kernels address every array with 32-bit byte offsets
-    if (n >= ((int64_t)1 << 31) / (int64_t)sizeof(R) ||
-        n * ph->per_particle >= ((int64_t)1 << 30))
-        return SR_E_UNSUPPORTED;
-    if (ph->per_particle > 0 &&
-        (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2] || !ph->parent))
+    if (n >= ((int64_t)1 << 31) / (int64_t)sizeof(R)) return SR_E_UNSUPPORTED;
+    if (n > 0 && (!parts->p[0] || !parts->p[1] || !parts->p[2] || !parts->w || !parts->id))
         return SR_E_INVAL;
-    if (!led->partials || !led->status) return SR_E_INVAL;
-    if (led->partials_len < sr_ledger_partials(n_chunks)) return SR_E_INVAL;
     const bool has_pos = parts->x[0] != nullptr;
     if (dim != 0) {
         if (!fields) return SR_E_INVAL;
         for (int q = 0; q < 3; ++q)
             if (!fields->e[q] || !fields->b[q]) return SR_E_INVAL;
-        if (!parts->x[0] || !parts->x[1] || (dim == 3 && !parts->x[2])) return SR_E_INVAL;
+        if (n > 0 && (!parts->x[0] || !parts->x[1] || (dim == 3 && !parts->x[2])))
+            return SR_E_INVAL;
         for (int q = 0; q < dim; ++q)
             if (grid->n[q] < 1 || grid->n[q] > (1 << 24) || !(grid->dx[q] > 0.0)) return SR_E_INVAL;
         if (grid->n[0] < 2) return SR_E_INVAL;   // rows are read as pairs
@@ -645,9 +661,6 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
         if (cells <= 0) return SR_E_INVAL;
         if (cells >= ((int64_t)1 << 30)) return SR_E_UNSUPPORTED;
     }
-    if (n_chunks == 0) return SR_OK;
-
-    StepArgs<R> a;
     a.n = n;
     for (int q = 0; q < 3; ++q) { a.x[q] = parts->x[q]; a.p[q] = parts->p[q]; }
     a.w = parts->w;
@@ -673,6 +686,43 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     if (dim == 2) { g.n[2] = 1; }
     a.dt = (R)dt;
     a.inv_dt = (R)(1.0 / dt);
+    a.has_pos = has_pos ? 1 : 0;
+    a.hbar_n = (R)prm->hbar_n;
+    a.rate_c = (float)(dt * 1.7320508075688772 / (2.0 * 3.14159265358979323846) * prm->alpha);
+    a.direct_c = (float)(dt * 5.0 / (2.0 * 1.7320508075688772) * prm->alpha);
+    a.ll_c = (R)((2.0 / 3.0) * (prm->alpha / prm->hbar_n) * dt);
+    return SR_OK;
+}
+
+template <typename R, typename PARTS>
+int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
+                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream) {
+    if (!parts || !grid || !prm || !tab || !chunks || !ph || !led) return SR_E_INVAL;
+    StepArgs<R> a;
+    const int rc = particle_args<R>(parts, fields, grid, dt, prm, a);
+    if (rc != SR_OK) return rc;
+    const int64_t n = parts->n;
+    const int dim = grid->dim;
+    const int K = prm->n_samples;
+    if (K < 1 || K > kMaxK) return SR_E_INVAL;
+    if (prm->sampler < SR_SAMPLER_S || prm->sampler > SR_SAMPLER_MLP) return SR_E_INVAL;
+    if (prm->sampler == SR_SAMPLER_MLP && (!prm->mlp_params || !prm->mlp_fallback))
+        return SR_E_INVAL;
+    if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
+        return SR_E_INVAL;
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
+    if (chunks->start == nullptr && chunks->n_chunks != n_chunks) return SR_E_INVAL;
+    if (n_chunks < 0 || n_chunks > 0x7FFFFFFF) return SR_E_INVAL;
+    if (ph->per_particle < 0 || !ph->seg_count) return SR_E_INVAL;
+    if (n * ph->per_particle >= ((int64_t)1 << 30)) return SR_E_UNSUPPORTED;
+    if (ph->per_particle > 0 &&
+        (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2] || !ph->parent))
+        return SR_E_INVAL;
+    if (!led->partials || !led->status) return SR_E_INVAL;
+    if (led->partials_len < sr_ledger_partials(n_chunks)) return SR_E_INVAL;
+    if (n_chunks == 0) return SR_OK;
+
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
     a.step = (uint32_t)step;
@@ -681,11 +731,6 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.dn_policy = prm->dn_policy;
     a.kin_cut = prm->kin_cut;
     a.push_position = prm->push_position;
-    a.has_pos = has_pos ? 1 : 0;
-    a.hbar_n = (R)prm->hbar_n;
-    a.rate_c = (float)(dt * 1.7320508075688772 / (2.0 * 3.14159265358979323846) * prm->alpha);
-    a.direct_c = (float)(dt * 5.0 / (2.0 * 1.7320508075688772) * prm->alpha);
-    a.ll_c = (R)((2.0 / 3.0) * (prm->alpha / prm->hbar_n) * dt);
     a.tab.ftab = tab->ftab;
     a.tab.pa = tab->pa;
     a.tab.t1 = tab->t1;
@@ -736,6 +781,48 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     return SR_OK;
 }
 
+// Gather, push and H_eff of every particle without emission or any write to
+// the particles: out_heff, out_chi, out_gamma_bar (device FP64, n each).
+template <typename R, int DIM>
+__global__ __launch_bounds__(kBlock) void eval_push_kernel(const StepArgs<R> a,
+                                                           double *__restrict__ heff,
+                                                           double *__restrict__ chi,
+                                                           double *__restrict__ gbar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t u = (uint32_t)i;
+    R pos[3] = {(R)0, (R)0, (R)0};
+    if (a.has_pos) {
+        pos[0] = ld(a.x[0], u);
+        if (DIM != 0 || a.x[1]) pos[1] = ld(a.x[1], u);
+        if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = ld(a.x[2], u);
+    }
+    const R p0[3] = {ld(a.p[0], u), ld(a.p[1], u), ld(a.p[2], u)};
+    const Pushed<R> q = push_heff<R, DIM>(a, pos, p0);
+    heff[i] = (double)q.H;
+    chi[i] = (double)q.chi;
+    gbar[i] = (double)q.gb;
+}
+
+template <typename R, typename PARTS>
+int launch_eval_push(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                     const sr_params *prm, double *heff, double *chi, double *gbar, void *stream) {
+    StepArgs<R> a;
+    const int rc = particle_args<R>(parts, fields, grid, dt, prm, a);
+    if (rc != SR_OK) return rc;
+    if (parts->n == 0) return SR_OK;
+    if (!heff || !chi || !gbar) return SR_E_INVAL;
+    const unsigned nb = (unsigned)((parts->n + kBlock - 1) / kBlock);
+    hipStream_t st = (hipStream_t)stream;
+    switch (grid->dim) {
+        case 0: eval_push_kernel<R, 0><<<nb, kBlock, 0, st>>>(a, heff, chi, gbar); break;
+        case 2: eval_push_kernel<R, 2><<<nb, kBlock, 0, st>>>(a, heff, chi, gbar); break;
+        default: eval_push_kernel<R, 3><<<nb, kBlock, 0, st>>>(a, heff, chi, gbar); break;
+    }
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
 }  // namespace
 }  // namespace sr
 
@@ -744,6 +831,21 @@ using namespace sr;
 extern "C" int64_t sr_ledger_partials(int64_t n_chunks) {
     if (n_chunks < 0) return 0;
     return (partial_rows(n_chunks) + kReduceL1Blocks + 1) * SR_LEDGER_COLS;
+}
+
+extern "C" int sr_eval_push(const sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                            const sr_grid *grid, double dt, const sr_params *prm, double *out_heff,
+                            double *out_chi, double *out_gamma_bar, void *stream) {
+    return launch_eval_push<float>(parts, fields, grid, dt, prm, out_heff, out_chi, out_gamma_bar,
+                                   stream);
+}
+
+extern "C" int sr_eval_push_f64(const sr_particles_f64 *parts, const sr_fields_f32 *fields,
+                                const sr_grid *grid, double dt, const sr_params *prm,
+                                double *out_heff, double *out_chi, double *out_gamma_bar,
+                                void *stream) {
+    return launch_eval_push<double>(parts, fields, grid, dt, prm, out_heff, out_chi,
+                                    out_gamma_bar, stream);
 }
 
 extern "C" int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields,

@@ -97,3 +97,46 @@ def test_step_rejects_bad_arguments_on_host(lib):
     assert lib.sr_energy_ledger(None, 0, None, None) == L.SR_E_INVAL
     assert lib.sr_ledger_reduce(None, 1, 0, None) == L.SR_E_INVAL
     assert lib.sr_ledger_reduce(C.byref(led), 1, 0, None) == L.SR_E_INVAL
+
+
+def test_eval_push_rejects_bad_arguments_on_host(lib):
+    from paper_1409_5574_amd import _lib as L
+    p = L.Particles32()
+    p.n = 10
+    grid = L.Grid()
+    grid.dim = 0
+    prm = L.Params(1e-5, 7.3e-3, 1, 0, 1, 0, 0, 0)
+    out = C.c_void_p(16)
+    # null particle arrays with n > 0
+    assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), out, out, out,
+                            None) == L.SR_E_INVAL
+    dummy = C.c_void_p(16)
+    for a in range(3):
+        p.p[a] = dummy
+    p.w = dummy
+    p.id = dummy
+    # null outputs, bad dt, bad hbar_n, a 2D grid without fields or with nx < 2
+    assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), None, out, out,
+                            None) == L.SR_E_INVAL
+    assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.0, C.byref(prm), out, out, out,
+                            None) == L.SR_E_INVAL
+    bad = L.Params(0.0, 7.3e-3, 1, 0, 1, 0, 0, 0)
+    assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.1, C.byref(bad), out, out, out,
+                            None) == L.SR_E_INVAL
+    grid.dim = 2
+    grid.n[0], grid.n[1], grid.n[2] = 1, 8, 1
+    grid.dx[0] = grid.dx[1] = grid.dx[2] = 0.1
+    assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), out, out, out,
+                            None) == L.SR_E_INVAL
+    f = L.Fields32()
+    for a in range(3):
+        f.e[a] = dummy
+        f.b[a] = dummy
+    p.x[0] = p.x[1] = dummy
+    assert lib.sr_eval_push(C.byref(p), C.byref(f), C.byref(grid), 0.1, C.byref(prm), out, out,
+                            out, None) == L.SR_E_INVAL
+    # an empty set is a no-op
+    p.n = 0
+    grid.dim = 0
+    assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), None, None, None,
+                            None) == L.SR_OK
