@@ -214,13 +214,25 @@ struct alignas(16) StepSmem {
         LedgerSmem led;
     };
 };
+// Photons staged in LDS for one block-wide flush: wave w's first kStage photons
+// of its (single) round sit at [w][0, kStage).
+constexpr int kStage = 64;
+struct PhotonStage {
+    float eps[kWaves][kStage], w[kWaves][kStage];
+    float dir[3][kWaves][kStage], pos[3][kWaves][kStage];
+    uint32_t parent[kWaves][kStage], k[kWaves][kStage];
+    uint32_t cnt[kWaves];       // staged photons per wave
+    uint32_t base[kWaves];      // first buffer slot of each wave's chunk segment
+};
 template <int KMAX>
 struct StepSmem<KMAX, SR_SAMPLER_S> {
     LedgerSmem led;
+    PhotonStage stage;
 };
 template <int KMAX>
 struct StepSmem<KMAX, SR_SAMPLER_TABLE> {
     LedgerSmem led;
+    PhotonStage stage;
 };
 template <typename S>
 __device__ __forceinline__ LedgerSmem &ledger_smem(S &s) { return s.led; }
@@ -248,6 +260,11 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
     const uint32_t pp = (uint32_t)a.per_particle;
     const uint32_t seg_base = s0 * pp;
     const uint32_t seg_cap = (e0 - s0) * pp;
+    // With uniform chunks every wave has a single round, so the S and table
+    // samplers stage their photons in LDS and the block writes them together
+    // at the end (one store per array for up to 256 photons of four chunks).
+    constexpr bool kCanStage = SAMPLER != SR_SAMPLER_MLP;
+    const bool staged = kCanStage && a.start == nullptr;
     const int K = a.K;
     const float invK = 1.0f / (float)K;
 
@@ -348,8 +365,22 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                         delta_ph += frac * eps;
                         const uint32_t slot = run_base + wave_tot + lane_prefix(m);
                         if (slot < seg_cap) {
-                            store_photon(cold_args<R>(), seg_base + slot, eps, wph, dirf, posf, pid,
-                                         (uint32_t)k, a.step);
+                            if (staged && slot < (uint32_t)kStage) {
+                                PhotonStage &S = sm.stage;
+                                S.eps[wave][slot] = eps;
+                                S.w[wave][slot] = wph;
+                                S.dir[0][wave][slot] = dirf[0];
+                                S.dir[1][wave][slot] = dirf[1];
+                                S.dir[2][wave][slot] = dirf[2];
+                                S.pos[0][wave][slot] = posf[0];
+                                S.pos[1][wave][slot] = posf[1];
+                                S.pos[2][wave][slot] = posf[2];
+                                S.parent[wave][slot] = pid;
+                                S.k[wave][slot] = (uint32_t)k;
+                            } else {
+                                store_photon(cold_args<R>(), seg_base + slot, eps, wph, dirf, posf,
+                                             pid, (uint32_t)k, a.step);
+                            }
                         } else {
                             acc_drop += (double)wph * (double)eps;
                             flags |= SR_W_PHOTON_OVERFLOW;
@@ -523,7 +554,29 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
     rs.f[0][tid] = acc_w;
     rs.f[1][tid] = chi_max;
     if (lane == 0) rs.cnt[wave] = run_base;
+    if constexpr (kCanStage) {
+        if (staged && lane == 0) {
+            sm.stage.cnt[wave] = min(min(run_base, seg_cap), (uint32_t)kStage);
+            sm.stage.base[wave] = seg_base;
+        }
+    }
     __syncthreads();
+    if constexpr (kCanStage) {
+        if (staged) {
+            const PhotonStage &S = sm.stage;
+            const uint32_t c0 = S.cnt[0], c1 = c0 + S.cnt[1], c2 = c1 + S.cnt[2];
+            const uint32_t total = c2 + S.cnt[3];
+            const uint32_t e = (uint32_t)tid;
+            if (e < total) {
+                const int wv = (int)(e >= c0) + (int)(e >= c1) + (int)(e >= c2);
+                const uint32_t j = e - (wv == 0 ? 0u : wv == 1 ? c0 : wv == 2 ? c1 : c2);
+                const float d[3] = {S.dir[0][wv][j], S.dir[1][wv][j], S.dir[2][wv][j]};
+                const float ps[3] = {S.pos[0][wv][j], S.pos[1][wv][j], S.pos[2][wv][j]};
+                store_photon(cold_args<R>(), S.base[wv] + j, S.eps[wv][j], S.w[wv][j], d, ps,
+                             S.parent[wv][j], S.k[wv][j], a.step);
+            }
+        }
+    }
     double *row = cold_args<R>().partials + (size_t)blk * SR_LEDGER_COLS;
     const auto dsum = [&](int q) {
         const double v = ((rs.d[q][lane] + rs.d[q][lane + 64]) + rs.d[q][lane + 128]) +
