@@ -8,7 +8,7 @@ A step is one pass of the whole hot path over the particle ensemble:
   position push (sr_gather_push_emit), the FP64 energy ledger reduction, and
   the photon-spectrum histogram that drains the photon buffer.
 The K timed steps run twice from the same warm state: once as eager launches,
-with HIP events around every emission-kernel launch on its stream (the
+with HIP events recorded by every emission-kernel dispatch on its stream (the
 roofline figure), and once captured into a HIP graph and run as one graph
 launch.  `value` is particle-steps/s of the graph pass (wall clock between
 device synchronisations; --no-graph reports the eager pass); both passes are
@@ -140,8 +140,13 @@ def run(args):
     structs = {id(parts): api.make_structs(parts, fields, photons, ledger),
                id(alt): api.make_structs(alt, fields, photons, ledger)}
     stream = torch.cuda.current_stream()
+    # events the emission kernel's dispatch records at its start and end (they
+    # are recorded once here so that they exist)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        b_.record(stream)
     ev_wave = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
 
@@ -157,12 +162,9 @@ def run(args):
             api.sort_particles(parts, alt, grid, tile, sort_work)
             parts, alt = alt, parts
         s = structs[id(parts)]
-        if timed_idx is not None:
-            ev[timed_idx][0].record(stream)
         api.gather_push_emit(parts, fields, grid, cfg.dt, seed, i, prm, table, photons, ledger,
-                             None, structs=s)
-        if timed_idx is not None:
-            ev[timed_idx][1].record(stream)
+                             None, structs=s,
+                             events=ev[timed_idx] if timed_idx is not None else None)
         api.ledger_reduce(ledger, n_chunks, i, s[4])
         api.spectrum_histogram(photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist, hwork)
 
@@ -200,7 +202,7 @@ def run(args):
     snap_bufs = (parts, alt)
     snap = [None if t is None else t.clone() for t in parts.x + parts.p + [parts.w, parts.id]]
 
-    # ---------------- timed pass 1, eager launches: HIP events around every
+    # ---------------- timed pass 1, eager launches: HIP events recorded by every
     # emission-kernel launch (the roofline) and every field refresh
     hist.zero_()
     torch.cuda.synchronize()
@@ -291,8 +293,9 @@ def run(args):
                              "steps": [args.warmup + 1, args.warmup + args.steps]},
                    "note": "both passes run the same K steps from the same warm state",
                    "hip_graph": graph_info,
-                   "kernel_ms_from": "HIP events around each emission-kernel launch of the "
-                                     "eager pass, on its stream"},
+                   "kernel_ms_from": "HIP events recorded by each emission-kernel dispatch "
+                                     "of the eager pass (hipExtLaunchKernel start/stop), on "
+                                     "its stream"},
     }
     if check is not None:
         out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, check, seed, args)

@@ -268,6 +268,16 @@ int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields, co
 
 /* The same step with FP64 state, FP64 gather (of the FP32 grid values), FP64
  * Boris push and H_eff; the trials run in FP32 as in the FP32 path. */
+/* sr_gather_push_emit with timing: ev_start and ev_stop are HIP events
+ * (hipEvent_t, created by the caller) that the kernel's own dispatch records at
+ * its start and end (hipExtLaunchKernel), so their elapsed time is the
+ * kernel's duration without the queue packets a separate event record adds.
+ * Either may be NULL.  Results are those of sr_gather_push_emit. */
+int sr_gather_push_emit_timed(sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                              const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
+                              const sr_params *prm, const sr_table *tab, const sr_chunking *chunks,
+                              sr_photon_buf *photons, sr_ledger *ledger, void *ev_start,
+                              void *ev_stop, void *stream);
 int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields,
                             const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
                             const sr_params *prm, const sr_table *tab, const sr_chunking *chunks,

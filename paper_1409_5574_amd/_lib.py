@@ -85,6 +85,10 @@ SIGNATURES = {
                                       C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,
                                       C.POINTER(Chunking), C.POINTER(PhotonBuf),
                                       C.POINTER(Ledger), _P]),
+    "sr_gather_push_emit_timed": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32),
+                                            C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params),
+                                            _P, C.POINTER(Chunking), C.POINTER(PhotonBuf),
+                                            C.POINTER(Ledger), _P, _P, _P]),
     "sr_gather_push_emit_f64": (C.c_int, [C.POINTER(Particles64), C.POINTER(Fields32),
                                           C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,
                                           C.POINTER(Chunking), C.POINTER(PhotonBuf),

@@ -398,17 +398,27 @@ class Mlp:
 def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, seed: int,
                      step: int, prm: L.Params, table: Table, photons: PhotonBuffer,
                      ledger: LedgerBuf, row: int | None, start: torch.Tensor | None = None,
-                     structs: tuple | None = None):
+                     structs: tuple | None = None, events: tuple | None = None):
     """One emission step; with row set, also reduce the ledger into that row.
     `structs` may hold pre-built (parts, fields, chunking, photons, ledger) C
-    structs to avoid rebuilding them every call."""
+    structs to avoid rebuilding them every call.  `events`: a (start, stop)
+    pair of recorded torch.cuda.Event(enable_timing=True) that the kernel's own
+    dispatch re-records at its start and end (FP32 path)."""
     if structs is None:
         structs = make_structs(parts, fields, photons, ledger, start)
     ps, fs, cs, phs, ls = structs
-    fn = lib().sr_gather_push_emit_f64 if parts.dtype == torch.float64 else lib().sr_gather_push_emit
-    rc = fn(C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid), float(dt),
+    args = (C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid), float(dt),
             seed & 0xFFFFFFFFFFFFFFFF, int(step), C.byref(prm), table.handle, C.byref(cs),
-            C.byref(phs), C.byref(ls), _stream())
+            C.byref(phs), C.byref(ls))
+    if events is not None:
+        if parts.dtype != torch.float32:
+            raise ValueError("timed launches exist for the FP32 path only")
+        rc = lib().sr_gather_push_emit_timed(*args, C.c_void_p(events[0].cuda_event),
+                                             C.c_void_p(events[1].cuda_event), _stream())
+    else:
+        fn = (lib().sr_gather_push_emit_f64 if parts.dtype == torch.float64
+              else lib().sr_gather_push_emit)
+        rc = fn(*args, _stream())
     L.check(rc, "sr_gather_push_emit")
     if row is not None:
         ledger_reduce(ledger, cs.n_chunks, row, ls)

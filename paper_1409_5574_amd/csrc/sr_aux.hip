@@ -190,15 +190,27 @@ __global__ __launch_bounds__(256) void hist_kernel(sr_photon_buf ph, const int64
         const int64_t cap = (e0 - s0) * ph.per_particle;
         const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
         const int64_t base = s0 * ph.per_particle;
-        for (int64_t q = 0; q < cnt; ++q) {
-            const float eps = ph.eps[base + q];
-            const float w = ph.w[base + q];
-            if (!(eps > 0.0f)) continue;
-            const float u = (__log2f(eps) - l2lo) * scale;
-            if (u < 0.0f || u >= (float)nbins) continue;
-            const int bin = (int)u;
-            atomicAdd(&sh[bin], (double)w * (double)eps);
-            atomicAdd(&sh[nbins + bin], (double)w);
+        // eight photons at a time: their loads are in flight together
+        for (int64_t q0 = 0; q0 < cnt; q0 += 8) {
+            float eps[8], w[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                eps[j] = 0.0f;
+                w[j] = 0.0f;
+                if (q0 + j < cnt) {
+                    eps[j] = ph.eps[base + q0 + j];
+                    w[j] = ph.w[base + q0 + j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (!(eps[j] > 0.0f)) continue;
+                const float u = (__log2f(eps[j]) - l2lo) * scale;
+                if (u < 0.0f || u >= (float)nbins) continue;
+                const int bin = (int)u;
+                atomicAdd(&sh[bin], (double)w[j] * (double)eps[j]);
+                atomicAdd(&sh[nbins + bin], (double)w[j]);
+            }
         }
     }
     __syncthreads();

@@ -15,6 +15,8 @@
 #include <math.h>
 #include <stddef.h>
 
+#include <hip/hip_ext.h>
+
 #include "sr_mlp.hpp"
 
 namespace sr {
@@ -750,7 +752,8 @@ int particle_args(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid
 template <typename R, typename PARTS>
 int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
                 uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
-                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream) {
+                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream,
+                void *ev_start = nullptr, void *ev_stop = nullptr) {
     if (!parts || !grid || !prm || !tab || !chunks || !ph || !led) return SR_E_INVAL;
     StepArgs<R> a;
     const int rc = particle_args<R>(parts, fields, grid, dt, prm, a);
@@ -808,8 +811,13 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     const dim3 grd((unsigned)partial_rows(n_chunks)), blk(kBlock);
     const int KM = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : 16;
 
-#define SR_LAUNCH(DIMV, KMV, SMP) \
-    push_emit_kernel<R, DIMV, KMV, SMP><<<grd, blk, 0, st>>>(a)
+    // with events: the dispatch packet itself records the kernel's start and stop
+#define SR_LAUNCH(DIMV, KMV, SMP)                                                              \
+    if (ev_start || ev_stop)                                                                   \
+        hipExtLaunchKernelGGL(push_emit_kernel<R, DIMV, KMV, SMP>, grd, blk, 0, st,            \
+                              (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, a);                \
+    else                                                                                       \
+        push_emit_kernel<R, DIMV, KMV, SMP><<<grd, blk, 0, st>>>(a)
 #define SR_BY_K(DIMV, SMP)                             \
     switch (KM) {                                      \
         case 1: SR_LAUNCH(DIMV, 1, SMP); break;        \
@@ -908,6 +916,16 @@ extern "C" int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 
                                    sr_ledger *ledger, void *stream) {
     return launch_step<float>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
                               ledger, stream);
+}
+
+extern "C" int sr_gather_push_emit_timed(sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                                         const sr_grid *grid, double dt, uint64_t seed,
+                                         uint64_t step, const sr_params *prm, const sr_table *tab,
+                                         const sr_chunking *chunks, sr_photon_buf *photons,
+                                         sr_ledger *ledger, void *ev_start, void *ev_stop,
+                                         void *stream) {
+    return launch_step<float>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
+                              ledger, stream, ev_start, ev_stop);
 }
 
 extern "C" int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields,

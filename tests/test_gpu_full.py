@@ -297,3 +297,38 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample):
     assert e_gpu == pytest.approx(led_o[0], rel=parity.LEDGER_TOL) or rep["decision_flips"]
     print(f"{name}: sampled {sample}, photons {rep['photons_oracle']}, flips "
           f"{rep['decision_flips']}, |dp|/p {rep['p_rel_err']:.2e}", flush=True)
+
+
+def test_timed_launch_matches_untimed(sr, table):
+    """sr_gather_push_emit_timed gives the results of sr_gather_push_emit and
+    fills its two events with the kernel's own start and stop."""
+    cfg = synth.config("c2", n_particles=50000, grid=(512, 256, 1))
+    grid = sr.grid_struct(2, n=cfg.grid, dx=(cfg.dx,) * 3)
+    fields = sr.Fields(ncells=cfg.grid[0] * cfg.grid[1])
+    sr.standing_wave(fields, grid, cfg.a0, 0.4)
+    st = synth.gen_particles(cfg)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, 1)
+    outs = []
+    for timed in (False, True):
+        parts = sr.Particles.from_numpy(st, dim=2)
+        photons = sr.PhotonBuffer(parts.n, 4, dim=2)
+        ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(parts.n))
+        ev = None
+        if timed:
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record()
+            ev[1].record()
+        _say(f"timed launch {timed}")
+        sr.gather_push_emit(parts, fields, grid, cfg.dt, 5, 1, prm, table, photons, ledger, 0,
+                            events=ev)
+        torch.cuda.synchronize()
+        outs.append((parts.to_numpy(), ledger.row(0), photons.gather(parts.n)))
+        if timed:
+            ms = ev[0].elapsed_time(ev[1])
+            assert 0.0 < ms < 50.0
+    (a, la, pa), (b, lb, pb) = outs
+    for k in ("x", "y", "px", "py", "pz"):
+        assert np.array_equal(a[k], b[k])
+    assert np.array_equal(la, lb)
+    assert np.array_equal(pa["eps"], pb["eps"])
+    assert pa["stored"] > 0
