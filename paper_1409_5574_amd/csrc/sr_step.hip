@@ -245,8 +245,14 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if constexpr (SAMPLER == SR_SAMPLER_MLP) {
-        mlp_load(sm.m, a.mlp, tid, kBlock);
-        __syncthreads();
+        // the network is copied to LDS only if the fallback map leaves some
+        // bin to it (the same decision in every thread of the block)
+        bool any_net = false;
+        for (int b = 0; b < kMlpFallbackBins; ++b) any_net |= a.mlp_fallback[b] == 0;
+        if (any_net) {
+            mlp_load(sm.m, a.mlp, tid, kBlock);
+            __syncthreads();
+        }
     }
     // one chunk per wave, kWaves consecutive chunks per block (blocks mapped so
     // that neighbouring chunks share an XCD)
