@@ -154,6 +154,18 @@ __global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const u
                              const uint32_t *offsets, uint32_t *cursor) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < src.n;
+    // the particle's values are read first: they do not depend on where it goes
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t id = 0;
+    if (valid) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (src.x[a]) v[a] = src.x[a][i];
+            v[3 + a] = src.p[a][i];
+        }
+        v[6] = src.w[i];
+        id = src.id[i];
+    }
     const uint32_t k = valid ? keys[i] : 0xFFFFFFFFu;
     const WaveRun r = wave_run(k, valid);
     uint32_t base = 0;
@@ -162,12 +174,13 @@ __global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const u
     if (!valid) return;
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)offsets[k] + base + (lane - r.head_lane);
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (src.x[a] && dst.x[a]) dst.x[a][j] = src.x[a][i];
-        dst.p[a][j] = src.p[a][i];
+        if (src.x[a] && dst.x[a]) dst.x[a][j] = v[a];
+        dst.p[a][j] = v[3 + a];
     }
-    dst.w[j] = src.w[i];
-    dst.id[j] = src.id[i];
+    dst.w[j] = v[6];
+    dst.id[j] = id;
 }
 
 // ------------------------------------------------------------ histogram
