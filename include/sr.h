@@ -17,9 +17,10 @@
  *    SYNCHRONOUS.
  *  - Return value: SR_OK (0) or a negative sr_error code.  Argument errors are
  *    detected on the host before anything is launched, so a failed call has
- *    enqueued no work.  Conditions found on the device (photon-segment
- *    overflow, recoil clamping, non-finite inputs) are latched as bits in the
- *    caller's status word and read back by sr_status().
+ *    enqueued no work.  Conditions the emission step finds on the device
+ *    (photon-segment overflow, recoil clamping, non-finite inputs) travel with
+ *    its ledger partials; sr_ledger_reduce latches them as bits in the
+ *    caller's status word, read back by sr_status().
  *  - Hot calls (sr_gather_push_emit*, sr_ledger_reduce, sr_spectrum_histogram,
  *    sr_field_standing_wave, sr_sort_particles, sr_mlp_*) allocate nothing.
  *    Only sr_table_build allocates device memory (released by sr_table_free).
@@ -173,8 +174,9 @@ typedef struct {
 
 /* FP64 energy ledger.  rows: device [n_rows][SR_LEDGER_COLS]; partials: device
  * workspace of at least sr_ledger_partials(n_chunks) doubles (the step writes
- * one partial row per group of four chunks); status: device uint32 whose bits
- * are OR-ed in by the kernels (the caller zeroes it). */
+ * one partial row per group of four chunks, with the block's condition bits);
+ * status: device uint32 into which sr_ledger_reduce ORs the condition bits of
+ * the step it reduces (the caller zeroes it). */
 typedef struct {
     double *rows;
     int64_t n_rows;
@@ -256,9 +258,10 @@ int sr_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out, int64_t n, void
  *   Carlo method"), random words from Philox4x32-10 with counter
  *   (id, step, k/2, 0) and key seed;
  *   photon append into the chunk's segment, recoil, position push.
- * Writes FP64 ledger partial rows into ledger->partials (sum them into a
- * ledger row with sr_ledger_reduce, passing the same n_chunks) and ORs condition bits into
- * ledger->status.  With per_particle == 0 nothing is stored and every photon
+ * Writes FP64 ledger partial rows, with the condition bits found, into
+ * ledger->partials (sum them into a ledger row with sr_ledger_reduce, passing
+ * the same n_chunks; that call latches the bits into ledger->status).  With
+ * per_particle == 0 nothing is stored and every photon
  * is counted as dropped.  Explicit chunk starts are trusted: the caller
  * guarantees 0 = start[0] <= ... <= start[n_chunks] = n. */
 int sr_gather_push_emit(sr_particles_f32 *parts, const sr_fields_f32 *fields, const sr_grid *grid,
@@ -285,8 +288,9 @@ int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields
 
 /* Sum the partial rows a step over n_chunks chunks wrote into ledger->rows[row]
  * (FP64, fixed order, so the result is reproducible; column SR_LED_CHI_MAX is
- * a maximum).  The energy ledger of the section "Comparison and benchmarking":
- * emitted photon energy against the Landau-Lifshitz loss. */
+ * a maximum) and OR the step's condition bits into *ledger->status.  The
+ * energy ledger of the section "Comparison and benchmarking": emitted photon
+ * energy against the Landau-Lifshitz loss. */
 int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row, void *stream);
 
 /* Workspace length (doubles) for ledger->partials with n_chunks chunks. */

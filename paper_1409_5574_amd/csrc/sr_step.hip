@@ -31,7 +31,6 @@ struct PhotonOut {
     uint8_t *k;
     uint32_t *seg_count;
     double *partials;
-    uint32_t *status;
 };
 
 template <typename R>
@@ -200,7 +199,14 @@ struct LedgerSmem {
     double d[5][kBlock];
     float f[2][kBlock];
     uint32_t cnt[kWaves];
+    uint32_t flags[kWaves];
 };
+
+// Partial ledger rows (internal workspace): the SR_LEDGER_COLS columns of a
+// ledger row, then the OR of the condition bits of the block (as a double),
+// then one pad column.
+constexpr int kPartCols = SR_LEDGER_COLS + 2;
+constexpr int kPartFlags = SR_LEDGER_COLS;
 
 // LDS of the kernel.  With the MLP sampler: the network, and per wave the
 // compacted inputs of the emitted trials and a 16x64 transpose buffer, which
@@ -535,16 +541,13 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
 
     if (have && lane == 0) cold_args<R>().seg_count[c] = run_base;
 
-    // latch device-side conditions.  Same-address atomics serialise across the
-    // whole device, so a wave only issues one when its bits are not yet set.
+    // the wave's condition bits; they travel in the block's partial row to the
+    // ledger reduction, which latches them into the status word
+    uint32_t wf = 0;
     if (__ballot(flags != 0)) {
-        uint32_t wf = flags;
+        wf = flags;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) wf |= (uint32_t)__shfl_xor((int)wf, o, 64);
-        if (lane == 0) {
-            uint32_t *status = cold_args<R>().status;
-            if ((__atomic_load_n(status, __ATOMIC_RELAXED) & wf) != wf) atomicOr(status, wf);
-        }
     }
 
     // ---- per-block ledger partial (FP64, fixed reduction order).  The lanes'
@@ -561,7 +564,10 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
     rs.d[4][tid] = acc_drop;
     rs.f[0][tid] = acc_w;
     rs.f[1][tid] = chi_max;
-    if (lane == 0) rs.cnt[wave] = run_base;
+    if (lane == 0) {
+        rs.cnt[wave] = run_base;
+        rs.flags[wave] = wf;
+    }
     if constexpr (kCanStage) {
         if (staged && lane == 0) {
             sm.stage.cnt[wave] = min(min(run_base, seg_cap), (uint32_t)kStage);
@@ -585,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             }
         }
     }
-    double *row = cold_args<R>().partials + (size_t)blk * SR_LEDGER_COLS;
+    double *row = cold_args<R>().partials + (size_t)blk * kPartCols;
     const auto dsum = [&](int q) {
         const double v = ((rs.d[q][lane] + rs.d[q][lane + 64]) + rs.d[q][lane + 128]) +
                          rs.d[q][lane + 192];
@@ -609,25 +615,33 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
         if (lane == 0) {
             row[SR_LED_CLAMPED] = cl;
             row[SR_LED_PHOTONS] = (double)((rs.cnt[0] + rs.cnt[1]) + (rs.cnt[2] + rs.cnt[3]));
+            row[kPartFlags] = (double)(rs.flags[0] | rs.flags[1] | rs.flags[2] | rs.flags[3]);
+            row[kPartFlags + 1] = 0.0;
         }
     }
 }
 
-// Sum rows [lo, hi) of `in` (column SR_LED_CHI_MAX is a maximum) into out[b].
-// Each thread keeps all columns of a strided set of rows in registers, then the
-// block combines them with wave shuffles and LDS: a fixed order, so the
-// ledger is bit-reproducible.
+// Sum partial rows [lo, hi) of `in` (column SR_LED_CHI_MAX is a maximum, the
+// flags column an OR).  Each thread keeps all columns of a strided set of rows
+// in registers, then the block combines them with wave shuffles and LDS: a
+// fixed order, so the ledger is bit-reproducible.  With status == nullptr the
+// block writes partial row out[b]; otherwise (a single block) it writes the
+// ledger row out[0..SR_LEDGER_COLS) and ORs the flags into *status (one atomic
+// per reduction).
 __global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__restrict__ in,
                                                                int64_t n_rows, int64_t per_block,
-                                                               double *__restrict__ out) {
+                                                               double *__restrict__ out,
+                                                               uint32_t *__restrict__ status) {
     __shared__ double s[kWaves][SR_LEDGER_COLS];
+    __shared__ uint32_t sf[kWaves];
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = min(lo + per_block, n_rows);
     double acc[SR_LEDGER_COLS];
+    uint32_t fl = 0;
 #pragma unroll
     for (int c = 0; c < SR_LEDGER_COLS; ++c) acc[c] = 0.0;
     for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-        const double2 *row = (const double2 *)(in + r * SR_LEDGER_COLS);
+        const double2 *row = (const double2 *)(in + r * kPartCols);
 #pragma unroll
         for (int q = 0; q < SR_LEDGER_COLS / 2; ++q) {
             const double2 v = row[q];
@@ -635,6 +649,7 @@ __global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__r
             acc[c0] = c0 == SR_LED_CHI_MAX ? fmax(acc[c0], v.x) : acc[c0] + v.x;
             acc[c1] = c1 == SR_LED_CHI_MAX ? fmax(acc[c1], v.y) : acc[c1] + v.y;
         }
+        fl |= (uint32_t)row[kPartFlags / 2].x;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -646,12 +661,24 @@ __global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__r
         }
         if (lane == 0) s[wave][c] = v;
     }
+    for (int o = 32; o > 0; o >>= 1) fl |= (uint32_t)__shfl_xor((int)fl, o, 64);
+    if (lane == 0) sf[wave] = fl;
     __syncthreads();
     if (threadIdx.x < SR_LEDGER_COLS) {
         const int c = threadIdx.x;
         double v = s[0][c];
         for (int w = 1; w < kWaves; ++w) v = c == SR_LED_CHI_MAX ? fmax(v, s[w][c]) : v + s[w][c];
-        out[(int64_t)blockIdx.x * SR_LEDGER_COLS + c] = v;
+        if (status) out[c] = v;
+        else out[(int64_t)blockIdx.x * kPartCols + c] = v;
+    } else if (threadIdx.x == SR_LEDGER_COLS) {
+        uint32_t f = 0;
+        for (int w = 0; w < kWaves; ++w) f |= sf[w];
+        if (status) {
+            if (f) atomicOr(status, f);
+        } else {
+            out[(int64_t)blockIdx.x * kPartCols + kPartFlags] = (double)f;
+            out[(int64_t)blockIdx.x * kPartCols + kPartFlags + 1] = 0.0;
+        }
     }
 }
 
@@ -672,14 +699,16 @@ int reduce_ledger(const sr_ledger *led, int64_t n_chunks, int64_t row, hipStream
     if (n_chunks == 0) {
         zero_row_kernel<<<1, 64, 0, st>>>(dst);
     } else if (n_chunks <= kReduceSingle) {
-        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(led->partials, n_chunks, n_chunks, dst);
+        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(led->partials, n_chunks, n_chunks, dst,
+                                                   led->status);
     } else {
         int64_t per = (n_chunks + kReduceL1Blocks - 1) / kReduceL1Blocks;
         if (per < kReducePerBlock) per = kReducePerBlock;
         const int64_t nb = (n_chunks + per - 1) / per;
-        double *mid = led->partials + n_chunks * SR_LEDGER_COLS;
-        ledger_reduce_kernel<<<(unsigned)nb, kBlock, 0, st>>>(led->partials, n_chunks, per, mid);
-        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(mid, nb, nb, dst);
+        double *mid = led->partials + n_chunks * kPartCols;
+        ledger_reduce_kernel<<<(unsigned)nb, kBlock, 0, st>>>(led->partials, n_chunks, per, mid,
+                                                              nullptr);
+        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(mid, nb, nb, dst, led->status);
     }
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
@@ -811,7 +840,6 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.ph.k = ph->k;
     a.ph.step = ph->step;
     a.ph.partials = led->partials;
-    a.ph.status = led->status;
 
     hipStream_t st = (hipStream_t)stream;
     const dim3 grd((unsigned)partial_rows(n_chunks)), blk(kBlock);
@@ -897,7 +925,7 @@ using namespace sr;
 
 extern "C" int64_t sr_ledger_partials(int64_t n_chunks) {
     if (n_chunks < 0) return 0;
-    return (partial_rows(n_chunks) + kReduceL1Blocks + 1) * SR_LEDGER_COLS;
+    return (partial_rows(n_chunks) + kReduceL1Blocks + 1) * kPartCols;
 }
 
 extern "C" int sr_eval_push(const sr_particles_f32 *parts, const sr_fields_f32 *fields,
@@ -945,7 +973,8 @@ extern "C" int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_
 
 extern "C" int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row,
                                 void *stream) {
-    if (!ledger || !ledger->rows || !ledger->partials || n_chunks < 0 || n_chunks > 0x7FFFFFFF ||
+    if (!ledger || !ledger->rows || !ledger->partials || !ledger->status || n_chunks < 0 ||
+        n_chunks > 0x7FFFFFFF ||
         row < 0 || row >= ledger->n_rows || ledger->partials_len < sr_ledger_partials(n_chunks))
         return SR_E_INVAL;
     return reduce_ledger(ledger, n_chunks, row, (hipStream_t)stream);
