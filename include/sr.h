@@ -311,6 +311,22 @@ int sr_spectrum_histogram(const sr_photon_buf *photons, const sr_chunking *chunk
                           double *work, void *stream);
 int64_t sr_hist_work(int32_t n_bins);
 
+/* Angular distribution of the emitted energy over the front hemisphere around
+ * `axis` (section "Comparison and benchmarking", Fig. 4: the front hemisphere
+ * around the laser propagation direction):
+ *   hist[it * n_phi + ip] += sum w*eps over the stored photons with theta, the
+ *   angle between dir and axis, in [it, it+1) * (pi/2)/n_theta, and phi, the
+ *   azimuth about the axis measured from the part of `ref` perpendicular to it
+ *   (towards axis x ref), in [ip, ip+1) * 2 pi/n_phi;
+ *   hist[n_theta * n_phi] += sum w*eps of the photons with dir . axis <= 0.
+ * axis and ref: host vectors (any length; ref not parallel to axis).  hist is
+ * device FP64 [n_theta * n_phi + 1]; work a device workspace of
+ * sr_angular_work(n_theta, n_phi) doubles; n_theta * n_phi <= 4096. */
+int sr_angular_histogram(const sr_photon_buf *photons, const sr_chunking *chunks, int64_t n,
+                         const double axis[3], const double ref[3], int32_t n_theta,
+                         int32_t n_phi, double *hist, double *work, void *stream);
+int64_t sr_angular_work(int32_t n_theta, int32_t n_phi);
+
 /* Prescribed field for the workloads: two counter-propagating circularly
  * polarised waves of amplitude a0 along x (k = omega = 1) forming
  *   E = 2 a0 cos x (0, cos t, -sin t),  B = 2 a0 sin x (0, -cos t, sin t),

@@ -104,6 +104,10 @@ SIGNATURES = {
     "sr_spectrum_histogram": (C.c_int, [C.POINTER(PhotonBuf), C.POINTER(Chunking), _I64, _D, _D,
                                         _I32, _P, _P, _P]),
     "sr_hist_work": (C.c_int64, [_I32]),
+    "sr_angular_histogram": (C.c_int, [C.POINTER(PhotonBuf), C.POINTER(Chunking), _I64,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), _I32, _I32,
+                                       _P, _P, _P]),
+    "sr_angular_work": (C.c_int64, [_I32, _I32]),
     "sr_field_standing_wave": (C.c_int, [P3, P3, C.POINTER(Grid), _D, _D, _P]),
     "sr_sort_particles": (C.c_int, [C.POINTER(Particles32), C.POINTER(Particles32),
                                     C.POINTER(Grid), C.POINTER(C.c_int32), _P, _P]),

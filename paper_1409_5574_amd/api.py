@@ -469,6 +469,28 @@ def spectrum_histogram(photons: PhotonBuffer, n: int, eps_lo: float, eps_hi: flo
                                         _ptr(hist), _ptr(work), _stream()), "sr_spectrum_histogram")
 
 
+def angular_histogram(photons: PhotonBuffer, n: int, axis, ref, n_theta: int, n_phi: int,
+                      hist: torch.Tensor, work: torch.Tensor, start: torch.Tensor | None = None):
+    """hist[n_theta*n_phi + 1] += energy-weighted (theta, phi) map of the stored
+    photons over the front hemisphere around `axis` (last entry: back hemisphere)."""
+    cs = L.Chunking()
+    cs.n_chunks = n_chunks_uniform(n) if start is None else start.numel() - 1
+    cs.start = None if start is None else start.data_ptr()
+    phs = photons.struct()
+    ax = (C.c_double * 3)(*[float(v) for v in axis])
+    rf = (C.c_double * 3)(*[float(v) for v in ref])
+    L.check(lib().sr_angular_histogram(C.byref(phs), C.byref(cs), n, ax, rf, int(n_theta),
+                                       int(n_phi), _ptr(hist), _ptr(work), _stream()),
+            "sr_angular_histogram")
+
+
+def angular_work(n_theta: int, n_phi: int) -> torch.Tensor:
+    nw = int(lib().sr_angular_work(n_theta, n_phi))
+    if nw < 0:
+        raise L.SRError("sr_angular_work: bad bin counts")
+    return torch.zeros(nw, device=DEV, dtype=torch.float64)
+
+
 def hist_work(n_bins: int) -> torch.Tensor:
     return torch.zeros(int(lib().sr_hist_work(n_bins)), device=DEV, dtype=torch.float64)
 

@@ -247,10 +247,94 @@ __global__ __launch_bounds__(256) void hist_reduce(const double *work, int nbloc
     if (threadIdx.x == 0) hist[b] += s[0];
 }
 
+// Energy-weighted angular map of the stored photons (the angular distribution
+// of emitted energy of section "Comparison and benchmarking", Fig. 4): theta is
+// the angle from the axis, binned uniformly on [0, pi/2) (the front
+// hemisphere); phi is the azimuth about the axis from e1 towards e2, binned on
+// [0, 2 pi).  Photons with dir . axis <= 0 go to the last bin (the back
+// hemisphere).  One lane per chunk, as hist_kernel; block partials to work.
+constexpr int kMaxAngularBins = 4096;
+__global__ __launch_bounds__(256) void angular_kernel(sr_photon_buf ph, const int64_t *start,
+                                                      int64_t n_chunks, int64_t n, float3 ax,
+                                                      float3 e1, float3 e2, int n_theta,
+                                                      int n_phi, double *work) {
+    extern __shared__ double sh[];   // [n_theta * n_phi + 1]
+    const int nvals = n_theta * n_phi + 1;
+    for (int b = threadIdx.x; b < nvals; b += blockDim.x) sh[b] = 0.0;
+    __syncthreads();
+    const float t_scale = (float)n_theta * 0.63661977236758134f;   // n_theta / (pi/2)
+    const float p_scale = (float)n_phi * 0.15915494309189535f;     // n_phi / (2 pi)
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s0 = start ? start[c] : c * (int64_t)kChunk;
+        const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kChunk, n);
+        const int64_t cap = (e0 - s0) * ph.per_particle;
+        const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
+        const int64_t base = s0 * ph.per_particle;
+        for (int64_t q = 0; q < cnt; ++q) {
+            const int64_t o = base + q;
+            const float e = ph.eps[o] * ph.w[o];
+            const float d0 = ph.dir[0][o], d1 = ph.dir[1][o], d2 = ph.dir[2][o];
+            const float cz = d0 * ax.x + d1 * ax.y + d2 * ax.z;
+            int bin = nvals - 1;
+            if (cz > 0.0f) {
+                const float theta = acosf(fminf(cz, 1.0f));
+                const int it = min((int)(theta * t_scale), n_theta - 1);
+                float phi = atan2f(d0 * e2.x + d1 * e2.y + d2 * e2.z, d0 * e1.x + d1 * e1.y + d2 * e1.z);
+                if (phi < 0.0f) phi += 6.2831853071795865f;
+                const int ip = min(max((int)(phi * p_scale), 0), n_phi - 1);
+                bin = it * n_phi + ip;
+            }
+            atomicAdd(&sh[bin], (double)e);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nvals; b += blockDim.x)
+        work[(int64_t)blockIdx.x * nvals + b] = sh[b];
+}
+
 }  // namespace
 }  // namespace sr
 
 using namespace sr;
+
+extern "C" int64_t sr_angular_work(int32_t n_theta, int32_t n_phi) {
+    if (n_theta < 1 || n_phi < 1 || (int64_t)n_theta * n_phi > kMaxAngularBins) return -1;
+    return (int64_t)kHistBlocks * ((int64_t)n_theta * n_phi + 1);
+}
+
+extern "C" int sr_angular_histogram(const sr_photon_buf *ph, const sr_chunking *chunks, int64_t n,
+                                    const double axis[3], const double ref[3], int32_t n_theta,
+                                    int32_t n_phi, double *hist, double *work, void *stream) {
+    if (!ph || !chunks || !axis || !ref || !hist || !work || n < 0 || n_theta < 1 || n_phi < 1 ||
+        (int64_t)n_theta * n_phi > kMaxAngularBins || !ph->seg_count)
+        return SR_E_INVAL;
+    const double an = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    if (!(an > 0.0)) return SR_E_INVAL;
+    const double a[3] = {axis[0] / an, axis[1] / an, axis[2] / an};
+    const double ra = ref[0] * a[0] + ref[1] * a[1] + ref[2] * a[2];
+    double u[3] = {ref[0] - ra * a[0], ref[1] - ra * a[1], ref[2] - ra * a[2]};
+    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(un > 1e-12 * sqrt(ref[0] * ref[0] + ref[1] * ref[1] + ref[2] * ref[2])) || !(un > 0.0))
+        return SR_E_INVAL;   // ref must not be parallel to the axis
+    for (int q = 0; q < 3; ++q) u[q] /= un;
+    const double v[3] = {a[1] * u[2] - a[2] * u[1], a[2] * u[0] - a[0] * u[2],
+                         a[0] * u[1] - a[1] * u[0]};
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
+    if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
+    if (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2]) return SR_E_INVAL;
+    const int nvals = n_theta * n_phi + 1;
+    const int64_t groups = (n_chunks + 255) / 256;
+    const int nb = (int)(groups < kHistBlocks ? groups : kHistBlocks);
+    hipStream_t st = (hipStream_t)stream;
+    angular_kernel<<<nb, 256, sizeof(double) * nvals, st>>>(
+        *ph, chunks->start, n_chunks, n, make_float3((float)a[0], (float)a[1], (float)a[2]),
+        make_float3((float)u[0], (float)u[1], (float)u[2]),
+        make_float3((float)v[0], (float)v[1], (float)v[2]), n_theta, n_phi, work);
+    hist_reduce<<<nvals, 256, 0, st>>>(work, nb, nvals, hist);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
 
 extern "C" int sr_field_standing_wave(float *e[3], float *b[3], const sr_grid *grid, double a0,
                                       double t, void *stream) {

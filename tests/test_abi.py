@@ -53,6 +53,8 @@ def test_strerror_and_sizes(lib):
     assert lib.sr_ledger_partials(100) >= 100 * L.SR_LEDGER_COLS
     assert lib.sr_ledger_partials(-1) == 0
     assert lib.sr_hist_work(64) > 0 and lib.sr_hist_work(0) == -1 and lib.sr_hist_work(5000) == -1
+    assert lib.sr_angular_work(45, 72) > 45 * 72
+    assert lib.sr_angular_work(0, 8) == -1 and lib.sr_angular_work(65, 64) == -1
     g = L.Grid()
     g.dim = 3
     for a in range(3):
@@ -140,3 +142,24 @@ def test_eval_push_rejects_bad_arguments_on_host(lib):
     grid.dim = 0
     assert lib.sr_eval_push(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), None, None, None,
                             None) == L.SR_OK
+
+
+def test_angular_histogram_rejects_bad_arguments_on_host(lib):
+    from paper_1409_5574_amd import _lib as L
+    ph = L.PhotonBuf()
+    ch = L.Chunking(1, None)
+    out = C.c_void_p(16)
+    ax = (C.c_double * 3)(1.0, 0.0, 0.0)
+    rf = (C.c_double * 3)(0.0, 1.0, 0.0)
+    # null photon buffer, no segment counts
+    assert lib.sr_angular_histogram(None, C.byref(ch), 10, ax, rf, 8, 8, out, out, None) == L.SR_E_INVAL
+    assert lib.sr_angular_histogram(C.byref(ph), C.byref(ch), 10, ax, rf, 8, 8, out, out,
+                                    None) == L.SR_E_INVAL
+    ph.seg_count = out
+    # zero axis, reference parallel to the axis, bad bin counts: caught before a launch
+    zero = (C.c_double * 3)(0.0, 0.0, 0.0)
+    par = (C.c_double * 3)(-3.0, 0.0, 0.0)
+    for a, r, nt, nph in ((zero, rf, 8, 8), (ax, par, 8, 8), (ax, zero, 8, 8), (ax, rf, 0, 8),
+                          (ax, rf, 8, -1), (ax, rf, 4096, 2)):
+        assert lib.sr_angular_histogram(C.byref(ph), C.byref(ch), 10, a, r, nt, nph, out, out,
+                                        None) == L.SR_E_INVAL

@@ -126,6 +126,59 @@ def test_spectrum_histogram_matches_host(sr, table):
     assert np.abs(h[nb:] - hw).sum() <= 1e-5 * hw.sum() + 2
 
 
+def _angular_reference(ph, axis, ref, nt, nph):
+    """FP64 binning of the gathered photons by (theta, phi) about axis, with
+    each photon's distance to the nearest bin edge (theta, phi in radians, the
+    phi distance scaled by sin theta: the arc length it stands for)."""
+    a = np.asarray(axis, np.float64) / np.linalg.norm(axis)
+    r = np.asarray(ref, np.float64)
+    e1 = r - (r @ a) * a
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(a, e1)
+    d = ph["dir"].astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    en = (ph["eps"].astype(np.float32) * ph["w"].astype(np.float32)).astype(np.float64)
+    cz = d @ a
+    theta = np.arccos(np.clip(cz, -1.0, 1.0))
+    phi = np.mod(np.arctan2(d @ e2, d @ e1), 2 * np.pi)
+    wt, wp = (np.pi / 2) / nt, 2 * np.pi / nph
+    it = np.minimum((theta / wt).astype(np.int64), nt - 1)
+    ip = np.minimum((phi / wp).astype(np.int64), nph - 1)
+    front = cz > 0
+    b = np.where(front, it * nph + ip, nt * nph)
+    h = np.bincount(b, weights=en, minlength=nt * nph + 1)
+    t_edge = np.abs(theta / wt - np.round(theta / wt)) * wt
+    p_edge = np.abs(phi / wp - np.round(phi / wp)) * wp * np.sin(theta)
+    return h, en, np.minimum(t_edge, p_edge), np.abs(cz)
+
+
+def test_angular_histogram_matches_host(sr, table):
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    n = 20000
+    _say("angular histogram")
+    parts, photons, ledger = _step_for_photons(sr, table, cfg, n, 2, 2000.0)
+    ph = photons.gather(n)
+    assert ph["count"] > 1000
+    for axis, ref, nt, nph in (((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45, 72),
+                               ((0.3, -2.0, 0.5), (1.0, 1.0, 1.0), 7, 13),
+                               ((-1.0, 0.0, 0.0), (0.0, 0.0, 5.0), 1, 1),
+                               ((0.0, 0.0, 1.0), (1.0, 0.0, 0.0), 64, 64)):
+        _say(f"angular histogram: axis {axis} ref {ref} bins {nt}x{nph}")
+        hist = torch.zeros(nt * nph + 1, device="cuda", dtype=torch.float64)
+        work = sr.angular_work(nt, nph)
+        sr.angular_histogram(photons, n, axis, ref, nt, nph, hist, work)
+        sr.angular_histogram(photons, n, axis, ref, nt, nph, hist, work)   # accumulates
+        torch.cuda.synchronize()
+        h = hist.cpu().numpy() / 2
+        href, en, edge, cz = _angular_reference(ph, axis, ref, nt, nph)
+        # every photon lands in exactly one bin: the totals agree to summation order
+        assert h.sum() == pytest.approx(en.sum(), rel=1e-12)
+        # photons within float rounding of a bin edge (or of the hemisphere
+        # boundary) may land in the neighbour bin; nowhere else may they differ
+        slack = en[(edge <= 2e-5) | (cz <= 1e-6)].sum()
+        assert np.abs(h - href).sum() <= 2 * slack + 1e-12 * en.sum(), (axis, nt, nph)
+
+
 def test_photon_overflow_is_counted_and_ledgered(sr, table):
     cfg = synth.config("c2", grid=(64, 64, 1))
     n = 4000
