@@ -22,7 +22,7 @@ SRC_PATH = os.path.join(_HERE, "sr_oracle.c")
 FIELD_ANALYTIC, FIELD_2D, FIELD_3D = 0, 2, 3
 RECOIL_NONE, RECOIL_PHOTON, RECOIL_LL = 0, 1, 2
 DN_WEIGHT, DN_CLAMP = 0, 1
-SAMPLER_S, SAMPLER_DIRECT = 0, 1
+SAMPLER_S, SAMPLER_DIRECT, SAMPLER_QUANTUM = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -84,6 +84,15 @@ def lib():
         L.orc_proposal_invert.argtypes = [d, d, p, p]
         L.orc_trial_dn.restype = d
         L.orc_trial_dn.argtypes = [d, d, d, d, p]
+        L.orc_bessel_K.restype = d
+        L.orc_bessel_K.argtypes = [d, d, d]
+        L.orc_bessel_K_tail.restype = d
+        L.orc_bessel_K_tail.argtypes = [d, d, d]
+        L.orc_quantum_kernel.restype = d
+        L.orc_quantum_kernel.argtypes = [d, d, d]
+        L.orc_quantum_kernel_array.argtypes = [i64, p, p, p, d]
+        L.orc_trial_dn_quantum.restype = d
+        L.orc_trial_dn_quantum.argtypes = [d, d, d, d, p]
         L.orc_boris.argtypes = [p, p, p, d, d, p]
         L.orc_heff.restype = d
         L.orc_heff.argtypes = [p, p, d, p, p]
@@ -118,6 +127,33 @@ def energy_integral(x: float, h: float = 0.1) -> float:
 
 def inv_number_cdf(chi: float, u: float, kin_cut: bool) -> float:
     return lib().orc_inv_number_cdf(float(chi), float(u), int(bool(kin_cut)))
+
+
+def bessel_K(nu: float, xi: float, h: float = 0.1) -> float:
+    return lib().orc_bessel_K(float(nu), float(xi), h)
+
+
+def bessel_K_tail(nu: float, xi: float, h: float = 0.1) -> float:
+    return lib().orc_bessel_K_tail(float(nu), float(xi), h)
+
+
+def quantum_kernel(x, chi, h: float = 0.1) -> np.ndarray:
+    """Q(x, chi), the quantum-corrected counterpart of F(x)/x (broadcasts)."""
+    xb, cb = np.broadcast_arrays(np.asarray(x, np.float64), np.asarray(chi, np.float64))
+    xb = np.ascontiguousarray(xb.ravel())
+    cb = np.ascontiguousarray(cb.ravel())
+    out = np.empty_like(xb)
+    lib().orc_quantum_kernel_array(xb.size, _ptr(xb), _ptr(cb), _ptr(out), h)
+    return out
+
+
+def trial_dn_quantum(Rp: float, rate: float, chi: float, Pa: float | None = None):
+    """dN of one quantum trial at uniform R' (returns (dN, x))."""
+    if Pa is None:
+        Pa = proposal_Pa_f32()
+    x = C.c_double()
+    dn = lib().orc_trial_dn_quantum(float(Rp), float(Pa), float(rate), float(chi), C.byref(x))
+    return dn, x.value
 
 
 def proposal_a() -> float:

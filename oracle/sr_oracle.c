@@ -212,6 +212,80 @@ double orc_trial_dn(double Rp, double Pa, double rate, double xcut, double *x_ou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Quantum-corrected spectrum for chi approaching 1 (section "Limitations":   */
+/* the classical expression fails there and a QED treatment is needed; the   */
+/* paper gives no formula).  Reading: the quantum synchrotron spectrum of    */
+/* Baier & Katkov / Ritus, written in the method's variable x = omega/omega_c */
+/* with delta = hbar omega / (gamma m c^2) = 1.5 chi x and xi = x / (1-delta): */
+/*   dN/(dt dx) = (sqrt3/2pi) alpha H_eff Q(x, chi),                          */
+/*   Q = (1 - delta + 1/(1-delta)) K_{2/3}(xi) - int_xi^inf K_{1/3}(t) dt,    */
+/* and Q = 0 for delta >= 1 (no photon above the emitter's energy).  As      */
+/* chi -> 0, Q -> 2 K_{2/3}(x) - int_x^inf K_{1/3} = int_x^inf K_{5/3} =      */
+/* F(x)/x, the classical kernel of the method.                               */
+/* ------------------------------------------------------------------------ */
+
+/* K_nu(xi) = int_0^inf exp(-xi cosh s) cosh(nu s) ds (entire integrand: the  */
+/* trapezoid rule converges faster than any power of h).                      */
+double orc_bessel_K(double nu, double xi, double h)
+{
+    if (!(xi > 0.0)) return INFINITY;
+    if (h <= 0.0) h = 0.1;
+    const double s_peak = asinh(fabs(nu) / xi);
+    double sum = 0.0;
+    for (long j = 0; j < 2000000; ++j) {
+        const double s = j * h;
+        const double term = exp(-xi * cosh(s) + log_cosh(nu * s)) * (j == 0 ? 0.5 : 1.0);
+        sum += term;
+        if (s > s_peak && term <= 1e-20 * sum) break;
+    }
+    return h * sum;
+}
+
+/* int_xi^inf K_nu(t) dt = int_0^inf exp(-xi cosh s) cosh(nu s) / cosh s ds  */
+/* (the t-integral of the representation above done in closed form).         */
+double orc_bessel_K_tail(double nu, double xi, double h)
+{
+    if (!(xi > 0.0)) return INFINITY;
+    if (h <= 0.0) h = 0.1;
+    const double s_peak = asinh(fabs(nu) / xi) + 1.0;
+    double sum = 0.0;
+    for (long j = 0; j < 2000000; ++j) {
+        const double s = j * h;
+        const double term = exp(-xi * cosh(s) + log_cosh(nu * s) - log_cosh(s)) *
+                            (j == 0 ? 0.5 : 1.0);
+        sum += term;
+        if (s > s_peak && term <= 1e-20 * sum) break;
+    }
+    return h * sum;
+}
+
+double orc_quantum_kernel(double x, double chi, double h)
+{
+    if (!(x > 0.0)) return 0.0;
+    const double delta = 1.5 * chi * x;
+    if (!(delta < 1.0)) return 0.0;
+    const double om = 1.0 - delta;
+    const double xi = x / om;
+    return (om + 1.0 / om) * orc_bessel_K(2.0 / 3.0, xi, h) - orc_bessel_K_tail(1.0 / 3.0, xi, h);
+}
+
+void orc_quantum_kernel_array(int64_t n, const double *x, const double *chi, double *out, double h)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_quantum_kernel(x[i], chi[i], h);
+}
+
+/* One trial of the quantum sampler: the proposal of the classical method with */
+/* the quantum kernel in place of F(x)/x, so dN = rate x Q / (x S) = rate Q / S. */
+double orc_trial_dn_quantum(double Rp, double Pa, double rate, double chi, double *x_out)
+{
+    double x, S;
+    orc_proposal_invert(Rp, Pa, &x, &S);
+    if (x_out) *x_out = x;
+    return rate * orc_quantum_kernel(x, chi, 0.0) / S;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Boris push (the scheme the section "Numerical implementation" describes:  */
 /* half electric kick, magnetic rotation, half electric kick).               */
 /* ------------------------------------------------------------------------ */
@@ -397,6 +471,8 @@ static void step_one(int64_t i, double *x, double *y, double *z,
         double xs = 0.0, dN = 0.0;
         if (prm->sampler == ORC_SAMPLER_S) {
             dN = orc_trial_dn(Rp, Pa, rate, xcut, &xs);         /* steps 3-5 */
+        } else if (prm->sampler == ORC_SAMPLER_QUANTUM) {
+            dN = orc_trial_dn_quantum(Rp, Pa, rate, chi, &xs);  /* steps 3-5, quantum kernel */
         } else {
             dN = direct_W;
         }

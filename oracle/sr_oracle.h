@@ -52,7 +52,25 @@ double orc_heff(const double p_old[3], const double p_new[3], double dt,
 enum { ORC_FIELD_ANALYTIC = 0, ORC_FIELD_2D = 2, ORC_FIELD_3D = 3 };
 enum { ORC_RECOIL_NONE = 0, ORC_RECOIL_PHOTON = 1, ORC_RECOIL_LL = 2 };
 enum { ORC_DN_WEIGHT = 0, ORC_DN_CLAMP = 1 };
-enum { ORC_SAMPLER_S = 0, ORC_SAMPLER_DIRECT = 1 };
+/* ORC_SAMPLER_S: the proposal S(x) and F(x)/x; ORC_SAMPLER_DIRECT: total rate
+ * and the inverse number CDF; ORC_SAMPLER_QUANTUM: the proposal S(x) with the
+ * quantum kernel Q(x, chi) below (kin_cut is implied by Q). */
+enum { ORC_SAMPLER_S = 0, ORC_SAMPLER_DIRECT = 1, ORC_SAMPLER_QUANTUM = 2 };
+/* Modified Bessel function K_nu(xi) = int_0^inf exp(-xi cosh s) cosh(nu s) ds
+ * and its tail int_xi^inf K_nu = int_0^inf exp(-xi cosh s) cosh(nu s)/cosh s ds,
+ * by the trapezoid rule with step h (h <= 0: 0.1). */
+double orc_bessel_K(double nu, double xi, double h);
+double orc_bessel_K_tail(double nu, double xi, double h);
+/* Quantum-corrected emission kernel (reading for chi approaching 1, section
+ * "Limitations"; the quantum synchrotron spectrum of Baier-Katkov / Ritus):
+ * with delta = 1.5 chi x and xi = x/(1-delta),
+ *   Q(x, chi) = (1 - delta + 1/(1-delta)) K_{2/3}(xi) - int_xi^inf K_{1/3},
+ * zero for delta >= 1; dN/(dt dx) = (sqrt3/2pi) alpha H_eff Q, and
+ * Q(x, 0) = F(x)/x. */
+double orc_quantum_kernel(double x, double chi, double h);
+void orc_quantum_kernel_array(int64_t n, const double *x, const double *chi, double *out, double h);
+/* dN of one quantum trial: rate * Q(x, chi) / S(x) at the proposal's x(R'). */
+double orc_trial_dn_quantum(double Rp, double Pa, double rate, double chi, double *x_out);
 
 typedef struct {
     int32_t kind;          /* ORC_FIELD_* */
