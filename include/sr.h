@@ -121,7 +121,16 @@ typedef struct {
 
 enum { SR_SAMPLER_S = 0,          /* proposal S(x), section "Monte Carlo method"     */
        SR_SAMPLER_TABLE = 1,      /* direct: total rate, x from the inverse-CDF table */
-       SR_SAMPLER_MLP = 2 };      /* direct: total rate, x from the MLP surrogate     */
+       SR_SAMPLER_MLP = 2,        /* direct: total rate, x from the MLP surrogate     */
+       SR_SAMPLER_QUANTUM = 3 };  /* proposal S(x) with the quantum-corrected kernel
+                                     (chi approaching 1, section "Limitations"): the
+                                     quantum synchrotron spectrum, delta = 1.5 chi x,
+                                     xi = x/(1-delta),
+                                     dN = dt (sqrt3/2pi) alpha H_eff Q / S(x),
+                                     Q = (1-delta+1/(1-delta)) K_{2/3}(xi)
+                                         - int_xi^inf K_{1/3},
+                                     Q = 0 for delta >= 1 (kin_cut is implied);
+                                     Q -> F(x)/x as chi -> 0                         */
 enum { SR_RECOIL_NONE = 0, SR_RECOIL_PHOTON = 1, SR_RECOIL_LL = 2 };
 enum { SR_DN_WEIGHT = 0, SR_DN_CLAMP = 1 };
 
@@ -215,6 +224,8 @@ typedef struct {
     int32_t r_nodes;        /* nodes of the cut fraction r(chi)                     */
     double r_log10chi_lo, r_log10chi_hi;
     int32_t g_pieces;       /* cubic pieces of the trial density log2 F/(x S) in R' */
+    int32_t q_pieces;       /* cubic pieces (each a pair) of the quantum kernel in
+                               log2 xi                                              */
 } sr_table_info;
 int sr_table_query(const sr_table *tab, sr_table_info *info);
 
@@ -228,6 +239,14 @@ int sr_eval_synchrotron_F(const sr_table *tab, const float *x, float *out, int64
  * log2 F/(x S) built in FP64 as a function of R' itself. */
 int sr_eval_trial(const sr_table *tab, const uint32_t *a, const float *rate, const float *chi,
                   int32_t kin_cut, float *out_dn, float *out_x, int64_t n, void *stream);
+
+/* dN of one quantum trial (SR_SAMPLER_QUANTUM) for n device (word a, rate, chi)
+ * triples: out_dn = rate Q(x, chi)/S(x), out_x = x, with x and S from the
+ * proposal exactly as sr_eval_trial; the emission kernel's device function.
+ * Q is read from a table of log2 K_{2/3} and log2 int K_{1/3} in log2 xi built
+ * in FP64; xi >= 128 (Q < e^-128) gives 0. */
+int sr_eval_trial_quantum(const sr_table *tab, const uint32_t *a, const float *rate,
+                          const float *chi, float *out_dn, float *out_x, int64_t n, void *stream);
 
 /* Gather, Boris push and H_eff of every particle, exactly as the emission step
  * computes them (section "Numerical implementation": E and B interpolated to

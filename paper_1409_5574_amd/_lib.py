@@ -18,7 +18,7 @@ SR_W_PHOTON_OVERFLOW, SR_W_RECOIL_CLAMP, SR_W_NONFINITE = 1, 2, 4
  SR_LED_WEIGHT, SR_LED_CHI_MAX) = range(8)
 SR_LEDGER_COLS = 8
 SR_CHUNK = 64
-SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP = 0, 1, 2
+SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP, SR_SAMPLER_QUANTUM = 0, 1, 2, 3
 SR_RECOIL_NONE, SR_RECOIL_PHOTON, SR_RECOIL_LL = 0, 1, 2
 SR_DN_WEIGHT, SR_DN_CLAMP = 0, 1
 SR_MLP_PARAMS = 8577
@@ -69,7 +69,8 @@ class Ledger(C.Structure):
 class TableInfo(C.Structure):
     _fields_ = [("proposal_pa", C.c_float), ("f_pieces", C.c_int32), ("proposal_a", C.c_double),
                 ("t1_pieces", C.c_int32), ("r_nodes", C.c_int32), ("r_log10chi_lo", C.c_double),
-                ("r_log10chi_hi", C.c_double), ("g_pieces", C.c_int32)]
+                ("r_log10chi_hi", C.c_double), ("g_pieces", C.c_int32),
+                ("q_pieces", C.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol include/sr.h declares
@@ -80,6 +81,7 @@ SIGNATURES = {
     "sr_table_query": (C.c_int, [_P, C.POINTER(TableInfo)]),
     "sr_eval_synchrotron_F": (C.c_int, [_P, _P, _P, _I64, _P]),
     "sr_eval_trial": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _I64, _P]),
+    "sr_eval_trial_quantum": (C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _P]),
     "sr_philox": (C.c_int, [_P, _U64, _P, _I64, _P]),
     "sr_gather_push_emit": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32),
                                       C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,

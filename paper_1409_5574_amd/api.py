@@ -72,6 +72,18 @@ def eval_trial(table: Table, a: torch.Tensor, rate: torch.Tensor, chi: torch.Ten
     return dn, xo
 
 
+def eval_trial_quantum(table: Table, a: torch.Tensor, rate: torch.Tensor, chi: torch.Tensor):
+    """dN = rate Q(x, chi)/S(x) and x of quantum trials (the emission kernel's code)."""
+    a = a.contiguous().to(DEV, torch.int32)
+    rate = rate.contiguous().to(DEV, torch.float32)
+    chi = chi.contiguous().to(DEV, torch.float32)
+    dn = torch.empty_like(rate)
+    xo = torch.empty_like(rate)
+    L.check(lib().sr_eval_trial_quantum(table.handle, _ptr(a), _ptr(rate), _ptr(chi), _ptr(dn),
+                                        _ptr(xo), a.numel(), _stream()), "sr_eval_trial_quantum")
+    return dn, xo
+
+
 def philox(ctr: torch.Tensor, seed: int) -> torch.Tensor:
     """ctr: [n,4] int32 (uint32 bit patterns) -> [n,4] int32."""
     ctr = ctr.contiguous().to(DEV, torch.int32)

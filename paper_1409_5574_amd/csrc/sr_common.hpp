@@ -82,12 +82,28 @@ constexpr int kGUpJ0 = 32;      // v from 1 ...
 constexpr int kGUpN = 736;      // ... to 24 (1 - R' = 2^-24)
 constexpr int kGTotal = kGLoN + kGUpN;
 
+// Quantum-corrected kernel table (the quantum synchrotron spectrum for chi
+// approaching 1, where section "Limitations" says the classical expression
+// fails).  With delta = 1.5 chi x and xi = x/(1 - delta) the per-unit-x kernel
+// is Q = (1 - delta + 1/(1 - delta)) K_{2/3}(xi) - int_xi^inf K_{1/3}.  Piece j
+// of t = log2 xi on [-19, 7) holds, as Hermite cubics in the local coordinate,
+//   qtab[2j]   : yA = log2 K_{2/3}(xi) + (2/3) t + xi log2 e
+//   qtab[2j+1] : yB = log2 int_xi^inf K_{1/3} + xi log2 e
+// (both slowly varying: the xi^{-2/3} and e^{-xi} behaviour is taken out).
+// xi >= 2^-18 always (x >= the proposal's smallest x); above xi = 128 the
+// kernel is below e^-128 and the trial is taken as dN = 0.
+constexpr int kQPerUnit = 16;
+constexpr int kQJ0 = -19 * kQPerUnit;
+constexpr int kQN = 26 * kQPerUnit;
+constexpr float kQXiMax = 128.0f;
+
 struct TableDev {
     const float4 *ftab;     // [kFTotal]
     float pa;               // binary32 branch point P(a)
     const float4 *t1;       // [kT1N]
     const float2 *r;        // [kRN] (r, 1 - r)
     const float4 *gtab;     // [kGTotal]
+    const float4 *qtab;     // [2 * kQN]
 };
 
 // ---------------------------------------------------------------------------
@@ -151,6 +167,36 @@ __device__ __forceinline__ float trial_x(uint32_t a, float lg, bool lower) {
         return s * __builtin_amdgcn_sqrtf(s);
     }
     return fmaf(-0.69314718055994531f, lg, -0.25131442828090605f);
+}
+
+// Quantum trial: dN / rate = Q(x, chi) / S(x) at the proposal's x(R') (the
+// classical recipe with the quantum kernel in place of F(x)/x), and x itself.
+// Zero at and above the kinematic edge delta = 1.5 chi x >= 1.
+__device__ __forceinline__ float quantum_q(uint32_t a, const float4 *__restrict__ qtab, float pa,
+                                           float chi, float &x) {
+    const float rp = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
+    const bool lower = rp <= pa;
+    const float lg = __builtin_amdgcn_logf(lower ? rp : 1.0f - rp);
+    x = trial_x(a, lg, lower);
+    // log2(1/S): lower S = (4/3) R'^{1/4}, upper S = 1 - R'
+    const float l2_inv_s = lower ? -fmaf(0.25f, lg, 0.41503749927884381f) : -lg;
+    const float delta = 1.5f * chi * x;
+    if (!(delta < 1.0f)) return 0.0f;
+    const float om = 1.0f - delta;
+    const float xi = x / om;
+    if (!(xi < kQXiMax)) return 0.0f;
+    const float t = __builtin_amdgcn_logf(xi);
+    const float u = t * (float)kQPerUnit;
+    int j = (int)floorf(u) - kQJ0;
+    j = min(max(j, 0), kQN - 1);
+    const float s = u - (float)(j + kQJ0);
+    const float4 ca = qtab[2 * j], cb = qtab[2 * j + 1];
+    const float ya = fmaf(fmaf(fmaf(ca.w, s, ca.z), s, ca.y), s, ca.x);
+    const float yb = fmaf(fmaf(fmaf(cb.w, s, cb.z), s, cb.y), s, cb.x);
+    const float c = om + 1.0f / om;
+    const float q = c * __builtin_amdgcn_exp2f(fmaf(-0.66666666666666667f, t, ya)) -
+                    __builtin_amdgcn_exp2f(yb);
+    return q * __builtin_amdgcn_exp2f(fmaf(-1.4426950408889634f, xi, l2_inv_s));
 }
 
 // Kinematic cut x > xc = 2/(3 chi) expressed on lg: on the lower branch
@@ -381,6 +427,7 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t G) {
 struct sr_table {
     float4 *ftab = nullptr;
     float4 *gtab = nullptr;
+    float4 *qtab = nullptr;
     float4 *t1 = nullptr;
     float2 *r = nullptr;
     float pa = 0.0f;

@@ -421,7 +421,7 @@ extern "C" int sr_mlp_make_batch(const sr_table *tab, uint64_t seed, uint64_t ba
     if (!tab || M < 0 || (M > 0 && (!feats || !target)) || !(log10chi_hi > log10chi_lo))
         return SR_E_INVAL;
     if (M == 0) return SR_OK;
-    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r, tab->gtab};
+    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r, tab->gtab, tab->qtab};
     make_batch_kernel<<<(unsigned)((M + 255) / 256), 256, 0, (hipStream_t)stream>>>(
         td, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)batch, kin_cut, (float)log10chi_lo,
         (float)log10chi_hi, (float2 *)feats, target, M);
@@ -433,7 +433,7 @@ extern "C" int sr_eval_direct(const sr_table *tab, const uint32_t *a, const floa
                               int32_t kin_cut, float *out_x, int64_t n, void *stream) {
     if (!tab || n < 0 || (n > 0 && (!a || !chi || !out_x))) return SR_E_INVAL;
     if (n == 0) return SR_OK;
-    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r, tab->gtab};
+    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r, tab->gtab, tab->qtab};
     eval_direct_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
         td, a, chi, kin_cut, out_x, n);
     SR_HIP_CHECK(hipGetLastError());

@@ -242,6 +242,11 @@ struct StepSmem<KMAX, SR_SAMPLER_TABLE> {
     LedgerSmem led;
     PhotonStage stage;
 };
+template <int KMAX>
+struct StepSmem<KMAX, SR_SAMPLER_QUANTUM> {
+    LedgerSmem led;
+    PhotonStage stage;
+};
 template <typename S>
 __device__ __forceinline__ LedgerSmem &ledger_smem(S &s) { return s.led; }
 
@@ -335,9 +340,10 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
         float delta_ph = 0.0f;                 // sum over trials of frac * eps
         uint32_t wave_tot = 0;
         float2 rr = make_float2(1.0f, 0.0f);
-        if (SAMPLER != SR_SAMPLER_S && active && a.kin_cut) rr = r_lookup(a.tab.r, chif);
-        const float rate = !active ? 0.0f
-                         : (SAMPLER == SR_SAMPLER_S ? a.rate_c * Hf : a.direct_c * Hf * rr.x);
+        if (SAMPLER != SR_SAMPLER_S && SAMPLER != SR_SAMPLER_QUANTUM && active && a.kin_cut)
+            rr = r_lookup(a.tab.r, chif);
+        constexpr bool kProposal = SAMPLER == SR_SAMPLER_S || SAMPLER == SR_SAMPLER_QUANTUM;
+        const float rate = !active ? 0.0f : (kProposal ? a.rate_c * Hf : a.direct_c * Hf * rr.x);
         if constexpr (SAMPLER != SR_SAMPLER_MLP) {
             const TrialCut cut = trial_cut(SAMPLER == SR_SAMPLER_S && a.kin_cut != 0, chif);
             uint4 words = make_uint4(0, 0, 0, 0);
@@ -349,11 +355,13 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                                           a.seed_lo, a.seed_hi);
                 const uint32_t wa = (k & 1) ? words.z : words.x;
                 const uint32_t wb = (k & 1) ? words.w : words.y;
-                float dn = rate, lg = 0.0f;
+                float dn = rate, lg = 0.0f, xq = 0.0f;
                 bool lower = true;
                 if (SAMPLER == SR_SAMPLER_S) {
                     dn = rate * trial_q(wa, a.tab.gtab, a.tab.pa, lg, lower);
                     if (trial_is_cut(cut, lg, lower)) dn = 0.0f;
+                } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
+                    dn = rate * quantum_q(wa, a.tab.qtab, a.tab.pa, chif, xq);
                 }
                 bool emit;
                 float frac = invK;
@@ -369,6 +377,8 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                         float x;
                         if (SAMPLER == SR_SAMPLER_S) {
                             x = trial_x(wa, lg, lower);
+                        } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
+                            x = xq;
                         } else {
                             float lnU, ln1mU;
                             direct_u(wa, rr, lnU, ln1mU);
@@ -797,7 +807,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     const int dim = grid->dim;
     const int K = prm->n_samples;
     if (K < 1 || K > kMaxK) return SR_E_INVAL;
-    if (prm->sampler < SR_SAMPLER_S || prm->sampler > SR_SAMPLER_MLP) return SR_E_INVAL;
+    if (prm->sampler < SR_SAMPLER_S || prm->sampler > SR_SAMPLER_QUANTUM) return SR_E_INVAL;
     if (prm->sampler == SR_SAMPLER_MLP && (!prm->mlp_params || !prm->mlp_fallback))
         return SR_E_INVAL;
     if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
@@ -827,6 +837,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.tab.t1 = tab->t1;
     a.tab.r = tab->r;
     a.tab.gtab = tab->gtab;
+    a.tab.qtab = tab->qtab;
     a.mlp = (const __bf16 *)prm->mlp_params;
     a.mlp_fallback = prm->mlp_fallback;
     a.start = chunks->start;
@@ -868,6 +879,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     }
     if (prm->sampler == SR_SAMPLER_S) { SR_BY_DIM(SR_SAMPLER_S); }
     else if (prm->sampler == SR_SAMPLER_TABLE) { SR_BY_DIM(SR_SAMPLER_TABLE); }
+    else if (prm->sampler == SR_SAMPLER_QUANTUM) { SR_BY_DIM(SR_SAMPLER_QUANTUM); }
     else { SR_BY_DIM(SR_SAMPLER_MLP); }
 #undef SR_BY_DIM
 #undef SR_BY_K

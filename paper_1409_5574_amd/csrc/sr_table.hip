@@ -123,6 +123,55 @@ __global__ void build_g_table(float4 *out) {
     out[p] = hermite_piece(y0, d0, y1, d1, h);
 }
 
+// K_{2/3}(xi), K_{1/3}(xi) and int_xi^inf K_{1/3} for the quantum kernel table,
+// from K_nu(xi) = int_0^inf exp(-xi cosh s) cosh(nu s) ds and
+// int_xi^inf K_nu = int_0^inf exp(-xi cosh s) cosh(nu s) / cosh s ds.
+__device__ void bessel_triple(double xi, double &k23, double &k13, double &ki13) {
+    const double s_peak = asinh(2.0 / (3.0 * xi)) + 1.0;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int j = 0; j < 200000; ++j) {
+        const double s = j * kH;
+        const double e = -xi * cosh(s);
+        const double half = j ? 1.0 : 0.5;
+        const double ta = exp(e + lncosh(2.0 * s / 3.0)) * half;
+        const double l13 = e + lncosh(s / 3.0);
+        a += ta;
+        b += exp(l13) * half;
+        c += exp(l13 - lncosh(s)) * half;
+        // the nu = 1/3 integrands fall faster than the nu = 2/3 one past the peak
+        if (s > s_peak && ta <= 1e-19 * a) break;
+    }
+    k23 = kH * a;
+    k13 = kH * b;
+    ki13 = kH * c;
+}
+
+// Nodes of the quantum table at t = log2 xi (see kQPerUnit): values and
+// d/dt, from K'_{2/3} = -K_{1/3} - (2/3) K_{2/3} / xi and (int_xi K_{1/3})' = -K_{1/3}:
+//   dyA/dt = xi - xi K_{1/3}/K_{2/3},  dyB/dt = xi - xi K_{1/3} / int_xi K_{1/3}.
+__device__ void q_node(double t, double &ya, double &da, double &yb, double &db) {
+    const double xi = exp2(t);
+    double k23, k13, ki13;
+    bessel_triple(xi, k23, k13, ki13);
+    const double xl = xi * 1.4426950408889634;
+    ya = log2(k23) + 2.0 * t / 3.0 + xl;
+    da = xi - xi * k13 / k23;
+    yb = log2(ki13) + xl;
+    db = xi - xi * k13 / ki13;
+}
+
+__global__ void build_q_table(float4 *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kQN) return;
+    const int j = p + kQJ0;
+    const double h = 1.0 / kQPerUnit;
+    double a0, da0, b0, db0, a1, da1, b1, db1;
+    q_node(j * h, a0, da0, b0, db0);
+    q_node((j + 1) * h, a1, da1, b1, db1);
+    out[2 * p] = hermite_piece(a0, da0, a1, da1, h);
+    out[2 * p + 1] = hermite_piece(b0, db0, b1, db1, h);
+}
+
 // x with N(x) = U N(inf), given U and 1-U (both accurate); bisection in log2 x.
 __device__ double inv_number(double one_minus_u) {
     const double target = one_minus_u * kNInf;   // = Ntail(x)
@@ -213,6 +262,17 @@ __global__ void eval_trial_kernel(const float4 *__restrict__ gtab, float pa,
     xo[i] = trial_x(a[i], lg, lower);
 }
 
+__global__ void eval_quantum_kernel(const float4 *__restrict__ qtab, float pa,
+                                    const uint32_t *__restrict__ a, const float *__restrict__ rate,
+                                    const float *__restrict__ chi, float *__restrict__ dn,
+                                    float *__restrict__ xo, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x;
+    dn[i] = rate[i] * quantum_q(a[i], qtab, pa, chi[i], x);
+    xo[i] = x;
+}
+
 __global__ void philox_kernel(const uint4 *__restrict__ ctr, uint32_t k0, uint32_t k1,
                               uint4 *__restrict__ out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -235,6 +295,7 @@ extern "C" int sr_table_build(sr_table **out, void *stream) {
     auto fail = [&](int code) {
         if (t->ftab) (void)hipFree(t->ftab);
         if (t->gtab) (void)hipFree(t->gtab);
+        if (t->qtab) (void)hipFree(t->qtab);
         if (t->t1) (void)hipFree(t->t1);
         if (t->r) (void)hipFree(t->r);
         if (aux) (void)hipFree(aux);
@@ -244,11 +305,13 @@ extern "C" int sr_table_build(sr_table **out, void *stream) {
     if (hipGetDevice(&t->device) != hipSuccess) return fail(SR_E_HIP);
     if (hipMalloc(&t->ftab, sizeof(float4) * kFTotal) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&t->gtab, sizeof(float4) * kGTotal) != hipSuccess) return fail(SR_E_NOMEM);
+    if (hipMalloc(&t->qtab, sizeof(float4) * 2 * kQN) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&t->t1, sizeof(float4) * kT1N) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&t->r, sizeof(float2) * kRN) != hipSuccess) return fail(SR_E_NOMEM);
     if (hipMalloc(&aux, sizeof(double) * 2) != hipSuccess) return fail(SR_E_NOMEM);
     build_f_table<<<(kFTotal + 63) / 64, 64, 0, st>>>(t->ftab);
     build_g_table<<<(kGTotal + 63) / 64, 64, 0, st>>>(t->gtab);
+    build_q_table<<<(kQN + 63) / 64, 64, 0, st>>>(t->qtab);
     build_t1_table<<<(kT1N + 63) / 64, 64, 0, st>>>(t->t1);
     build_r_table<<<(kRN + 63) / 64, 64, 0, st>>>(t->r);
     solve_proposal<<<1, 64, 0, st>>>(aux);
@@ -269,6 +332,7 @@ extern "C" void sr_table_free(sr_table *t) {
     if (!t) return;
     if (t->ftab) (void)hipFree(t->ftab);
     if (t->gtab) (void)hipFree(t->gtab);
+    if (t->qtab) (void)hipFree(t->qtab);
     if (t->t1) (void)hipFree(t->t1);
     if (t->r) (void)hipFree(t->r);
     delete t;
@@ -279,6 +343,7 @@ extern "C" int sr_table_query(const sr_table *t, sr_table_info *info) {
     info->proposal_pa = t->pa;
     info->f_pieces = kFTotal;
     info->g_pieces = kGTotal;
+    info->q_pieces = kQN;
     info->proposal_a = t->a;
     info->t1_pieces = kT1N;
     info->r_nodes = kRN;
@@ -303,6 +368,17 @@ extern "C" int sr_eval_trial(const sr_table *t, const uint32_t *a, const float *
     if (n == 0) return SR_OK;
     eval_trial_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
         t->gtab, t->pa, a, rate, chi, kin_cut, out_dn, out_x, n);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_eval_trial_quantum(const sr_table *t, const uint32_t *a, const float *rate,
+                                     const float *chi, float *out_dn, float *out_x, int64_t n,
+                                     void *stream) {
+    if (!t || n < 0 || (n > 0 && (!a || !rate || !chi || !out_dn || !out_x))) return SR_E_INVAL;
+    if (n == 0) return SR_OK;
+    eval_quantum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+        t->qtab, t->pa, a, rate, chi, out_dn, out_x, n);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }

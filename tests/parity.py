@@ -19,19 +19,35 @@ LEDGER_TOL = 1e-4
 NEAR = 1e-5
 
 
-def near_threshold(dn, b):
-    """Trials whose decision may flip between FP32 and FP64 dN."""
+def quantum_dn_tol(chi, x):
+    """Relative accuracy of the FP32 quantum dN at (chi, x): the table's 3e-6,
+    the rounding of xi log2 e, and the rounding of delta = 1.5 chi x (about
+    4e-7 relative), which 1 - delta turns into a relative error of xi of
+    4e-7 delta/(1 - delta), and Q ~ e^-xi multiplies by xi."""
+    chi = np.asarray(chi, np.float64)
+    x = np.asarray(x, np.float64)
+    d = np.minimum(1.5 * chi * x, 1.0 - 1e-12)
+    xi = x / (1.0 - d)
+    return 3e-6 + 1e-7 * xi + 6e-7 * (xi + 1.0) * d / (1.0 - d)
+
+
+def near_threshold(dn, b, tol=None):
+    """Trials whose decision may flip between FP32 and FP64 dN (tol: per-trial
+    relative accuracy of the FP32 dN, default NEAR)."""
     dn = np.asarray(dn, dtype=np.float64)
+    tol = NEAR if tol is None else np.maximum(np.asarray(tol, np.float64), NEAR)
     thr = np.minimum(dn, 1.0) * 2.0 ** 32
-    near_b = np.abs(np.asarray(b, dtype=np.float64) - thr) <= NEAR * thr + 1.0
-    near_one = np.abs(dn - 1.0) <= NEAR
+    near_b = np.abs(np.asarray(b, dtype=np.float64) - thr) <= tol * thr + 1.0
+    near_one = np.abs(dn - 1.0) <= tol
     near_kin = np.zeros_like(near_b)
     return near_b | near_one | near_kin
 
 
 def compare_step(gpu_state: dict, orc_state: dict, old_state: dict, gpu_ph: dict, orc_ph: dict,
-                 det: dict, K: int, box=None, xcut_band=None):
-    """Compare one step.  Returns a report dict; raises AssertionError on failure."""
+                 det: dict, K: int, box=None, xcut_band=None, dn_tol=None):
+    """Compare one step.  Returns a report dict; raises AssertionError on failure.
+    dn_tol: optional per-trial relative accuracy of the GPU's dN (oracle order),
+    for samplers whose FP32 dN is less accurate than NEAR in places."""
     order_g = np.argsort(gpu_state["id"])
     order_o = np.argsort(orc_state["id"])
     ids = orc_state["id"][order_o]
@@ -52,7 +68,7 @@ def compare_step(gpu_state: dict, orc_state: dict, old_state: dict, gpu_ph: dict
     emit_o[slot_o] = True
     emit_g[slot_g] = True
     mism = emit_o != emit_g
-    near = near_threshold(det["dn"], det["bword"])
+    near = near_threshold(det["dn"], det["bword"], dn_tol)
     if xcut_band is not None:
         near |= xcut_band
     bad = mism & ~near
@@ -71,7 +87,8 @@ def compare_step(gpu_state: dict, orc_state: dict, old_state: dict, gpu_ph: dict
         rel_e = np.abs(gpu_ph["eps"][ig] - orc_ph["eps"][io]) / np.abs(orc_ph["eps"][io])
         rel_w = np.abs(gpu_ph["w"][ig] - orc_ph["w"][io]) / np.abs(orc_ph["w"][io])
         ddir = np.abs(gpu_ph["dir"][ig] - orc_ph["dir"][io]).max()
-        assert rel_w.max() <= PH_TOL, f"photon weight rel err {rel_w.max()}"
+        w_tol = PH_TOL if dn_tol is None else PH_TOL + np.asarray(dn_tol)[np.nonzero(both)[0]]
+        assert (rel_w <= w_tol).all(), f"photon weight rel err {rel_w.max()}"
         assert rel_e.max() <= PH_TOL, f"photon energy rel err {rel_e.max()} at {np.argmax(rel_e)}"
         assert ddir <= 1e-5, f"photon direction err {ddir}"
     else:

@@ -163,3 +163,12 @@ def test_angular_histogram_rejects_bad_arguments_on_host(lib):
                           (ax, rf, 8, -1), (ax, rf, 4096, 2)):
         assert lib.sr_angular_histogram(C.byref(ph), C.byref(ch), 10, a, r, nt, nph, out, out,
                                         None) == L.SR_E_INVAL
+
+
+def test_eval_trial_quantum_rejects_bad_arguments_on_host(lib):
+    from paper_1409_5574_amd import _lib as L
+    d = C.c_void_p(16)
+    assert lib.sr_eval_trial_quantum(None, d, d, d, d, d, 4, None) == L.SR_E_INVAL
+    assert lib.sr_eval_trial_quantum(d, None, d, d, d, d, 4, None) == L.SR_E_INVAL
+    assert lib.sr_eval_trial_quantum(d, d, d, d, d, d, -1, None) == L.SR_E_INVAL
+    assert lib.sr_eval_trial_quantum(d, None, None, None, None, None, 0, None) == L.SR_OK

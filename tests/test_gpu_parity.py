@@ -80,6 +80,39 @@ def test_trial_dn_against_oracle(sr, table, oracle):
     assert np.max(np.abs(dn / ref[:, 0] - 1)) < 3e-6
 
 
+def test_quantum_trial_against_oracle(sr, table, oracle):
+    rng = np.random.default_rng(11)
+    n = 20000
+    a = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    chi = (10.0 ** rng.uniform(-3.0, 0.8, n)).astype(np.float32)
+    rate = np.float32(0.013)
+    _say("eval quantum trial 20000")
+    dn, xg = sr.eval_trial_quantum(table, torch.from_numpy(a.view(np.int32)),
+                                   torch.full((n,), float(rate)), torch.from_numpy(chi))
+    dn = dn.cpu().numpy().astype(np.float64)
+    xg = xg.cpu().numpy().astype(np.float64)
+    Pa = oracle.proposal_Pa_f32()
+    rp = ((a >> 9).astype(np.float64) + 0.5) / 2 ** 23
+    c64 = chi.astype(np.float64)
+    ref = np.array([oracle.trial_dn_quantum(r, float(rate), c, Pa) for r, c in zip(rp, c64)])
+    assert np.max(np.abs(xg / ref[:, 1] - 1)) < 3e-7
+    d = 1.5 * c64 * ref[:, 1]
+    xi = ref[:, 1] / np.maximum(1.0 - d, 1e-300)
+    # (dN below 1e-30 is under FP32's normal range once multiplied out, and far
+    # below any decision: a trial emits only if dN 2^32 >= 1)
+    live = (d < 1.0 - 1e-5) & (xi < 100.0) & (ref[:, 0] > 1e-30)
+    dead = d >= 1.0 + 1e-5
+    assert live.sum() > n // 2 and dead.sum() > 100
+    # beyond the kinematic edge: exactly zero on both sides
+    assert (dn[dead] == 0).all() and (ref[dead, 0] == 0).all()
+    tol = parity.quantum_dn_tol(c64, ref[:, 1])
+    rel = np.abs(dn[live] / ref[live, 0] - 1)
+    assert (rel <= tol[live]).all(), (rel.max(), np.argmax(rel / tol[live]))
+    # the bulk (away from the edge) as accurate as the classical trial table
+    bulk = live & (d < 0.5) & (xi < 20.0)
+    assert np.max(np.abs(dn[bulk] / ref[bulk, 0] - 1)) < 5e-6
+
+
 # ------------------------------------------------------------------ one-step parity
 def _orc_state(d):
     return {k: (v.astype(np.float64) if v.dtype != np.uint32 else v.copy()) for k, v in d.items()}
@@ -114,7 +147,7 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
         orc["z"] = None
     ph_o, led_o, det = oracle.step(orc, fo, cfg.dt, seed, step, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
                                    n_samples=K, recoil=recoil, kin_cut=kin_cut,
-                                   sampler=1 if sampler else 0, dn_policy=dn_policy,
+                                   sampler={0: 0, 3: 2}.get(sampler, 1), dn_policy=dn_policy,
                                    push_position=dim != 0, detail=True)
     # GPU
     tdtype = torch.float64 if dtype == np.float64 else torch.float32
@@ -142,8 +175,12 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
     if kin_cut:
         chi = np.repeat(det["chi"], K)
         xcut_band = np.abs(1.5 * chi * det["xs"] - 1.0) <= 1e-5
+    dn_tol = None
+    if sampler == 3:
+        dn_tol = parity.quantum_dn_tol(np.repeat(det["chi"], K), det["xs"])
     box = cfg.box if dim else None
-    rep = parity.compare_step(gs, orc, old, ph_g, ph_o, det, K, box=box, xcut_band=xcut_band)
+    rep = parity.compare_step(gs, orc, old, ph_g, ph_o, det, K, box=box, xcut_band=xcut_band,
+                              dn_tol=dn_tol)
     # ledger: remove the energy of flipped trials from the comparison budget
     flips_e = 0.0
     if rep["decision_flips"]:
@@ -210,3 +247,20 @@ def test_step_table_sampler(sr, table, oracle):
     rep = run_step_case(sr, table, oracle, cfg, 4000, K=2, sampler=1, kin_cut=True,
                         label="table sampler")
     assert rep["photons_oracle"] > 40
+
+
+def test_step_quantum_sampler_3d(sr, table, oracle):
+    # chi ~ 1 (the regime the quantum kernel is for): thermal momenta scaled up
+    # in the a0 = 500 standing wave; the kinematic edge is built into the kernel
+    cfg = synth.config("c3", grid=(24, 20, 16), slab=None)
+    rep = run_step_case(sr, table, oracle, cfg, 4099, p_scale=6000.0, sampler=3, kin_cut=False,
+                        label="3d quantum K8")
+    assert rep["photons_oracle"] > 1000
+
+
+def test_step_quantum_sampler_uniform_K1(sr, table, oracle):
+    # chi = hbar_n B gamma sin(pitch) from 1e-2 to 10
+    cfg = synth.config("c1", b0=(0.0, 0.0, 100.0), gamma_range=(1e2, 1e5), hbar_n=1e-6)
+    rep = run_step_case(sr, table, oracle, cfg, 8000, K=1, sampler=3, kin_cut=False,
+                        label="uniform quantum K1")
+    assert rep["photons_oracle"] > 150
