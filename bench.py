@@ -314,7 +314,10 @@ def samplers_leg(args):
       table_direct    cut-rate decision + tabulated inverse number-CDF,
       mlp_direct      the same decisions, x from the network where the judge
                       admitted it and from the table elsewhere,
-      mlp_network     the same with every emitted trial through the network.
+      mlp_network     the same with every emitted trial through the network,
+      quantum         the S(x) proposal with the quantum-corrected kernel (other
+                      physics: its spectrum difference from the classical cut
+                      run is the quantum suppression at chi ~ 1, not an error).
     Each run's energy spectrum (accumulated over its steps) is compared with the
     table_direct run's; s_proposal draws other random numbers, so its error is
     the Monte-Carlo noise floor of that comparison."""
@@ -356,7 +359,8 @@ def samplers_leg(args):
     stream = torch.cuda.current_stream()
     seed = 0x5A3B1E
     variants = [("s_proposal", 0, None), ("table_direct", 1, None),
-                ("mlp_direct", 2, judged), ("mlp_network", 2, torch.zeros_like(judged))]
+                ("mlp_direct", 2, judged), ("mlp_network", 2, torch.zeros_like(judged)),
+                ("quantum", 3, None)]
     res, hists = {}, {}
     for name, sampler, fb in variants:
         if fb is not None:
@@ -392,8 +396,8 @@ def samplers_leg(args):
                      "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300))}
     ref = hists["table_direct"]
     for name in res:
-        res[name]["spectrum_error_vs_table_direct"] = float(
-            np.abs(hists[name] - ref).sum() / max(ref.sum(), 1e-300))
+        key = "spectrum_change_vs_classical" if name == "quantum" else "spectrum_error_vs_table_direct"
+        res[name][key] = float(np.abs(hists[name] - ref).sum() / max(ref.sum(), 1e-300))
     base = res["s_proposal"]["particle_steps_per_s"]
     for name in res:
         res[name]["speedup_vs_s_proposal"] = res[name]["particle_steps_per_s"] / base

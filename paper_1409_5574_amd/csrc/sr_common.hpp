@@ -33,13 +33,17 @@ template <> __device__ __forceinline__ double rcp_r<double>(double v) { return 1
 // Element access through a 32-bit byte offset from a base pointer, so the
 // address is formed as (scalar base + vector offset) with no 64-bit arithmetic.
 // Callers keep every array below 4 GiB.
+// The accesses name the global address space, so they compile to global (not
+// flat) memory instructions: flat ones also count against the LDS / scalar wait
+// counter, which would make every LDS or scalar wait also wait for them.
+#define SR_GLOBAL __attribute__((address_space(1)))
 template <typename T>
 __device__ __forceinline__ T ld(const T *base, uint32_t i) {
-    return *(const T *)((const char *)base + i * (uint32_t)sizeof(T));
+    return *(const SR_GLOBAL T *)((const SR_GLOBAL char *)base + i * (uint32_t)sizeof(T));
 }
 template <typename T>
 __device__ __forceinline__ void st(T *base, uint32_t i, T v) {
-    *(T *)((char *)base + i * (uint32_t)sizeof(T)) = v;
+    *(SR_GLOBAL T *)((SR_GLOBAL char *)base + i * (uint32_t)sizeof(T)) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -322,7 +326,7 @@ __device__ __forceinline__ void axis_setup(double x, double inv, int n, Axis<dou
 // Two consecutive grid values of a row from one 8-byte load (4-byte aligned).
 typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 __device__ __forceinline__ float2 ld2(const float *base, uint32_t i) {
-    const f32x2_a4 v = *(const f32x2_a4 *)((const char *)base + i * 4u);
+    const f32x2_a4 v = *(const SR_GLOBAL f32x2_a4 *)((const SR_GLOBAL char *)base + i * 4u);
     return make_float2(v.x, v.y);
 }
 

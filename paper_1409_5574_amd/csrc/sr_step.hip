@@ -169,11 +169,28 @@ __device__ __forceinline__ R wrap_pos(R v, R L) {
 
 // The output pointers of the kernel arguments, reached through an opaque copy
 // of the argument-segment pointer: the loads happen where they are used.
+// The copy names the constant address space, so the fields are read with
+// scalar loads.
 template <typename R>
-__device__ __forceinline__ const PhotonOut &cold_args() {
+__device__ __forceinline__ PhotonOut cold_args() {
+    typedef const __attribute__((address_space(4))) char cchar;
+    typedef const __attribute__((address_space(4))) PhotonOut cphoton;
     const char *kp = (const char *)__builtin_amdgcn_kernarg_segment_ptr();
     asm volatile("" : "+s"(kp));
-    return *(const PhotonOut *)(kp + offsetof(StepArgs<R>, ph));
+    cphoton *q = (cphoton *)((cchar *)kp + offsetof(StepArgs<R>, ph));
+    PhotonOut o;
+    o.eps = q->eps;
+    o.w = q->w;
+    for (int c = 0; c < 3; ++c) {
+        o.dir[c] = q->dir[c];
+        o.pos[c] = q->pos[c];
+    }
+    o.parent = q->parent;
+    o.step = q->step;
+    o.k = q->k;
+    o.seg_count = q->seg_count;
+    o.partials = q->partials;
+    return o;
 }
 
 // One photon record into slot o of the buffer (section "The field setup":
