@@ -46,7 +46,7 @@ class _Field(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("hbar_n", C.c_double), ("alpha", C.c_double), ("n_samples", C.c_int32),
                 ("recoil", C.c_int32), ("dn_policy", C.c_int32), ("kin_cut", C.c_int32),
-                ("sampler", C.c_int32), ("push_position", C.c_int32)]
+                ("sampler", C.c_int32), ("push_position", C.c_int32), ("omega_grid", C.c_double)]
 
 
 class _Photons(C.Structure):
@@ -242,7 +242,7 @@ def gather(field: "Field", pos):
 def step(state: dict, field: Field, dt: float, seed: int, step_index: int, *, hbar_n: float,
          alpha: float, n_samples: int = 1, recoil: int = RECOIL_PHOTON, dn_policy: int = DN_WEIGHT,
          kin_cut: bool = False, sampler: int = SAMPLER_S, push_position: bool = True,
-         detail: bool = False, threads: int = 0):
+         detail: bool = False, threads: int = 0, omega_grid: float = 0.0):
     """Advance ``state`` (dict of FP64 arrays x,y,z,px,py,pz,w and uint32 id) by one step
     in place.  Returns (photons dict, ledger[5], detail dict or None)."""
     n = int(state["px"].shape[0])
@@ -258,7 +258,7 @@ def step(state: dict, field: Field, dt: float, seed: int, step_index: int, *, hb
           "pos": np.empty((cap, 3)), "parent": np.empty(cap, np.uint32), "k": np.empty(cap, np.uint32)}
     phs = _Photons(cap, 0, *(ph[k].ctypes.data for k in ("eps", "w", "dir", "pos", "parent", "k")))
     prm = _Params(hbar_n, alpha, K, recoil, dn_policy, int(bool(kin_cut)), sampler,
-                  int(bool(push_position)))
+                  int(bool(push_position)), float(omega_grid))
     det = None
     dets = None
     if detail:
@@ -280,6 +280,38 @@ def step(state: dict, field: Field, dt: float, seed: int, step_index: int, *, hb
     m = phs.count
     photons = {k: v[:m] for k, v in ph.items()}
     return photons, ledger, det
+
+
+# ---------------------------------------------------------------- validity diagnostics
+VALID_QUANTUM, VALID_NON_SYNCHROTRON = 1, 2
+
+
+def validity_flags(heff, chi, tau_em: float) -> np.ndarray:
+    """Per-particle flags of the method's two stated limits.
+
+    VALID_QUANTUM: chi >= 1, where the classical emission formula fails and a QED
+    treatment is needed (section "Limitations").
+    VALID_NON_SYNCHROTRON: 0 < H_eff tau_em <= 1.  The synchrotron (wiggler)
+    spectrum needs the field to vary slower than the particle turns by an angle
+    1/gamma, tau_em > 1/(gamma omega_H) with omega_H = e H_eff/(m c gamma)
+    (section "Synchrotron emission"), i.e. H_eff tau_em > 1 in normalised units."""
+    heff = np.asarray(heff, np.float64)
+    chi = np.asarray(chi, np.float64)
+    f = np.where(chi >= 1.0, VALID_QUANTUM, 0)
+    f |= np.where((heff > 0.0) & (heff * tau_em <= 1.0), VALID_NON_SYNCHROTRON, 0)
+    return f.astype(np.uint8)
+
+
+def validity_sums(w, heff, chi, gamma_bar, pbar_over_gamma2, flags, alpha: float, hbar_n: float):
+    """{sum w, sum w [quantum], sum w [non-synchrotron], sum w P, sum w P [quantum],
+    sum w P [non-synchrotron]} with P = (2/3)(alpha/hbar_n) chi^2 beta^2, the
+    Landau-Lifshitz power (eq:LLformOfRRForce with |v| = beta)."""
+    w = np.asarray(w, np.float64)
+    P = (2.0 / 3.0) * (alpha / hbar_n) * np.asarray(chi) ** 2 * np.asarray(pbar_over_gamma2)
+    q = (flags & VALID_QUANTUM) != 0
+    ns = (flags & VALID_NON_SYNCHROTRON) != 0
+    return np.array([w.sum(), w[q].sum(), w[ns].sum(), (w * P).sum(), (w * P)[q].sum(),
+                     (w * P)[ns].sum()])
 
 
 # ---------------------------------------------------------------- spectrum metric

@@ -488,6 +488,10 @@ static void step_one(int64_t i, double *x, double *y, double *z,
         }
         if (emit && prm->sampler == ORC_SAMPLER_DIRECT)
             xs = orc_inv_number_cdf(chi, Rp, prm->kin_cut);
+        /* grid cutoff: a photon below omega_grid (hbar omega_c x < hbar omega_grid)
+           is resolved by the grid and is not emitted as a particle */
+        if (emit && prm->omega_grid > 0.0 && 1.5 * chi * gb * xs < prm->hbar_n * prm->omega_grid)
+            emit = 0;
         if (det) {
             const int64_t s = i * K + k;
             if (det->dn) det->dn[s] = dN;

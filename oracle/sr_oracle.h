@@ -91,6 +91,10 @@ typedef struct {
     int32_t kin_cut;       /* 1: reject x > 2/(3 chi) */
     int32_t sampler;       /* ORC_SAMPLER_* */
     int32_t push_position; /* 1: advance positions */
+    double omega_grid;     /* > 0: the grid's cutoff frequency c/dx (section "The
+                              field setup"); photons of lower frequency are not
+                              emitted as particles (the grid carries them).
+                              0: no floor */
 } orc_params;
 
 /* Photons in id order, then sample order.  Capacity must be >= n*K. */
