@@ -150,6 +150,12 @@ typedef struct {
     const uint8_t *mlp_fallback; /* SR_SAMPLER_MLP: device uint8[SR_MLP_FALLBACK_BINS]:
                                1 sends the trials of that log10 chi bin on
                                [-4, 2) (and any chi outside it) to the table       */
+    double omega_grid;      /* > 0: the grid's cutoff frequency c/dx in units of
+                               omega_r (section "The field setup": the grid resolves
+                               radiation below it).  A photon of energy below
+                               hbar_n omega_grid is not emitted (no record, no
+                               recoil, not in the ledger's emitted column).  0: no
+                               floor.  Not with SR_SAMPLER_MLP (SR_E_INVAL)        */
 } sr_params;
 
 /* Chunking of the particle array.  Chunk c covers particles
@@ -239,6 +245,28 @@ int sr_eval_synchrotron_F(const sr_table *tab, const float *x, float *out, int64
  * log2 F/(x S) built in FP64 as a function of R' itself. */
 int sr_eval_trial(const sr_table *tab, const uint32_t *a, const float *rate, const float *chi,
                   int32_t kin_cut, float *out_dn, float *out_x, int64_t n, void *stream);
+
+/* Validity diagnostics of the two limits the paper states for the method:
+ *   SR_VALID_QUANTUM          chi >= 1: the classical emission formula fails and a
+ *                             QED treatment is needed (section "Limitations");
+ *   SR_VALID_NON_SYNCHROTRON  0 < H_eff tau_em <= 1: the field varies faster than
+ *                             the particle turns by 1/gamma, tau_em <= 1/(gamma
+ *                             omega_H), so the emission need not have the
+ *                             synchrotron (wiggler) spectrum (section "Synchrotron
+ *                             emission", the criterion a^-1 < omega_L tau_EM).
+ * H_eff and chi are those the emission step computes (gather, Boris push,
+ * eq:effective_H), without emission and without writing the particles.
+ * tau_em > 0: the time scale of the field variation in units of 1/omega_r (for
+ * a laser, 1/omega_L).  flags: device uint8[parts->n] or NULL.  sums: device
+ * double[SR_VALID_SUMS] receiving {sum w, sum w [quantum], sum w
+ * [non-synchrotron], sum w LL, sum w LL [quantum], sum w LL [non-synchrotron]},
+ * LL the Landau-Lifshitz energy of the step (ledger column SR_LED_LL), summed
+ * in a fixed order.  work: device double[sr_validity_work(parts->n)]. */
+enum { SR_VALID_QUANTUM = 1u, SR_VALID_NON_SYNCHROTRON = 2u, SR_VALID_SUMS = 6 };
+int sr_validity(const sr_particles_f32 *parts, const sr_fields_f32 *fields, const sr_grid *grid,
+                double dt, const sr_params *prm, double tau_em, uint8_t *flags, double *sums,
+                double *work, void *stream);
+int64_t sr_validity_work(int64_t n);
 
 /* dN of one quantum trial (SR_SAMPLER_QUANTUM) for n device (word a, rate, chi)
  * triples: out_dn = rate Q(x, chi)/S(x), out_x = x, with x and S from the

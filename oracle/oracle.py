@@ -302,12 +302,12 @@ def validity_flags(heff, chi, tau_em: float) -> np.ndarray:
     return f.astype(np.uint8)
 
 
-def validity_sums(w, heff, chi, gamma_bar, pbar_over_gamma2, flags, alpha: float, hbar_n: float):
+def validity_sums(w, chi, beta2, flags, alpha: float, hbar_n: float, dt: float):
     """{sum w, sum w [quantum], sum w [non-synchrotron], sum w P, sum w P [quantum],
-    sum w P [non-synchrotron]} with P = (2/3)(alpha/hbar_n) chi^2 beta^2, the
-    Landau-Lifshitz power (eq:LLformOfRRForce with |v| = beta)."""
+    sum w P [non-synchrotron]} with P = (2/3)(alpha/hbar_n) chi^2 beta^2 dt, the
+    Landau-Lifshitz energy of the step (eq:LLformOfRRForce with |v| = beta)."""
     w = np.asarray(w, np.float64)
-    P = (2.0 / 3.0) * (alpha / hbar_n) * np.asarray(chi) ** 2 * np.asarray(pbar_over_gamma2)
+    P = (2.0 / 3.0) * (alpha / hbar_n) * np.asarray(chi) ** 2 * np.asarray(beta2) * dt
     q = (flags & VALID_QUANTUM) != 0
     ns = (flags & VALID_NON_SYNCHROTRON) != 0
     return np.array([w.sum(), w[q].sum(), w[ns].sum(), (w * P).sum(), (w * P)[q].sum(),

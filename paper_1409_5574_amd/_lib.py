@@ -21,6 +21,7 @@ SR_CHUNK = 64
 SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP, SR_SAMPLER_QUANTUM = 0, 1, 2, 3
 SR_RECOIL_NONE, SR_RECOIL_PHOTON, SR_RECOIL_LL = 0, 1, 2
 SR_DN_WEIGHT, SR_DN_CLAMP = 0, 1
+SR_VALID_QUANTUM, SR_VALID_NON_SYNCHROTRON, SR_VALID_SUMS = 1, 2, 6
 SR_MLP_PARAMS = 8577
 SR_MLP_FALLBACK_BINS = 24
 
@@ -48,7 +49,8 @@ class Params(C.Structure):
     _fields_ = [("hbar_n", C.c_double), ("alpha", C.c_double), ("n_samples", C.c_int32),
                 ("sampler", C.c_int32), ("recoil", C.c_int32), ("dn_policy", C.c_int32),
                 ("kin_cut", C.c_int32), ("push_position", C.c_int32),
-                ("mlp_params", C.c_void_p), ("mlp_fallback", C.c_void_p)]
+                ("mlp_params", C.c_void_p), ("mlp_fallback", C.c_void_p),
+                ("omega_grid", C.c_double)]
 
 
 class Chunking(C.Structure):
@@ -82,6 +84,9 @@ SIGNATURES = {
     "sr_eval_synchrotron_F": (C.c_int, [_P, _P, _P, _I64, _P]),
     "sr_eval_trial": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _I64, _P]),
     "sr_eval_trial_quantum": (C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _P]),
+    "sr_validity": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32), C.POINTER(Grid),
+                              C.c_double, C.POINTER(Params), C.c_double, _P, _P, _P, _P]),
+    "sr_validity_work": (C.c_int64, [_I64]),
     "sr_philox": (C.c_int, [_P, _U64, _P, _I64, _P]),
     "sr_gather_push_emit": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32),
                                       C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,

@@ -280,11 +280,11 @@ class LedgerBuf:
 
 def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.SR_RECOIL_PHOTON,
                   dn_policy=L.SR_DN_WEIGHT, kin_cut=False, push_position=True,
-                  mlp: "Mlp | None" = None) -> L.Params:
+                  mlp: "Mlp | None" = None, omega_grid: float = 0.0) -> L.Params:
     return L.Params(float(hbar_n), float(alpha), int(n_samples), int(sampler), int(recoil),
                     int(dn_policy), int(bool(kin_cut)), int(bool(push_position)),
                     None if mlp is None else mlp.params.data_ptr(),
-                    None if mlp is None else mlp.fallback.data_ptr())
+                    None if mlp is None else mlp.fallback.data_ptr(), float(omega_grid))
 
 
 def eval_direct(table: Table, a: torch.Tensor, chi: torch.Tensor, kin_cut: bool) -> torch.Tensor:
@@ -451,6 +451,24 @@ def eval_push(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, 
                C.byref(prm), _ptr(out["heff"]), _ptr(out["chi"]), _ptr(out["gamma_bar"]),
                _stream()), "sr_eval_push")
     return {k: v[:n] for k, v in out.items()}
+
+
+def validity(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, hbar_n: float,
+             alpha: float, tau_em: float, want_flags: bool = True):
+    """Validity flags (uint8 per particle, SR_VALID_* bits, or None) and the six
+    weighted sums of sr_validity (host numpy)."""
+    n = parts.n
+    flags = torch.empty(max(n, 1), device=DEV, dtype=torch.uint8) if want_flags else None
+    sums = torch.empty(L.SR_VALID_SUMS, device=DEV, dtype=torch.float64)
+    nw = int(lib().sr_validity_work(n))
+    work = torch.empty(max(nw, 1), device=DEV, dtype=torch.float64)
+    prm = params_struct(hbar_n, alpha)
+    ps = parts.struct()
+    fs = fields.struct() if fields is not None else None
+    L.check(lib().sr_validity(C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid),
+                              float(dt), C.byref(prm), float(tau_em), _ptr(flags), _ptr(sums),
+                              _ptr(work), _stream()), "sr_validity")
+    return (None if flags is None else flags[:n]), sums.cpu().numpy()
 
 
 def ledger_reduce(ledger: "LedgerBuf", n_chunks: int, row: int, ls=None):

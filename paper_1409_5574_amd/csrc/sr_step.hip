@@ -48,6 +48,7 @@ struct StepArgs {
     R hbar_n;
     float rate_c;      // dt sqrt3/(2 pi) alpha        (x H gives the trial rate)
     float direct_c;    // dt 5/(2 sqrt3) alpha          (x H r gives the direct rate)
+    float e_grid;      // hbar_n omega_grid: no photon below this energy (0: no floor)
     R ll_c;            // (2/3)(alpha/hbar_n) dt        (x chi^2 beta^2 gives the LL loss)
     TableDev tab;
     const __bf16 *mlp;              // network parameters (MLP sampler)
@@ -388,19 +389,23 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 } else {
                     emit = wb < (uint32_t)(dn * 4294967296.0f);
                 }
+                float x = 0.0f;
+                if (emit) {
+                    if (SAMPLER == SR_SAMPLER_S) {
+                        x = trial_x(wa, lg, lower);
+                    } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
+                        x = xq;
+                    } else {
+                        float lnU, ln1mU;
+                        direct_u(wa, rr, lnU, ln1mU);
+                        x = __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                    }
+                }
+                // grid cutoff: photons below hbar omega_grid stay with the grid
+                if (a.e_grid > 0.0f && eps_unit * x < a.e_grid) emit = false;
                 const uint64_t m = __ballot(emit);
                 if (m) {
                     if (emit) {
-                        float x;
-                        if (SAMPLER == SR_SAMPLER_S) {
-                            x = trial_x(wa, lg, lower);
-                        } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
-                            x = xq;
-                        } else {
-                            float lnU, ln1mU;
-                            direct_u(wa, rr, lnU, ln1mU);
-                            x = __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
-                        }
                         const float eps = eps_unit * x;
                         const float wph = wi_f * frac;
                         delta_ph += frac * eps;
@@ -808,6 +813,7 @@ int particle_args(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid
     a.rate_c = (float)(dt * 1.7320508075688772 / (2.0 * 3.14159265358979323846) * prm->alpha);
     a.direct_c = (float)(dt * 5.0 / (2.0 * 1.7320508075688772) * prm->alpha);
     a.ll_c = (R)((2.0 / 3.0) * (prm->alpha / prm->hbar_n) * dt);
+    a.e_grid = (float)(prm->hbar_n * prm->omega_grid);
     return SR_OK;
 }
 
@@ -827,6 +833,10 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     if (prm->sampler < SR_SAMPLER_S || prm->sampler > SR_SAMPLER_QUANTUM) return SR_E_INVAL;
     if (prm->sampler == SR_SAMPLER_MLP && (!prm->mlp_params || !prm->mlp_fallback))
         return SR_E_INVAL;
+    // the grid floor needs x before the slot is taken; the learned sampler finds
+    // x after it
+    if (!(prm->omega_grid >= 0.0) || !isfinite(prm->omega_grid)) return SR_E_INVAL;
+    if (prm->sampler == SR_SAMPLER_MLP && prm->omega_grid > 0.0) return SR_E_INVAL;
     if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
         return SR_E_INVAL;
     const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
@@ -928,6 +938,96 @@ __global__ __launch_bounds__(kBlock) void eval_push_kernel(const StepArgs<R> a,
     gbar[i] = (double)q.gb;
 }
 
+// Validity diagnostics of the method's two stated limits, per particle (flag
+// bits SR_VALID_*) and as weighted sums over the particles: {sum w, sum w
+// [quantum], sum w [non-synchrotron], sum w LL, sum w LL [quantum], sum w LL
+// [non-synchrotron]}, LL the Landau-Lifshitz energy of the step (the ledger's
+// LL column).  Each block writes its sums to part[block][SR_VALID_SUMS]; a
+// second kernel adds the blocks in a fixed order.
+template <typename R, int DIM>
+__global__ __launch_bounds__(kBlock) void validity_kernel(const StepArgs<R> a, R tau_em,
+                                                          uint8_t *__restrict__ flags,
+                                                          double *__restrict__ part) {
+    __shared__ double sh[SR_VALID_SUMS][kWaves];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[SR_VALID_SUMS];
+#pragma unroll
+    for (int c = 0; c < SR_VALID_SUMS; ++c) v[c] = 0.0;
+    if (i < a.n) {
+        const uint32_t u = (uint32_t)i;
+        R pos[3] = {(R)0, (R)0, (R)0};
+        if (a.has_pos) {
+            pos[0] = ld(a.x[0], u);
+            if (DIM != 0 || a.x[1]) pos[1] = ld(a.x[1], u);
+            if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = ld(a.x[2], u);
+        }
+        const R p0[3] = {ld(a.p[0], u), ld(a.p[1], u), ld(a.p[2], u)};
+        const Pushed<R> q = push_heff<R, DIM>(a, pos, p0);
+        const bool quantum = q.chi >= (R)1;
+        const bool non_synch = q.H > (R)0 && q.H * tau_em <= (R)1;
+        const uint32_t f = (quantum ? SR_VALID_QUANTUM : 0u) | (non_synch ? SR_VALID_NON_SYNCHROTRON : 0u);
+        if (flags) st(flags, u, (uint8_t)f);
+        const double w = (double)ld(a.w, u);
+        const R beta2 = q.gb > (R)0 ? q.p2 * rcp_r<R>(q.gb * q.gb) : (R)0;
+        const double ll = w * (double)(a.ll_c * q.chi * q.chi * beta2);
+        v[0] = w;
+        v[1] = quantum ? w : 0.0;
+        v[2] = non_synch ? w : 0.0;
+        v[3] = ll;
+        v[4] = quantum ? ll : 0.0;
+        v[5] = non_synch ? ll : 0.0;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < SR_VALID_SUMS; ++c) {
+        const double t = wave_sum(v[c]);
+        if (lane == 0) sh[c][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < SR_VALID_SUMS) {
+        const int c = threadIdx.x;
+        part[(int64_t)blockIdx.x * SR_VALID_SUMS + c] = ((sh[c][0] + sh[c][1]) + sh[c][2]) + sh[c][3];
+    }
+}
+
+// out[c] = sum over the blocks of part[b][c], in block order within each thread's
+// strided set, then a fixed tree over the threads.
+__global__ __launch_bounds__(kBlock) void validity_reduce(const double *__restrict__ part,
+                                                          int64_t n_blocks,
+                                                          double *__restrict__ out) {
+    __shared__ double sh[kWaves];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < n_blocks; b += kBlock) acc += part[b * SR_VALID_SUMS + c];
+    const double t = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+template <typename R, typename PARTS>
+int launch_validity(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                    const sr_params *prm, double tau_em, uint8_t *flags, double *sums,
+                    double *work, void *stream) {
+    StepArgs<R> a;
+    const int rc = particle_args<R>(parts, fields, grid, dt, prm, a);
+    if (rc != SR_OK) return rc;
+    if (!sums || !work || !(tau_em > 0.0) || !isfinite(tau_em)) return SR_E_INVAL;
+    const int64_t nb = (parts->n + kBlock - 1) / kBlock;
+    if (nb > 0x7fffffffLL) return SR_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (nb > 0) {
+        switch (grid->dim) {
+            case 0: validity_kernel<R, 0><<<(unsigned)nb, kBlock, 0, st>>>(a, (R)tau_em, flags, work); break;
+            case 2: validity_kernel<R, 2><<<(unsigned)nb, kBlock, 0, st>>>(a, (R)tau_em, flags, work); break;
+            default: validity_kernel<R, 3><<<(unsigned)nb, kBlock, 0, st>>>(a, (R)tau_em, flags, work); break;
+        }
+    }
+    validity_reduce<<<SR_VALID_SUMS, kBlock, 0, st>>>(work, nb, sums);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
 template <typename R, typename PARTS>
 int launch_eval_push(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
                      const sr_params *prm, double *heff, double *chi, double *gbar, void *stream) {
@@ -955,6 +1055,17 @@ using namespace sr;
 extern "C" int64_t sr_ledger_partials(int64_t n_chunks) {
     if (n_chunks < 0) return 0;
     return (partial_rows(n_chunks) + kReduceL1Blocks + 1) * kPartCols;
+}
+
+extern "C" int64_t sr_validity_work(int64_t n) {
+    if (n < 0) return -1;
+    return ((n + kBlock - 1) / kBlock) * SR_VALID_SUMS;
+}
+
+extern "C" int sr_validity(const sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                           const sr_grid *grid, double dt, const sr_params *prm, double tau_em,
+                           uint8_t *flags, double *sums, double *work, void *stream) {
+    return launch_validity<float>(parts, fields, grid, dt, prm, tau_em, flags, sums, work, stream);
 }
 
 extern "C" int sr_eval_push(const sr_particles_f32 *parts, const sr_fields_f32 *fields,

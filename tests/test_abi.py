@@ -172,3 +172,32 @@ def test_eval_trial_quantum_rejects_bad_arguments_on_host(lib):
     assert lib.sr_eval_trial_quantum(d, None, d, d, d, d, 4, None) == L.SR_E_INVAL
     assert lib.sr_eval_trial_quantum(d, d, d, d, d, d, -1, None) == L.SR_E_INVAL
     assert lib.sr_eval_trial_quantum(d, None, None, None, None, None, 0, None) == L.SR_OK
+
+
+def test_validity_and_floor_reject_bad_arguments_on_host(lib):
+    from paper_1409_5574_amd import _lib as L
+    p = L.Particles32()
+    p.n = 10
+    d = C.c_void_p(16)
+    for a in range(3):
+        p.p[a] = d
+    p.w = d
+    p.id = d
+    grid = L.Grid()
+    grid.dim = 0
+    prm = L.Params(1e-5, 7.3e-3, 1, 0, 1, 0, 0, 0, None, None, 0.0)
+    assert lib.sr_validity_work(1000) >= 6 and lib.sr_validity_work(-1) == -1
+    # tau_em must be positive; sums and work are required
+    assert lib.sr_validity(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), 0.0, None, d, d,
+                           None) == L.SR_E_INVAL
+    assert lib.sr_validity(C.byref(p), None, C.byref(grid), 0.1, C.byref(prm), 1.0, None, None, d,
+                           None) == L.SR_E_INVAL
+    ch = L.Chunking(1, None)
+    ph = L.PhotonBuf()
+    led = L.Ledger()
+    # a negative grid frequency, and the floor with the learned sampler
+    for bad in (L.Params(1e-5, 7.3e-3, 1, 0, 1, 0, 0, 0, None, None, -1.0),
+                L.Params(1e-5, 7.3e-3, 1, 2, 1, 0, 0, 0, d, d, 5.0)):
+        rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), 0.1, 1, 0, C.byref(bad), d,
+                                     C.byref(ch), C.byref(ph), C.byref(led), None)
+        assert rc == L.SR_E_INVAL

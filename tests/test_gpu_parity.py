@@ -120,7 +120,7 @@ def _orc_state(d):
 
 def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=None, dtype=np.float32,
                   p_scale=1.0, seed=777, step=3, t=0.4, sampler=0, chunks=None, dn_policy=0,
-                  label=""):
+                  label="", omega_grid=0.0):
     K = cfg.n_samples if K is None else K
     recoil = cfg.recoil if recoil is None else recoil
     kin_cut = cfg.kin_cut if kin_cut is None else kin_cut
@@ -148,7 +148,7 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
     ph_o, led_o, det = oracle.step(orc, fo, cfg.dt, seed, step, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
                                    n_samples=K, recoil=recoil, kin_cut=kin_cut,
                                    sampler={0: 0, 3: 2}.get(sampler, 1), dn_policy=dn_policy,
-                                   push_position=dim != 0, detail=True)
+                                   push_position=dim != 0, detail=True, omega_grid=omega_grid)
     # GPU
     tdtype = torch.float64 if dtype == np.float64 else torch.float32
     gst = {k: (v if k == "id" else v.astype(dtype)) for k, v in st.items()}
@@ -162,7 +162,8 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
         n_chunks = len(chunks) - 1
     photons = sr.PhotonBuffer(n, K, n_chunks=n_chunks, dim=dim if dim else 3)
     ledger = sr.LedgerBuf(4, n_chunks if n_chunks is not None else sr.n_chunks_uniform(n))
-    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, recoil, dn_policy, kin_cut, dim != 0)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, recoil, dn_policy, kin_cut, dim != 0,
+                           omega_grid=omega_grid)
     _say(f"step {label} n={n} K={K} dim={dim} dtype={np.dtype(dtype).name}")
     sr.gather_push_emit(parts, fields, grid, cfg.dt, seed, step, prm, table, photons, ledger, 1,
                         start=start)
@@ -175,6 +176,11 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
     if kin_cut:
         chi = np.repeat(det["chi"], K)
         xcut_band = np.abs(1.5 * chi * det["xs"] - 1.0) <= 1e-5
+    if omega_grid > 0:
+        # photons within FP32 rounding of hbar omega_grid may land on either side
+        eps_x = 1.5 * np.repeat(det["chi"] * det["gamma_bar"], K) * det["xs"]
+        band = np.abs(eps_x / (cfg.hbar_n * omega_grid) - 1.0) <= 1e-5
+        xcut_band = band if xcut_band is None else (xcut_band | band)
     dn_tol = None
     if sampler == 3:
         dn_tol = parity.quantum_dn_tol(np.repeat(det["chi"], K), det["xs"])
@@ -264,3 +270,69 @@ def test_step_quantum_sampler_uniform_K1(sr, table, oracle):
     rep = run_step_case(sr, table, oracle, cfg, 8000, K=1, sampler=3, kin_cut=False,
                         label="uniform quantum K1")
     assert rep["photons_oracle"] > 150
+
+
+def _median_photon_omega(oracle, cfg, n, K, p_scale, sampler, kin_cut):
+    """A grid frequency inside the emitted band of the case (about half the
+    photons below it), from an oracle step of the same case."""
+    st = synth.gen_particles(cfg, n=n)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k].astype(np.float64) * p_scale).astype(np.float32)
+    orc = _orc_state(st)
+    if cfg.dim == 0:
+        fo = oracle.Field(0, b0=cfg.b0)
+        orc["x"] = orc["y"] = orc["z"] = None
+    else:
+        E, B = synth.standing_wave_grid(cfg, 0.4)
+        fo = oracle.Field(cfg.dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
+    ph, _, _ = oracle.step(orc, fo, cfg.dt, 777, 3, hbar_n=cfg.hbar_n, alpha=cfg.alpha, n_samples=K,
+                           recoil=cfg.recoil, kin_cut=kin_cut, sampler={0: 0, 3: 2}.get(sampler, 1),
+                           push_position=cfg.dim != 0)
+    return float(np.median(ph["eps"])) / cfg.hbar_n
+
+
+@pytest.mark.parametrize("sampler", [0, 1, 3])
+def test_step_grid_frequency_floor(sr, table, oracle, sampler):
+    cfg = synth.config("c3", grid=(24, 20, 16), slab=None)
+    kin_cut = sampler == 1
+    og = _median_photon_omega(oracle, cfg, 4099, 8, 3000.0, sampler, kin_cut)
+    rep = run_step_case(sr, table, oracle, cfg, 4099, p_scale=3000.0, sampler=sampler,
+                        kin_cut=kin_cut, omega_grid=og, label=f"3d floor sampler {sampler}")
+    assert rep["photons_oracle"] > 300
+
+
+def test_validity_against_oracle(sr, table, oracle):
+    cfg = synth.config("c3", grid=(24, 20, 16), slab=None)
+    n = 6000
+    st = synth.gen_particles(cfg, n=n)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k].astype(np.float64) * 4000.0).astype(np.float32)
+    old = _orc_state(st)
+    orc = _orc_state(st)
+    E, B = synth.standing_wave_grid(cfg, 0.4)
+    fo = oracle.Field(3, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
+    _, _, det = oracle.step(orc, fo, cfg.dt, 1, 0, hbar_n=cfg.hbar_n, alpha=cfg.alpha, n_samples=1,
+                            recoil=0, push_position=False, detail=True)
+    tau_em = 0.02
+    f_o = oracle.validity_flags(det["heff"], det["chi"], tau_em)
+    pb = 0.5 * (np.stack([old[k] for k in ("px", "py", "pz")], 1)
+                + np.stack([orc[k] for k in ("px", "py", "pz")], 1))
+    beta2 = (pb * pb).sum(1) / det["gamma_bar"] ** 2
+    parts = sr.Particles.from_numpy(st, dim=3)
+    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    fields = sr.Fields(E, B)
+    _say("validity diagnostics")
+    flags, sums = sr.validity(parts, fields, grid, cfg.dt, cfg.hbar_n, cfg.alpha, tau_em)
+    torch.cuda.synchronize()
+    f_g = flags.cpu().numpy()
+    # away from the two thresholds the flags agree exactly
+    away = (np.abs(det["chi"] - 1.0) > 1e-5) & (np.abs(det["heff"] * tau_em - 1.0) > 1e-5)
+    assert np.array_equal(f_g[away], f_o[away])
+    assert (f_o & 1).any() and (f_o & 2).any() and (f_o == 0).any()
+    # the sums, with the oracle's definition over the GPU's flags (the flags are
+    # compared above); the LL energy carries the FP32 chi error
+    ref = oracle.validity_sums(st["w"], det["chi"], beta2, f_g, cfg.alpha, cfg.hbar_n, cfg.dt)
+    np.testing.assert_allclose(sums[:3], ref[:3], rtol=1e-12)
+    np.testing.assert_allclose(sums[3:], ref[3:], rtol=2e-5)
+    # the particles are untouched
+    assert np.array_equal(parts.to_numpy()["px"], st["px"])
