@@ -221,6 +221,21 @@ __device__ __forceinline__ TrialCut trial_cut(bool on, float chi) {
 __device__ __forceinline__ bool trial_is_cut(const TrialCut &c, float lg, bool lower) {
     return lower ? lg > c.lo : lg < c.hi;
 }
+// Grid floor x < xf = e_grid / eps_unit on lg: on the lower branch lg <
+// (4/3) log2 xf, on the upper one lg > -(xf + ln(9/7))/ln2.  The bounds come
+// back in a TrialCut: below lo (lower) or above hi (upper) is under the floor.
+__device__ __forceinline__ TrialCut trial_floor(float e_grid, float eps_unit) {
+    TrialCut c{-__builtin_inff(), __builtin_inff()};
+    if (eps_unit > 0.0f) {
+        const float xf = e_grid / eps_unit;
+        c.lo = 1.3333333333333333f * __builtin_amdgcn_logf(xf);
+        c.hi = -(xf + 0.25131442828090605f) * 1.4426950408889634f;
+    }
+    return c;
+}
+__device__ __forceinline__ bool trial_is_floored(const TrialCut &c, float lg, bool lower) {
+    return lower ? lg < c.lo : lg > c.hi;
+}
 
 // r(chi) and 1 - r(chi), linear in log10 chi; r ~ chi^{-1/3} above the table.
 __device__ __forceinline__ float2 r_lookup(const float2 *__restrict__ rt, float chi) {

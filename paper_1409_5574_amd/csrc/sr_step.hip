@@ -268,7 +268,9 @@ struct StepSmem<KMAX, SR_SAMPLER_QUANTUM> {
 template <typename S>
 __device__ __forceinline__ LedgerSmem &ledger_smem(S &s) { return s.led; }
 
-template <typename R, int DIM, int KMAX, int SAMPLER>
+// FLOOR: the grid-frequency floor is on (a.e_grid > 0); a template flag, so the
+// kernels without it carry none of its code.
+template <typename R, int DIM, int KMAX, int SAMPLER, bool FLOOR>
 __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) {
     __shared__ StepSmem<KMAX, SAMPLER> sm;
 
@@ -364,6 +366,11 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
         const float rate = !active ? 0.0f : (kProposal ? a.rate_c * Hf : a.direct_c * Hf * rr.x);
         if constexpr (SAMPLER != SR_SAMPLER_MLP) {
             const TrialCut cut = trial_cut(SAMPLER == SR_SAMPLER_S && a.kin_cut != 0, chif);
+            // grid cutoff: photons below hbar omega_grid stay with the grid (the
+            // S sampler tests it on R', the quantum one on x, the table sampler
+            // on the drawn x before the slot is taken)
+            TrialCut flr{-__builtin_inff(), __builtin_inff()};
+            if (SAMPLER == SR_SAMPLER_S && FLOOR) flr = trial_floor(a.e_grid, eps_unit);
             uint4 words = make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
@@ -378,8 +385,10 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 if (SAMPLER == SR_SAMPLER_S) {
                     dn = rate * trial_q(wa, a.tab.gtab, a.tab.pa, lg, lower);
                     if (trial_is_cut(cut, lg, lower)) dn = 0.0f;
+                    if (FLOOR && trial_is_floored(flr, lg, lower)) dn = 0.0f;
                 } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
                     dn = rate * quantum_q(wa, a.tab.qtab, a.tab.pa, chif, xq);
+                    if (FLOOR && eps_unit * xq < a.e_grid) dn = 0.0f;
                 }
                 bool emit;
                 float frac = invK;
@@ -389,23 +398,23 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
                 } else {
                     emit = wb < (uint32_t)(dn * 4294967296.0f);
                 }
+                const auto draw_x = [&]() {
+                    if (SAMPLER == SR_SAMPLER_S) return trial_x(wa, lg, lower);
+                    if (SAMPLER == SR_SAMPLER_QUANTUM) return xq;
+                    float lnU, ln1mU;
+                    direct_u(wa, rr, lnU, ln1mU);
+                    return __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                };
                 float x = 0.0f;
-                if (emit) {
-                    if (SAMPLER == SR_SAMPLER_S) {
-                        x = trial_x(wa, lg, lower);
-                    } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
-                        x = xq;
-                    } else {
-                        float lnU, ln1mU;
-                        direct_u(wa, rr, lnU, ln1mU);
-                        x = __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
-                    }
+                constexpr bool kDrawFirst = SAMPLER == SR_SAMPLER_TABLE && FLOOR;
+                if (kDrawFirst && emit) {
+                    x = draw_x();
+                    emit = eps_unit * x >= a.e_grid;
                 }
-                // grid cutoff: photons below hbar omega_grid stay with the grid
-                if (a.e_grid > 0.0f && eps_unit * x < a.e_grid) emit = false;
                 const uint64_t m = __ballot(emit);
                 if (m) {
                     if (emit) {
+                        if (!kDrawFirst) x = draw_x();
                         const float eps = eps_unit * x;
                         const float wph = wi_f * frac;
                         delta_ph += frac * eps;
@@ -884,30 +893,34 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     const int KM = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : 16;
 
     // with events: the dispatch packet itself records the kernel's start and stop
-#define SR_LAUNCH(DIMV, KMV, SMP)                                                              \
+#define SR_LAUNCH(DIMV, KMV, SMP, FL)                                                          \
     if (ev_start || ev_stop)                                                                   \
-        hipExtLaunchKernelGGL(push_emit_kernel<R, DIMV, KMV, SMP>, grd, blk, 0, st,            \
+        hipExtLaunchKernelGGL(push_emit_kernel<R, DIMV, KMV, SMP, FL>, grd, blk, 0, st,        \
                               (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, a);                \
     else                                                                                       \
-        push_emit_kernel<R, DIMV, KMV, SMP><<<grd, blk, 0, st>>>(a)
-#define SR_BY_K(DIMV, SMP)                             \
+        push_emit_kernel<R, DIMV, KMV, SMP, FL><<<grd, blk, 0, st>>>(a)
+#define SR_BY_K(DIMV, SMP, FL)                         \
     switch (KM) {                                      \
-        case 1: SR_LAUNCH(DIMV, 1, SMP); break;        \
-        case 2: SR_LAUNCH(DIMV, 2, SMP); break;        \
-        case 4: SR_LAUNCH(DIMV, 4, SMP); break;        \
-        case 8: SR_LAUNCH(DIMV, 8, SMP); break;        \
-        default: SR_LAUNCH(DIMV, 16, SMP); break;      \
+        case 1: SR_LAUNCH(DIMV, 1, SMP, FL); break;    \
+        case 2: SR_LAUNCH(DIMV, 2, SMP, FL); break;    \
+        case 4: SR_LAUNCH(DIMV, 4, SMP, FL); break;    \
+        case 8: SR_LAUNCH(DIMV, 8, SMP, FL); break;    \
+        default: SR_LAUNCH(DIMV, 16, SMP, FL); break;  \
     }
-#define SR_BY_DIM(SMP)                                 \
+#define SR_BY_DIM(SMP, FL)                             \
     switch (dim) {                                     \
-        case 0: SR_BY_K(0, SMP); break;                \
-        case 2: SR_BY_K(2, SMP); break;                \
-        default: SR_BY_K(3, SMP); break;               \
+        case 0: SR_BY_K(0, SMP, FL); break;            \
+        case 2: SR_BY_K(2, SMP, FL); break;            \
+        default: SR_BY_K(3, SMP, FL); break;           \
     }
-    if (prm->sampler == SR_SAMPLER_S) { SR_BY_DIM(SR_SAMPLER_S); }
-    else if (prm->sampler == SR_SAMPLER_TABLE) { SR_BY_DIM(SR_SAMPLER_TABLE); }
-    else if (prm->sampler == SR_SAMPLER_QUANTUM) { SR_BY_DIM(SR_SAMPLER_QUANTUM); }
-    else { SR_BY_DIM(SR_SAMPLER_MLP); }
+#define SR_BY_FLOOR(SMP)                               \
+    if (a.e_grid > 0.0f) { SR_BY_DIM(SMP, true); }     \
+    else { SR_BY_DIM(SMP, false); }
+    if (prm->sampler == SR_SAMPLER_S) { SR_BY_FLOOR(SR_SAMPLER_S); }
+    else if (prm->sampler == SR_SAMPLER_TABLE) { SR_BY_FLOOR(SR_SAMPLER_TABLE); }
+    else if (prm->sampler == SR_SAMPLER_QUANTUM) { SR_BY_FLOOR(SR_SAMPLER_QUANTUM); }
+    else { SR_BY_DIM(SR_SAMPLER_MLP, false); }
+#undef SR_BY_FLOOR
 #undef SR_BY_DIM
 #undef SR_BY_K
 #undef SR_LAUNCH
