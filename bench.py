@@ -279,7 +279,7 @@ def run(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic() if args.config == "c2" else None,
-                     "kernel": "push_emit_kernel<float,%d,%d,0>" % (dim, 1 if K <= 1 else K),
+                     "kernel": "push_emit_kernel<float,%d,%d,0,false>" % (dim, 1 if K <= 1 else K),
                      "kernel_ms": k1_mean, "algorithmic_bytes_per_launch": bytes_per_launch},
         "push_emit_particle_steps_per_s": n / (k1_mean * 1e-3),
         "field_refresh_ms": float(k9_ms.mean()),
