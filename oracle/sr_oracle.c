@@ -632,3 +632,163 @@ void orc_philox_array(int64_t n, const uint32_t *ctr, const uint32_t key[2], uin
 {
     for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Closing the PIC loop (the field solve and current deposition of the PIC  */
+/* codes the method runs in: section "The field setup" -- particles on a    */
+/* grid with Maxwell's equations, the currents feeding the grid).           */
+/*                                                                          */
+/* Normalised units: E, B in m c omega_r / e, lengths in c / omega_r,       */
+/* densities in n_r = m omega_r^2 / (4 pi e^2), so div E = rho and          */
+/* dE/dt = curl B - J.  A macro-particle of weight w carries charge q w in  */
+/* units of n_r (c/omega_r)^3; rho and J are per cell volume dV.            */
+/*                                                                          */
+/* Charge: first-order (cloud-in-cell) shape on the nodes (i, j, k).        */
+/* Current: Esirkepov's charge-conserving decomposition of the change of    */
+/* that shape between x^n and x^{n+1} (Comput. Phys. Commun. 135, 144,      */
+/* 2001), Jx at (i+1/2, j, k), Jy at (i, j+1/2, k), Jz at (i, j, k+1/2); in */
+/* 2D (no z dependence) Jz sits on the nodes and carries q w v_z.           */
+/* ------------------------------------------------------------------------ */
+
+/* CIC weights of coordinate u (in cells) on the four nodes base..base+3. */
+static void shape4(double u, int64_t base, double s[4])
+{
+    for (int a = 0; a < 4; ++a) {
+        const double d = fabs(u - (double)(base + a));
+        s[a] = d < 1.0 ? 1.0 - d : 0.0;
+    }
+}
+
+int orc_deposit_rho(int64_t n, const double *x, const double *y, const double *z,
+                    const double *w, double q, int32_t dim, const int64_t nn[3],
+                    const double dx[3], double *rho)
+{
+    if (n < 0 || !x || !y || !w || !rho || (dim != 2 && dim != 3) || (dim == 3 && !z)) return -1;
+    const int64_t nx = nn[0], ny = nn[1], nz = dim == 3 ? nn[2] : 1;
+    const double dV = dx[0] * dx[1] * (dim == 3 ? dx[2] : 1.0);
+    for (int64_t p = 0; p < n; ++p) {
+        const double u[3] = {x[p] / dx[0], y[p] / dx[1], dim == 3 ? z[p] / dx[2] : 0.0};
+        int64_t b[3];
+        double s[3][4];
+        for (int a = 0; a < 3; ++a) {
+            b[a] = (int64_t)floor(u[a]) - 1;
+            shape4(u[a], b[a], s[a]);
+        }
+        const int kz = dim == 3 ? 4 : 1;
+        for (int c = 0; c < kz; ++c)
+            for (int bj = 0; bj < 4; ++bj)
+                for (int ai = 0; ai < 4; ++ai) {
+                    const double wt = s[0][ai] * s[1][bj] * (dim == 3 ? s[2][c] : 1.0);
+                    if (wt == 0.0) continue;
+                    const int64_t i = wrap_index(b[0] + ai, nx), j = wrap_index(b[1] + bj, ny);
+                    const int64_t k = dim == 3 ? wrap_index(b[2] + c, nz) : 0;
+                    rho[i + nx * (j + ny * k)] += q * w[p] * wt / dV;
+                }
+    }
+    return 0;
+}
+
+/* The displacement x1 - x0 is taken modulo the box (the shorter way round) and
+ * must be below one cell on every axis; returns -2 otherwise. */
+int orc_deposit_current(int64_t n, const double *x0, const double *y0, const double *z0,
+                        const double *x1, const double *y1, const double *z1, const double *vz,
+                        const double *w, double q, double dt, int32_t dim, const int64_t nn[3],
+                        const double dx[3], double *jx, double *jy, double *jz)
+{
+    if (n < 0 || !x0 || !y0 || !x1 || !y1 || !w || !jx || !jy || !jz || !(dt > 0.0)) return -1;
+    if (dim != 2 && dim != 3) return -1;
+    if (dim == 3 && (!z0 || !z1)) return -1;
+    if (dim == 2 && !vz) return -1;
+    const int64_t nx = nn[0], ny = nn[1], nz = dim == 3 ? nn[2] : 1;
+    const double dV = dx[0] * dx[1] * (dim == 3 ? dx[2] : 1.0);
+    const int64_t ncell[3] = {nx, ny, nz};
+    for (int64_t p = 0; p < n; ++p) {
+        const double a0[3] = {x0[p], y0[p], dim == 3 ? z0[p] : 0.0};
+        const double a1[3] = {x1[p], y1[p], dim == 3 ? z1[p] : 0.0};
+        double u0[3], u1[3];
+        int64_t b[3];
+        double S0[3][4], S1[3][4], D[3][4];
+        const int na = dim;
+        for (int a = 0; a < 3; ++a) {
+            if (a >= na) { u0[a] = u1[a] = 0.0; b[a] = 0; continue; }
+            const double L = (double)ncell[a] * dx[a];
+            double d = a1[a] - a0[a];
+            d -= L * floor(d / L + 0.5);           /* shorter way round the box */
+            u0[a] = a0[a] / dx[a];
+            u1[a] = u0[a] + d / dx[a];
+            if (!(fabs(u1[a] - u0[a]) < 1.0)) return -2;
+            b[a] = (int64_t)floor(u0[a]) - 1;
+            shape4(u0[a], b[a], S0[a]);
+            shape4(u1[a], b[a], S1[a]);
+            for (int c = 0; c < 4; ++c) D[a][c] = S1[a][c] - S0[a][c];
+        }
+        const double qw = q * w[p];
+        if (dim == 3) {
+            /* Jx: W_x = Dx (S0y S0z + Dy S0z/2 + S0y Dz/2 + Dy Dz/3), summed along x */
+            for (int c = 0; c < 4; ++c)
+                for (int bj = 0; bj < 4; ++bj) {
+                    double acc = 0.0;
+                    const double fy = S0[1][bj] * S0[2][c] + 0.5 * D[1][bj] * S0[2][c] +
+                                      0.5 * S0[1][bj] * D[2][c] + D[1][bj] * D[2][c] / 3.0;
+                    for (int ai = 0; ai < 4; ++ai) {
+                        acc -= qw * (dx[0] / dt) * D[0][ai] * fy / dV;
+                        const int64_t i = wrap_index(b[0] + ai, nx), j = wrap_index(b[1] + bj, ny),
+                                      k = wrap_index(b[2] + c, nz);
+                        jx[i + nx * (j + ny * k)] += acc;
+                    }
+                }
+            for (int c = 0; c < 4; ++c)
+                for (int ai = 0; ai < 4; ++ai) {
+                    double acc = 0.0;
+                    const double fx = S0[0][ai] * S0[2][c] + 0.5 * D[0][ai] * S0[2][c] +
+                                      0.5 * S0[0][ai] * D[2][c] + D[0][ai] * D[2][c] / 3.0;
+                    for (int bj = 0; bj < 4; ++bj) {
+                        acc -= qw * (dx[1] / dt) * D[1][bj] * fx / dV;
+                        const int64_t i = wrap_index(b[0] + ai, nx), j = wrap_index(b[1] + bj, ny),
+                                      k = wrap_index(b[2] + c, nz);
+                        jy[i + nx * (j + ny * k)] += acc;
+                    }
+                }
+            for (int bj = 0; bj < 4; ++bj)
+                for (int ai = 0; ai < 4; ++ai) {
+                    double acc = 0.0;
+                    const double fz = S0[0][ai] * S0[1][bj] + 0.5 * D[0][ai] * S0[1][bj] +
+                                      0.5 * S0[0][ai] * D[1][bj] + D[0][ai] * D[1][bj] / 3.0;
+                    for (int c = 0; c < 4; ++c) {
+                        acc -= qw * (dx[2] / dt) * D[2][c] * fz / dV;
+                        const int64_t i = wrap_index(b[0] + ai, nx), j = wrap_index(b[1] + bj, ny),
+                                      k = wrap_index(b[2] + c, nz);
+                        jz[i + nx * (j + ny * k)] += acc;
+                    }
+                }
+        } else {
+            /* 2D: W_x = Dx (S0y + Dy/2), W_y = Dy (S0x + Dx/2); Jz = q w vz
+               (S0x S0y + Dx S0y/2 + S0x Dy/2 + Dx Dy/3) / dV on the nodes */
+            for (int bj = 0; bj < 4; ++bj) {
+                double acc = 0.0;
+                const double fy = S0[1][bj] + 0.5 * D[1][bj];
+                for (int ai = 0; ai < 4; ++ai) {
+                    acc -= qw * (dx[0] / dt) * D[0][ai] * fy / dV;
+                    jx[wrap_index(b[0] + ai, nx) + nx * wrap_index(b[1] + bj, ny)] += acc;
+                }
+            }
+            for (int ai = 0; ai < 4; ++ai) {
+                double acc = 0.0;
+                const double fx = S0[0][ai] + 0.5 * D[0][ai];
+                for (int bj = 0; bj < 4; ++bj) {
+                    acc -= qw * (dx[1] / dt) * D[1][bj] * fx / dV;
+                    jy[wrap_index(b[0] + ai, nx) + nx * wrap_index(b[1] + bj, ny)] += acc;
+                }
+            }
+            for (int bj = 0; bj < 4; ++bj)
+                for (int ai = 0; ai < 4; ++ai) {
+                    const double wt = S0[0][ai] * S0[1][bj] + 0.5 * D[0][ai] * S0[1][bj] +
+                                      0.5 * S0[0][ai] * D[1][bj] + D[0][ai] * D[1][bj] / 3.0;
+                    jz[wrap_index(b[0] + ai, nx) + nx * wrap_index(b[1] + bj, ny)] +=
+                        qw * vz[p] * wt / dV;
+                }
+        }
+    }
+    return 0;
+}
+

@@ -138,6 +138,19 @@ int orc_step(int64_t n, double *x, double *y, double *z,
              const orc_params *prm,
              orc_photons *ph, double ledger[5], orc_detail *det, int32_t threads);
 
+/* Closing the PIC loop: charge and current on the Yee grid (see the C file
+ * for units).  CIC charge on the nodes, rho[i + nx (j + ny k)] += q w S / dV. */
+int orc_deposit_rho(int64_t n, const double *x, const double *y, const double *z,
+                    const double *w, double q, int32_t dim, const int64_t nn[3],
+                    const double dx[3], double *rho);
+/* Esirkepov charge-conserving current of the moves x0 -> x1 (each below one
+ * cell, taken the shorter way round the periodic box); vz: the z velocity for
+ * 2D (ignored in 3D).  Adds into jx, jy, jz.  Returns 0, -1 on a bad argument,
+ * -2 on a move of a cell or more. */
+int orc_deposit_current(int64_t n, const double *x0, const double *y0, const double *z0,
+                        const double *x1, const double *y1, const double *z1, const double *vz,
+                        const double *w, double q, double dt, int32_t dim, const int64_t nn[3],
+                        const double dx[3], double *jx, double *jy, double *jz);
 #ifdef __cplusplus
 }
 #endif
