@@ -53,7 +53,9 @@ enum {
                                   goes to ledger column SR_LED_DROPPED             */
     SR_W_RECOIL_CLAMP = 2u,    /* recoil larger than |p|: p set to 0, remainder in
                                   ledger column SR_LED_CLAMPED                      */
-    SR_W_NONFINITE = 4u        /* a non-finite momentum or field value was met      */
+    SR_W_NONFINITE = 4u,       /* a non-finite momentum or field value was met      */
+    SR_W_CFL = 8u              /* sr_deposit_current: a particle moved a cell or more
+                                  in one step; its current was not deposited         */
 };
 
 /* Ledger columns: one row of SR_LEDGER_COLS doubles per time step (FP64). */
@@ -245,6 +247,53 @@ int sr_eval_synchrotron_F(const sr_table *tab, const float *x, float *out, int64
  * log2 F/(x S) built in FP64 as a function of R' itself. */
 int sr_eval_trial(const sr_table *tab, const uint32_t *a, const float *rate, const float *chi,
                   int32_t kin_cut, float *out_dn, float *out_x, int64_t n, void *stream);
+
+/* ---------------------------------------------------------- the PIC loop
+ * The emission method runs inside a PIC code: particles on a grid, Maxwell's
+ * equations for the field, the particles' currents feeding it (section "The
+ * field setup"); the photons it emits are particles moving at c.  These calls
+ * close that loop around sr_gather_push_emit.  Normalised units: E, B in
+ * m c omega_r / e, lengths in c/omega_r, densities in n_r = m omega_r^2 /
+ * (4 pi e^2): dB/dt = -curl E, dE/dt = curl B - J, div E = rho.  A particle of
+ * weight w carries charge q w in units of n_r (c/omega_r)^3 (per unit length
+ * in z for 2D).  Grid dim 2 or 3, periodic; arrays as sr_fields_f32 (x
+ * fastest), J on the E points, rho on the nodes.  A step: sr_gather_push_emit
+ * (gathers E, B at t^n, moves x^n -> x^{n+1}), sr_deposit_current (J of the
+ * move, from a copy of x^n the caller kept), sr_field_step, sr_photon_advance.
+ * All asynchronous on `stream`; the arrays are the caller's device memory. */
+
+/* One Yee step with E and B kept at whole steps:
+ *   B -= (dt/2) curl E;  E += dt (curl B - J);  B -= (dt/2) curl E
+ * (forward differences for curl E on the B points, backward for curl B on the
+ * E points).  j may be NULL (or j[0] NULL) for no current.  dt must satisfy
+ * the Courant condition dt^2 sum_a 1/dx_a^2 < 1 (SR_E_INVAL otherwise). */
+int sr_field_step(float *e[3], float *b[3], const float *j[3], const sr_grid *grid, double dt,
+                  void *stream);
+
+/* rho += charge w S / dV on the nodes, S the cloud-in-cell weights
+ * (device float[cells], accumulated with float atomics: the order of the sums
+ * is not fixed). */
+int sr_deposit_rho(const sr_particles_f32 *parts, const sr_grid *grid, double charge, float *rho,
+                   void *stream);
+
+/* j += the charge-conserving current of the moves x_old -> parts->x (Esirkepov,
+ * Comput. Phys. Commun. 135, 144 (2001), for the cloud-in-cell shape): the
+ * discrete continuity equation rho(x) - rho(x_old) + dt div J = 0 holds for
+ * the charge of sr_deposit_rho.  Moves are taken the shorter way round the
+ * periodic box and must be below one cell per axis: a particle that moved
+ * further deposits nothing and sets SR_W_CFL in *status (device uint32).  In
+ * 2D, Jz is charge w v_z S / dV with v_z = p_z / gamma(p) of parts->p, the
+ * momentum the position push used.  x_old: device arrays of the positions at
+ * the start of the step (x_old[2] unused in 2D).  Float atomics: the order of
+ * the sums is not fixed. */
+int sr_deposit_current(const sr_particles_f32 *parts, const float *x_old[3], const sr_grid *grid,
+                       double dt, double charge, float *j[3], uint32_t *status, void *stream);
+
+/* Photons move at c along their direction: pos += dt dir for every stored
+ * photon of the buffer (chunked as in sr_gather_push_emit), wrapped into the
+ * periodic box on the grid's axes; pos arrays that are NULL are skipped. */
+int sr_photon_advance(const sr_photon_buf *photons, const sr_chunking *chunks, int64_t n,
+                      const sr_grid *grid, double dt, void *stream);
 
 /* Validity diagnostics of the two limits the paper states for the method:
  *   SR_VALID_QUANTUM          chi >= 1: the classical emission formula fails and a

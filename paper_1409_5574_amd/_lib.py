@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsr.so")
 
 SR_OK, SR_E_INVAL, SR_E_HIP, SR_E_NOMEM, SR_E_UNSUPPORTED = 0, -1, -2, -3, -4
-SR_W_PHOTON_OVERFLOW, SR_W_RECOIL_CLAMP, SR_W_NONFINITE = 1, 2, 4
+SR_W_PHOTON_OVERFLOW, SR_W_RECOIL_CLAMP, SR_W_NONFINITE, SR_W_CFL = 1, 2, 4, 8
 (SR_LED_EMITTED, SR_LED_LL, SR_LED_RECOIL, SR_LED_CLAMPED, SR_LED_DROPPED, SR_LED_PHOTONS,
  SR_LED_WEIGHT, SR_LED_CHI_MAX) = range(8)
 SR_LEDGER_COLS = 8
@@ -87,6 +87,12 @@ SIGNATURES = {
     "sr_validity": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32), C.POINTER(Grid),
                               C.c_double, C.POINTER(Params), C.c_double, _P, _P, _P, _P]),
     "sr_validity_work": (C.c_int64, [_I64]),
+    "sr_field_step": (C.c_int, [P3, P3, P3, C.POINTER(Grid), _D, _P]),
+    "sr_deposit_rho": (C.c_int, [C.POINTER(Particles32), C.POINTER(Grid), _D, _P, _P]),
+    "sr_deposit_current": (C.c_int, [C.POINTER(Particles32), P3, C.POINTER(Grid), _D, _D, P3, _P,
+                                     _P]),
+    "sr_photon_advance": (C.c_int, [C.POINTER(PhotonBuf), C.POINTER(Chunking), _I64,
+                                    C.POINTER(Grid), _D, _P]),
     "sr_philox": (C.c_int, [_P, _U64, _P, _I64, _P]),
     "sr_gather_push_emit": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32),
                                       C.POINTER(Grid), _D, _U64, _U64, C.POINTER(Params), _P,

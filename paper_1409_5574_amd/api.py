@@ -184,6 +184,40 @@ def standing_wave(fields: Fields, grid: L.Grid, a0: float, t: float):
             "sr_field_standing_wave")
 
 
+def field_step(fields: Fields, grid: L.Grid, dt: float, J: list | None = None):
+    """One Yee step of the fields (E and B at whole steps), with current J."""
+    e = L.P3(*[f.data_ptr() for f in fields.e])
+    b = L.P3(*[f.data_ptr() for f in fields.b])
+    j = L.P3(None, None, None) if J is None else L.P3(*[t.data_ptr() for t in J])
+    L.check(lib().sr_field_step(e, b, j, C.byref(grid), float(dt), _stream()), "sr_field_step")
+
+
+def deposit_rho(parts: "Particles", grid: L.Grid, charge: float, rho: torch.Tensor):
+    ps = parts.struct()
+    L.check(lib().sr_deposit_rho(C.byref(ps), C.byref(grid), float(charge), _ptr(rho), _stream()),
+            "sr_deposit_rho")
+
+
+def deposit_current(parts: "Particles", x_old: list, grid: L.Grid, dt: float, charge: float,
+                    J: list, status: torch.Tensor):
+    """J += the charge-conserving current of the moves x_old -> parts.x."""
+    ps = parts.struct()
+    xo = L.P3(*[None if t is None else t.data_ptr() for t in x_old])
+    j = L.P3(*[t.data_ptr() for t in J])
+    L.check(lib().sr_deposit_current(C.byref(ps), xo, C.byref(grid), float(dt), float(charge), j,
+                                     _ptr(status), _stream()), "sr_deposit_current")
+
+
+def photon_advance(photons: "PhotonBuffer", n: int, grid: L.Grid, dt: float,
+                   start: torch.Tensor | None = None):
+    cs = L.Chunking()
+    cs.n_chunks = n_chunks_uniform(n) if start is None else start.numel() - 1
+    cs.start = None if start is None else start.data_ptr()
+    phs = photons.struct()
+    L.check(lib().sr_photon_advance(C.byref(phs), C.byref(cs), n, C.byref(grid), float(dt),
+                                    _stream()), "sr_photon_advance")
+
+
 def n_chunks_uniform(n: int) -> int:
     return (n + L.SR_CHUNK - 1) // L.SR_CHUNK
 

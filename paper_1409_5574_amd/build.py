@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["sr_table.hip", "sr_step.hip", "sr_aux.hip", "sr_mlp.hip"]
+SOURCES = ["sr_table.hip", "sr_step.hip", "sr_aux.hip", "sr_mlp.hip", "sr_pic.hip"]
 OUT = os.path.join(HERE, "libsr.so")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,433 @@
+// sr_pic.hip -- closing the PIC loop around the emission step: the Yee field
+// solve, the grid charge and the charge-conserving current of the particles'
+// moves, and the ballistic motion of the emitted photons.
+//
+// The paper's emission method runs inside a PIC code: particles on a grid,
+// Maxwell's equations for the field, the particles' currents feeding it
+// (section "The field setup"); the photons it emits are particles that move at
+// c along their direction.  Normalised units: E, B in m c omega_r / e, lengths
+// in c/omega_r, densities in n_r = m omega_r^2 / (4 pi e^2), so
+//     dB/dt = -curl E,   dE/dt = curl B - J,   div E = rho.
+// A step keeps E and B at whole steps, where the particles gather them:
+//     B -= (dt/2) curl E;   E += dt (curl B - J);   B -= (dt/2) curl E.
+#include <math.h>
+
+#include "sr_common.hpp"
+
+namespace sr {
+namespace {
+
+// Grid geometry for the PIC kernels (positions from the lower corner).
+struct PicGrid {
+    int n[3];
+    float inv_hi[3], inv_lo[3];   // 1/dx split so that x/dx keeps ~2^-24 absolute accuracy
+    float L[3];                   // box lengths
+    float dV;                     // cell volume (2D: dx dy)
+};
+
+inline int pic_grid(const sr_grid *g, PicGrid &G) {
+    if (!g || (g->dim != 2 && g->dim != 3)) return SR_E_INVAL;
+    if (g->dim == 2 && g->n[2] != 1) return SR_E_INVAL;
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1 || g->n[a] > (1 << 24)) return SR_E_INVAL;
+        if (a < g->dim && (!(g->dx[a] > 0.0) || !isfinite(g->dx[a]))) return SR_E_INVAL;
+        cells *= g->n[a];
+    }
+    if (cells >= (int64_t)1 << 30) return SR_E_UNSUPPORTED;
+    G.dV = 1.0f;
+    for (int a = 0; a < 3; ++a) {
+        G.n[a] = (int)g->n[a];
+        const double inv = a < g->dim ? 1.0 / g->dx[a] : 0.0;
+        G.inv_hi[a] = (float)inv;
+        G.inv_lo[a] = (float)(inv - (double)G.inv_hi[a]);
+        G.L[a] = a < g->dim ? (float)(g->n[a] * g->dx[a]) : 0.0f;
+        if (a < g->dim) G.dV *= (float)g->dx[a];
+    }
+    return SR_OK;
+}
+
+__device__ __forceinline__ uint32_t cell(int i, int j, int k, const PicGrid &G) {
+    return (uint32_t)i + (uint32_t)G.n[0] * ((uint32_t)j + (uint32_t)G.n[1] * (uint32_t)k);
+}
+__device__ __forceinline__ int up(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+__device__ __forceinline__ int dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+
+// ------------------------------------------------------------ Yee field solve
+// B -= h curl E on the B points (forward differences), one thread per cell.
+template <int DIM>
+__global__ __launch_bounds__(256) void curl_e_kernel(const float *__restrict__ ex,
+                                                     const float *__restrict__ ey,
+                                                     const float *__restrict__ ez,
+                                                     float *__restrict__ bx, float *__restrict__ by,
+                                                     float *__restrict__ bz, PicGrid G, float hx,
+                                                     float hy, float hz, uint32_t cells) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int nx = G.n[0], ny = G.n[1];
+    const int i = (int)(c % (uint32_t)nx), r = (int)(c / (uint32_t)nx);
+    const int j = r % ny, k = r / ny;
+    const uint32_t cx = cell(up(i, nx), j, k, G), cy = cell(i, up(j, ny), k, G);
+    const float ex0 = ld(ex, c), ey0 = ld(ey, c), ez0 = ld(ez, c);
+    // hx = h/dx etc.
+    float dbx = hy * (ld(ez, cy) - ez0);
+    float dby = -hx * (ld(ez, cx) - ez0);
+    const float dbz = hx * (ld(ey, cx) - ey0) - hy * (ld(ex, cy) - ex0);
+    if (DIM == 3) {
+        const uint32_t cz = cell(i, j, up(k, G.n[2]), G);
+        dbx -= hz * (ld(ey, cz) - ey0);
+        dby += hz * (ld(ex, cz) - ex0);
+    }
+    st(bx, c, ld(bx, c) - dbx);
+    st(by, c, ld(by, c) - dby);
+    st(bz, c, ld(bz, c) - dbz);
+}
+
+// E += dt (curl B - J) on the E points (backward differences).
+template <int DIM, bool HAS_J>
+__global__ __launch_bounds__(256) void curl_b_kernel(float *__restrict__ ex, float *__restrict__ ey,
+                                                     float *__restrict__ ez,
+                                                     const float *__restrict__ bx,
+                                                     const float *__restrict__ by,
+                                                     const float *__restrict__ bz,
+                                                     const float *__restrict__ jx,
+                                                     const float *__restrict__ jy,
+                                                     const float *__restrict__ jz, PicGrid G,
+                                                     float dt, float tx, float ty, float tz,
+                                                     uint32_t cells) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int nx = G.n[0], ny = G.n[1];
+    const int i = (int)(c % (uint32_t)nx), r = (int)(c / (uint32_t)nx);
+    const int j = r % ny, k = r / ny;
+    const uint32_t cx = cell(dn(i, nx), j, k, G), cy = cell(i, dn(j, ny), k, G);
+    const float bx0 = ld(bx, c), by0 = ld(by, c), bz0 = ld(bz, c);
+    // tx = dt/dx etc.
+    float dex = ty * (bz0 - ld(bz, cy));
+    float dey = -tx * (bz0 - ld(bz, cx));
+    float dez = tx * (by0 - ld(by, cx)) - ty * (bx0 - ld(bx, cy));
+    if (DIM == 3) {
+        const uint32_t cz = cell(i, j, dn(k, G.n[2]), G);
+        dex -= tz * (by0 - ld(by, cz));
+        dey += tz * (bx0 - ld(bx, cz));
+    }
+    if (HAS_J) {
+        dex = fmaf(-dt, ld(jx, c), dex);
+        dey = fmaf(-dt, ld(jy, c), dey);
+        dez = fmaf(-dt, ld(jz, c), dez);
+    }
+    st(ex, c, ld(ex, c) + dex);
+    st(ey, c, ld(ey, c) + dey);
+    st(ez, c, ld(ez, c) + dez);
+}
+
+// --------------------------------------------------- charge and current
+// Position on one axis as (cell index, fraction in [0, 1)).
+__device__ __forceinline__ void locate(float x, float inv_hi, float inv_lo, int n, int &i, float &f) {
+    const float u = x * inv_hi;
+    float fi = floorf(u);
+    float fr = fmaf(x, inv_hi, -fi) + x * inv_lo;
+    if (fr < 0.0f) { fr += 1.0f; fi -= 1.0f; }
+    if (fr >= 1.0f) { fr -= 1.0f; fi += 1.0f; }
+    i = (int)fi;
+    i = i < 0 ? i + n : (i >= n ? i - n : i);
+    i = min(max(i, 0), n - 1);
+    f = fr;
+}
+
+// Node index base + c (c = 0..3, base = i - 1) wrapped into [0, n).
+__device__ __forceinline__ int node(int i, int c, int n) {
+    int v = i - 1 + c;
+    v = v < 0 ? v + n : (v >= n ? v - n : v);
+    return min(max(v, 0), n - 1);
+}
+
+// CIC weight of a particle at relative coordinate r (cells from node i) on the
+// node i - 1 + c.
+__device__ __forceinline__ float cic_w(float r, int c) {
+    return fmaxf(0.0f, 1.0f - fabsf(r - (float)(c - 1)));
+}
+
+// Charge: rho += q w S / dV on the 4 (2D) or 8 (3D) nodes of each particle.
+template <int DIM>
+__global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G, float qv,
+                                                  float *__restrict__ rho) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    const uint32_t u = (uint32_t)p;
+    int I[3] = {0, 0, 0};
+    float F[3] = {0.0f, 0.0f, 0.0f};
+    for (int a = 0; a < DIM; ++a) locate(ld(P.x[a], u), G.inv_hi[a], G.inv_lo[a], G.n[a], I[a], F[a]);
+    const float qw = qv * ld(P.w, u) / G.dV;
+    for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                const float wt = (a ? F[0] : 1.0f - F[0]) * (b ? F[1] : 1.0f - F[1]) *
+                                 (DIM == 3 ? (c ? F[2] : 1.0f - F[2]) : 1.0f);
+                const int i = node(I[0], 1 + a, G.n[0]), j = node(I[1], 1 + b, G.n[1]);
+                const int k = DIM == 3 ? node(I[2], 1 + c, G.n[2]) : 0;
+                unsafeAtomicAdd(&rho[cell(i, j, k, G)], qw * wt);
+            }
+}
+
+// Esirkepov's current of the move x_old -> x (one lane per particle).  On each
+// axis the old shape S0 and the new shape S1 live on nodes i-1 .. i+2 of the
+// old cell i (moves below one cell); D = S1 - S0.  Per node of the stencil
+//   3D  W_x = Dx (S0y S0z + Dy S0z/2 + S0y Dz/2 + Dy Dz/3)  (and cyclically),
+//   Jx(i+1/2) = Jx(i-1/2) - q w (dx/dt) W_x / dV, summed along x;
+//   2D  W_x = Dx (S0y + Dy/2),  W_y = Dy (S0x + Dx/2),
+//       Jz = q w v_z (S0x S0y + Dx S0y/2 + S0x Dy/2 + Dx Dy/3) / dV on the nodes.
+// Zero contributions are skipped.  A move of a cell or more sets *status.
+template <int DIM>
+__global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const float *xo0,
+                                                      const float *xo1, const float *xo2,
+                                                      PicGrid G, float qv, float inv_dt,
+                                                      float *__restrict__ jx, float *__restrict__ jy,
+                                                      float *__restrict__ jz,
+                                                      uint32_t *__restrict__ status) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    const uint32_t u = (uint32_t)p;
+    const float *xo[3] = {xo0, xo1, xo2};
+    int I[3] = {0, 0, 0};
+    float S0[3][4], D[3][4];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a >= DIM) {
+            for (int c = 0; c < 4; ++c) { S0[a][c] = c == 1 ? 1.0f : 0.0f; D[a][c] = 0.0f; }
+            continue;
+        }
+        const float x0 = ld(xo[a], u), x1 = ld(P.x[a], u);
+        float d = x1 - x0;                       // the shorter way round the box
+        if (d > 0.5f * G.L[a]) d -= G.L[a];
+        else if (d < -0.5f * G.L[a]) d += G.L[a];
+        float f0;
+        locate(x0, G.inv_hi[a], G.inv_lo[a], G.n[a], I[a], f0);
+        const float du = d * G.inv_hi[a];
+        ok = ok && fabsf(du) < 1.0f;
+        const float r1 = f0 + du;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            S0[a][c] = cic_w(f0, c);
+            D[a][c] = cic_w(r1, c) - S0[a][c];
+        }
+    }
+    if (!ok) {
+        atomicOr(status, SR_W_CFL);
+        return;
+    }
+    const float qw = qv * ld(P.w, u);
+    const float inv_dV = 1.0f / G.dV;
+    int ix[4], iy[4], iz[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        ix[c] = node(I[0], c, G.n[0]);
+        iy[c] = node(I[1], c, G.n[1]);
+        iz[c] = DIM == 3 ? node(I[2], c, G.n[2]) : 0;
+    }
+    // dx/dt = L/(n dt); with the split inverse, dx = 1/inv (exact enough for the scale)
+    const float cx = -qw * inv_dt * inv_dV / (G.inv_hi[0] + G.inv_lo[0]);
+    const float cy = -qw * inv_dt * inv_dV / (G.inv_hi[1] + G.inv_lo[1]);
+    if (DIM == 3) {
+        const float cz = -qw * inv_dt * inv_dV / (G.inv_hi[2] + G.inv_lo[2]);
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 4; ++j) {
+                const float f = S0[1][j] * S0[2][k] + 0.5f * D[1][j] * S0[2][k] +
+                                0.5f * S0[1][j] * D[2][k] + D[1][j] * D[2][k] * (1.0f / 3.0f);
+                if (f == 0.0f) continue;
+                float acc = 0.0f;
+                for (int i = 0; i < 3; ++i) {
+                    acc += cx * D[0][i] * f;
+                    if (acc != 0.0f) unsafeAtomicAdd(&jx[cell(ix[i], iy[j], iz[k], G)], acc);
+                }
+            }
+        for (int k = 0; k < 4; ++k)
+            for (int i = 0; i < 4; ++i) {
+                const float f = S0[0][i] * S0[2][k] + 0.5f * D[0][i] * S0[2][k] +
+                                0.5f * S0[0][i] * D[2][k] + D[0][i] * D[2][k] * (1.0f / 3.0f);
+                if (f == 0.0f) continue;
+                float acc = 0.0f;
+                for (int j = 0; j < 3; ++j) {
+                    acc += cy * D[1][j] * f;
+                    if (acc != 0.0f) unsafeAtomicAdd(&jy[cell(ix[i], iy[j], iz[k], G)], acc);
+                }
+            }
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i) {
+                const float f = S0[0][i] * S0[1][j] + 0.5f * D[0][i] * S0[1][j] +
+                                0.5f * S0[0][i] * D[1][j] + D[0][i] * D[1][j] * (1.0f / 3.0f);
+                if (f == 0.0f) continue;
+                float acc = 0.0f;
+                for (int k = 0; k < 3; ++k) {
+                    acc += cz * D[2][k] * f;
+                    if (acc != 0.0f) unsafeAtomicAdd(&jz[cell(ix[i], iy[j], iz[k], G)], acc);
+                }
+            }
+    } else {
+        for (int j = 0; j < 4; ++j) {
+            const float f = S0[1][j] + 0.5f * D[1][j];
+            if (f == 0.0f) continue;
+            float acc = 0.0f;
+            for (int i = 0; i < 3; ++i) {
+                acc += cx * D[0][i] * f;
+                if (acc != 0.0f) unsafeAtomicAdd(&jx[cell(ix[i], iy[j], 0, G)], acc);
+            }
+        }
+        for (int i = 0; i < 4; ++i) {
+            const float f = S0[0][i] + 0.5f * D[0][i];
+            if (f == 0.0f) continue;
+            float acc = 0.0f;
+            for (int j = 0; j < 3; ++j) {
+                acc += cy * D[1][j] * f;
+                if (acc != 0.0f) unsafeAtomicAdd(&jy[cell(ix[i], iy[j], 0, G)], acc);
+            }
+        }
+        // v_z of the move from the momentum the position push used
+        const float pz = ld(P.p[2], u), px = ld(P.p[0], u), py = ld(P.p[1], u);
+        const float vz = pz * __builtin_amdgcn_rsqf(1.0f + px * px + py * py + pz * pz);
+        const float cz = qw * vz * inv_dV;
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i) {
+                const float wt = S0[0][i] * S0[1][j] + 0.5f * D[0][i] * S0[1][j] +
+                                 0.5f * S0[0][i] * D[1][j] + D[0][i] * D[1][j] * (1.0f / 3.0f);
+                if (wt != 0.0f && cz != 0.0f)
+                    unsafeAtomicAdd(&jz[cell(ix[i], iy[j], 0, G)], cz * wt);
+            }
+    }
+}
+
+// Photons move at c along their direction: pos += dt dir, wrapped into the box
+// (one lane per chunk segment, as the photon histograms).
+__global__ __launch_bounds__(256) void photon_advance_kernel(sr_photon_buf ph, const int64_t *start,
+                                                             int64_t n_chunks, int64_t n, PicGrid G,
+                                                             int dim, float dt) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const int64_t s0 = start ? start[c] : c * (int64_t)kChunk;
+    const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kChunk, n);
+    const int64_t cap = (e0 - s0) * ph.per_particle;
+    const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
+    const int64_t base = s0 * ph.per_particle;
+    for (int64_t q = 0; q < cnt; ++q) {
+        const uint32_t o = (uint32_t)(base + q);
+        for (int a = 0; a < 3; ++a) {
+            if (!ph.pos[a]) continue;
+            float v = fmaf(dt, ld(ph.dir[a], o), ld(ph.pos[a], o));
+            if (a < dim) {
+                const float L = G.L[a];
+                v -= L * floorf(v / L);
+                if (v >= L || v < 0.0f) v = 0.0f;   // rounding guard (and a corrupt value)
+            }
+            st(ph.pos[a], o, v);
+        }
+    }
+}
+
+}  // namespace
+}  // namespace sr
+
+using namespace sr;
+
+extern "C" int sr_field_step(float *e[3], float *b[3], const float *j[3], const sr_grid *grid,
+                             double dt, void *stream) {
+    PicGrid G;
+    const int rc = pic_grid(grid, G);
+    if (rc != SR_OK) return rc;
+    if (!e || !b) return SR_E_INVAL;
+    for (int q = 0; q < 3; ++q)
+        if (!e[q] || !b[q]) return SR_E_INVAL;
+    const bool has_j = j && j[0];
+    if (has_j && (!j[1] || !j[2])) return SR_E_INVAL;
+    // Courant condition of the Yee scheme: dt^2 (sum 1/dx_a^2) < 1
+    double s = 0.0;
+    for (int a = 0; a < grid->dim; ++a) s += 1.0 / (grid->dx[a] * grid->dx[a]);
+    if (!(dt > 0.0) || !(dt * dt * s < 1.0)) return SR_E_INVAL;
+    const uint32_t cells = (uint32_t)(grid->n[0] * grid->n[1] * grid->n[2]);
+    const unsigned nb = (cells + 255) / 256;
+    hipStream_t st = (hipStream_t)stream;
+    const float h[3] = {(float)(0.5 * dt / grid->dx[0]), (float)(0.5 * dt / grid->dx[1]),
+                        grid->dim == 3 ? (float)(0.5 * dt / grid->dx[2]) : 0.0f};
+    const float t[3] = {2.0f * h[0], 2.0f * h[1], 2.0f * h[2]};
+    for (int half = 0; half < 3; ++half) {
+        if (half == 1) {
+            if (grid->dim == 3) {
+                if (has_j) curl_b_kernel<3, true><<<nb, 256, 0, st>>>(e[0], e[1], e[2], b[0], b[1], b[2], j[0], j[1], j[2], G, (float)dt, t[0], t[1], t[2], cells);
+                else curl_b_kernel<3, false><<<nb, 256, 0, st>>>(e[0], e[1], e[2], b[0], b[1], b[2], nullptr, nullptr, nullptr, G, (float)dt, t[0], t[1], t[2], cells);
+            } else {
+                if (has_j) curl_b_kernel<2, true><<<nb, 256, 0, st>>>(e[0], e[1], e[2], b[0], b[1], b[2], j[0], j[1], j[2], G, (float)dt, t[0], t[1], t[2], cells);
+                else curl_b_kernel<2, false><<<nb, 256, 0, st>>>(e[0], e[1], e[2], b[0], b[1], b[2], nullptr, nullptr, nullptr, G, (float)dt, t[0], t[1], t[2], cells);
+            }
+        } else {
+            if (grid->dim == 3)
+                curl_e_kernel<3><<<nb, 256, 0, st>>>(e[0], e[1], e[2], b[0], b[1], b[2], G, h[0], h[1], h[2], cells);
+            else
+                curl_e_kernel<2><<<nb, 256, 0, st>>>(e[0], e[1], e[2], b[0], b[1], b[2], G, h[0], h[1], h[2], cells);
+        }
+    }
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_deposit_rho(const sr_particles_f32 *parts, const sr_grid *grid, double charge,
+                              float *rho, void *stream) {
+    PicGrid G;
+    const int rc = pic_grid(grid, G);
+    if (rc != SR_OK) return rc;
+    if (!parts || !rho || parts->n < 0 || parts->n >= ((int64_t)1 << 31)) return SR_E_INVAL;
+    if (parts->n == 0) return SR_OK;
+    if (!parts->x[0] || !parts->x[1] || (grid->dim == 3 && !parts->x[2]) || !parts->w)
+        return SR_E_INVAL;
+    const unsigned nb = (unsigned)((parts->n + 255) / 256);
+    hipStream_t st = (hipStream_t)stream;
+    if (grid->dim == 3) rho_kernel<3><<<nb, 256, 0, st>>>(*parts, G, (float)charge, rho);
+    else rho_kernel<2><<<nb, 256, 0, st>>>(*parts, G, (float)charge, rho);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_deposit_current(const sr_particles_f32 *parts, const float *x_old[3],
+                                  const sr_grid *grid, double dt, double charge, float *j[3],
+                                  uint32_t *status, void *stream) {
+    PicGrid G;
+    const int rc = pic_grid(grid, G);
+    if (rc != SR_OK) return rc;
+    if (!parts || !x_old || !j || !status || !(dt > 0.0) || parts->n < 0 ||
+        parts->n >= ((int64_t)1 << 31))
+        return SR_E_INVAL;
+    for (int q = 0; q < 3; ++q)
+        if (!j[q]) return SR_E_INVAL;
+    if (parts->n == 0) return SR_OK;
+    const int dim = grid->dim;
+    for (int a = 0; a < dim; ++a)
+        if (!parts->x[a] || !x_old[a]) return SR_E_INVAL;
+    if (!parts->w || (dim == 2 && (!parts->p[0] || !parts->p[1] || !parts->p[2])))
+        return SR_E_INVAL;
+    const unsigned nb = (unsigned)((parts->n + 255) / 256);
+    hipStream_t st = (hipStream_t)stream;
+    if (dim == 3)
+        current_kernel<3><<<nb, 256, 0, st>>>(*parts, x_old[0], x_old[1], x_old[2], G, (float)charge,
+                                              (float)(1.0 / dt), j[0], j[1], j[2], status);
+    else
+        current_kernel<2><<<nb, 256, 0, st>>>(*parts, x_old[0], x_old[1], nullptr, G, (float)charge,
+                                              (float)(1.0 / dt), j[0], j[1], j[2], status);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+extern "C" int sr_photon_advance(const sr_photon_buf *ph, const sr_chunking *chunks, int64_t n,
+                                 const sr_grid *grid, double dt, void *stream) {
+    PicGrid G;
+    const int rc = pic_grid(grid, G);
+    if (rc != SR_OK) return rc;
+    if (!ph || !chunks || n < 0 || !ph->seg_count || !(dt >= 0.0)) return SR_E_INVAL;
+    const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
+    if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
+    if (!ph->dir[0] || !ph->dir[1] || !ph->dir[2]) return SR_E_INVAL;
+    if (n * ph->per_particle >= ((int64_t)1 << 32)) return SR_E_UNSUPPORTED;
+    const unsigned nb = (unsigned)((n_chunks + 255) / 256);
+    photon_advance_kernel<<<nb, 256, 0, (hipStream_t)stream>>>(*ph, chunks->start, n_chunks, n, G,
+                                                               grid->dim, (float)dt);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}

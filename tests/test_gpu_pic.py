@@ -1,0 +1,269 @@
+"""GPU parity of the PIC-loop kernels against the oracle: the Yee field step,
+the cloud-in-cell charge, the Esirkepov current (and the discrete continuity
+equation on the GPU's own results), photon advance, and Gauss's law kept over
+a few steps of the whole loop with emission."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1409_5574_amd import api
+    api.lib()
+    return api
+
+
+def _geom(dim):
+    if dim == 2:
+        return (40, 36, 1), (0.3, 0.25, 1.0)
+    return (20, 18, 16), (0.3, 0.25, 0.35)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32).ravel()).to("cuda")
+
+
+def _host(t, shape):
+    return t.cpu().numpy().astype(np.float64).reshape(shape)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_field_step_matches_oracle(sr, dim):
+    n, dx = _geom(dim)
+    shape = (n[2], n[1], n[0])
+    rng = np.random.default_rng(10 + dim)
+    E = [rng.normal(size=shape).astype(np.float32) for _ in range(3)]
+    B = [rng.normal(size=shape).astype(np.float32) for _ in range(3)]
+    J = [rng.normal(size=shape).astype(np.float32) for _ in range(3)]
+    dt = 0.45 * min(dx[:dim])
+    grid = sr.grid_struct(dim, n=n, dx=dx)
+    f = sr.Fields([a.ravel() for a in E], [a.ravel() for a in B])
+    Jd = [_dev(a) for a in J]
+    _say(f"field step {dim}D")
+    steps = 5
+    for _ in range(steps):
+        sr.field_step(f, grid, dt, Jd)
+    torch.cuda.synchronize()
+    Eo = [a.astype(np.float64) for a in E]
+    Bo = [a.astype(np.float64) for a in B]
+    Jo = [a.astype(np.float64) for a in J]
+    for _ in range(steps):
+        pic.fdtd_step(Eo, Bo, Jo, dt, dx)
+    for q in range(3):
+        for got, ref in ((_host(f.e[q], shape), Eo[q]), (_host(f.b[q], shape), Bo[q])):
+            assert np.max(np.abs(got - ref)) <= 1e-5 * max(np.max(np.abs(ref)), 1.0), q
+
+
+def test_field_step_plane_wave(sr):
+    # a wave along y in 3D (Ez, Bx) against the Yee scheme's exact discrete solution
+    n, dx = _geom(3)
+    shape = (n[2], n[1], n[0])
+    dt = 0.45 * min(dx)
+    L = n[1] * dx[1]
+    k = 2 * math.pi * 2 / L
+    w = 2.0 / dt * math.asin(dt / dx[1] * math.sin(k * dx[1] / 2))
+    j = np.indices(shape)[1].astype(np.float64)
+    ye, yb = j * dx[1], (j + 0.5) * dx[1]
+    E = [np.zeros(shape) for _ in range(3)]
+    B = [np.zeros(shape) for _ in range(3)]
+    E[2] = np.cos(k * ye)
+    B[0] = np.cos(k * yb - w * dt / 2)
+    c = pic.curl_E(E, dx)
+    for q in range(3):
+        B[q] += 0.5 * dt * c[q]
+    grid = sr.grid_struct(3, n=n, dx=dx)
+    f = sr.Fields([a.astype(np.float32).ravel() for a in E], [a.astype(np.float32).ravel() for a in B])
+    _say("field step plane wave")
+    steps = 100
+    for _ in range(steps):
+        sr.field_step(f, grid, dt, None)
+    torch.cuda.synchronize()
+    got = _host(f.e[2], shape)
+    assert np.max(np.abs(got - np.cos(k * ye - w * steps * dt))) < 2e-4
+
+
+def _moves(dim, n, dx, count, rng, frac=0.9):
+    box = np.array([n[a] * dx[a] for a in range(dim)])
+    p0 = (rng.uniform(0, 1, (count, dim)) * box).astype(np.float32)
+    d = rng.uniform(-frac, frac, (count, dim)) * np.array(dx[:dim])
+    p1 = np.mod(p0.astype(np.float64) + d, box).astype(np.float32)
+    p1 = np.where(p1 >= box.astype(np.float32), 0.0, p1).astype(np.float32)
+    return p0, p1
+
+
+def _parts(sr, dim, pos, p, w):
+    n = pos.shape[0]
+    st = {"x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy() if dim == 3 else None,
+          "px": p[:, 0].astype(np.float32), "py": p[:, 1].astype(np.float32),
+          "pz": p[:, 2].astype(np.float32), "w": w.astype(np.float32),
+          "id": np.arange(n, dtype=np.uint32)}
+    return sr.Particles.from_numpy(st, dim=dim)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_current_matches_oracle_and_conserves_charge(sr, dim):
+    n, dx = _geom(dim)
+    shape = (n[2], n[1], n[0])
+    rng = np.random.default_rng(20 + dim)
+    count = 20000
+    p0, p1 = _moves(dim, n, dx, count, rng)
+    w = rng.uniform(0.5, 2.0, count).astype(np.float32)
+    mom = rng.normal(0, 3.0, (count, 3)).astype(np.float32)
+    grid = sr.grid_struct(dim, n=n, dx=dx)
+    parts = _parts(sr, dim, p1, mom, w)
+    x_old = [_dev(p0[:, a]) for a in range(dim)] + [None] * (3 - dim)
+    cells = int(np.prod(shape))
+    J = [torch.zeros(cells, device="cuda", dtype=torch.float32) for _ in range(3)]
+    status = torch.zeros(1, device="cuda", dtype=torch.int32)
+    q, dt = -1.0, 0.11
+    _say(f"deposit current {dim}D {count}")
+    sr.deposit_current(parts, x_old, grid, dt, q, J, status)
+    r0 = torch.zeros(cells, device="cuda", dtype=torch.float32)
+    r1 = torch.zeros(cells, device="cuda", dtype=torch.float32)
+    parts_old = _parts(sr, dim, p0, mom, w)
+    sr.deposit_rho(parts_old, grid, q, r0)
+    sr.deposit_rho(parts, grid, q, r1)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    pm = mom.astype(np.float64)
+    vz = pm[:, 2] / np.sqrt(1 + (pm * pm).sum(1))
+    Jo = pic.deposit_current(p0.astype(np.float64), p1.astype(np.float64), vz, w, q, dt, dim, n, dx)
+    ro0 = pic.deposit_rho(p0.astype(np.float64), w, q, dim, n, dx)
+    Jg = [_host(t, shape) for t in J]
+    for a in range(3):
+        scale = max(np.max(np.abs(Jo[a])), 1e-30)
+        assert np.max(np.abs(Jg[a] - Jo[a])) <= 2e-5 * scale, (a, np.max(np.abs(Jg[a] - Jo[a])) / scale)
+    rg0, rg1 = _host(r0, shape), _host(r1, shape)
+    assert np.max(np.abs(rg0 - ro0)) <= 1e-5 * np.max(np.abs(ro0))
+    # discrete continuity on the GPU's own charge and current
+    resid = rg1 - rg0 + dt * pic.div_E(Jg, dx)
+    assert np.max(np.abs(resid)) <= 2e-5 * np.max(np.abs(rg0))
+
+
+def test_current_flags_long_moves(sr):
+    dim = 2
+    n, dx = _geom(dim)
+    shape = (n[2], n[1], n[0])
+    pos0 = np.array([[1.0, 1.0], [2.0, 2.0]], np.float32)
+    pos1 = np.array([[1.1, 1.05], [2.0 + 1.5 * dx[0], 2.0]], np.float32)   # second: 1.5 cells
+    mom = np.zeros((2, 3), np.float32)
+    w = np.ones(2, np.float32)
+    grid = sr.grid_struct(dim, n=n, dx=dx)
+    parts = _parts(sr, dim, pos1, mom, w)
+    cells = int(np.prod(shape))
+    J = [torch.zeros(cells, device="cuda", dtype=torch.float32) for _ in range(3)]
+    status = torch.zeros(1, device="cuda", dtype=torch.int32)
+    _say("deposit current long move")
+    sr.deposit_current(parts, [_dev(pos0[:, 0]), _dev(pos0[:, 1]), None], grid, 0.1, -1.0, J, status)
+    torch.cuda.synchronize()
+    from paper_1409_5574_amd import _lib as L
+    assert int(status.item()) & L.SR_W_CFL
+    Jo = pic.deposit_current(pos0[:1].astype(np.float64), pos1[:1].astype(np.float64), [0.0], [1.0],
+                             -1.0, 0.1, dim, n, dx)
+    for a in range(2):
+        np.testing.assert_allclose(_host(J[a], shape), Jo[a], rtol=0, atol=2e-5 * np.max(np.abs(Jo[a])))
+
+
+def test_photon_advance_matches_oracle(sr):
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    n = 20000
+    st = synth.gen_particles(cfg, n=n)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k] * 2000.0).astype(np.float32)
+    parts = sr.Particles.from_numpy(st, dim=2)
+    grid = sr.grid_struct(2, n=cfg.grid, dx=(cfg.dx,) * 3)
+    E, B = synth.standing_wave_grid(cfg, 0.4)
+    fields = sr.Fields(E, B)
+    photons = sr.PhotonBuffer(n, 2, dim=2)
+    ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
+    table = sr.Table()
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, 2, kin_cut=cfg.kin_cut)
+    _say("photon advance")
+    sr.gather_push_emit(parts, fields, grid, cfg.dt, 5, 0, prm, table, photons, ledger, 0)
+    torch.cuda.synchronize()
+    before = photons.gather(n)
+    assert before["count"] > 1000
+    dt = 7.3
+    sr.photon_advance(photons, n, grid, dt)
+    torch.cuda.synchronize()
+    after = photons.gather(n)
+    box = (cfg.grid[0] * cfg.dx, cfg.grid[1] * cfg.dx, None)
+    ref = pic.photon_advance(before["pos"], before["dir"], dt, box)
+    d = np.abs(after["pos"][:, :2] - ref[:, :2])
+    d = np.minimum(d, np.array(box[:2]) - d)          # periodic distance
+    assert d.max() < 1e-4
+    assert np.array_equal(after["eps"], before["eps"])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_loop_with_emission_keeps_gauss_law(sr, dim):
+    """Steps of the whole loop (emission step, current, field step) from a
+    standing-wave start: div E - rho stays what it was, to FP32 rounding."""
+    if dim == 2:
+        cfg = synth.config("c2", grid=(64, 48, 1), n_particles=30000)
+    else:
+        cfg = synth.config("c3", grid=(32, 24, 16), slab=None, n_particles=30000)
+    n_p = cfg.n_particles
+    st = synth.gen_particles(cfg, n=n_p)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k] * 500.0).astype(np.float32)
+    st["w"] = np.full(n_p, 0.05, np.float32)
+    parts = sr.Particles.from_numpy(st, dim=dim)
+    n = cfg.grid
+    dx = (cfg.dx,) * 3
+    shape = (n[2], n[1], n[0])
+    grid = sr.grid_struct(dim, n=n, dx=dx)
+    E, B = synth.standing_wave_grid(cfg, 0.0)
+    fields = sr.Fields(E, B)
+    photons = sr.PhotonBuffer(n_p, cfg.photons_per_particle, dim=dim)
+    ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n_p))
+    table = sr.Table()
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, kin_cut=cfg.kin_cut)
+    cells = int(np.prod(shape))
+    J = [torch.zeros(cells, device="cuda", dtype=torch.float32) for _ in range(3)]
+    rho = torch.zeros(cells, device="cuda", dtype=torch.float32)
+    status = torch.zeros(1, device="cuda", dtype=torch.int32)
+
+    def gauss():
+        rho.zero_()
+        sr.deposit_rho(parts, grid, -1.0, rho)
+        torch.cuda.synchronize()
+        Eh = [_host(t, shape) for t in fields.e]
+        return pic.div_E(Eh, dx) - _host(rho, shape)
+
+    g0 = gauss()
+    _say(f"pic loop {dim}D")
+    photons_total = 0
+    for s in range(4):
+        x_old = [t.clone() if t is not None else None for t in parts.x]
+        sr.gather_push_emit(parts, fields, grid, cfg.dt, 3, s, prm, table, photons, ledger, 0)
+        for t in J:
+            t.zero_()
+        sr.deposit_current(parts, x_old, grid, cfg.dt, -1.0, J, status)
+        sr.field_step(fields, grid, cfg.dt, J)
+        sr.photon_advance(photons, n_p, grid, cfg.dt)
+        torch.cuda.synchronize()
+        photons_total += photons.gather(n_p)["count"]
+    assert int(status.item()) == 0
+    assert photons_total > 100
+    g1 = gauss()
+    scale = max(np.max(np.abs(g0)), np.max(np.abs(_host(rho, shape))))
+    assert np.max(np.abs(g1 - g0)) <= 1e-4 * scale
