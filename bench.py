@@ -299,11 +299,110 @@ def run(args):
     }
     if check is not None:
         out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, check, seed, args)
-    if not args.no_samplers:
+    if not args.no_samplers or not args.no_pic:
         del parts, alt, photons, fields, sort_work
         torch.cuda.empty_cache()
+    if not args.no_samplers:
         out["samplers"] = samplers_leg(args)
+        torch.cuda.empty_cache()
+    if not args.no_pic:
+        out["pic_loop"] = pic_leg(args)
     return out
+
+
+def pic_leg(args):
+    """The emission step inside a closed PIC loop, on the wakefield-shaped
+    workload (512x128x64 cells of lambda/32, a 0.01 n_c plasma at 2 electrons
+    per cell and 1 keV, a linearly polarised a0 = 50 pulse along x).  Per step:
+    the tile sort (every 10 steps), a copy of the positions, the emission step
+    (gather, push, photons, recoil), the Esirkepov current, the Yee field step,
+    photon advance and the ledger reduction, each bracketed by HIP events on
+    the one stream they run on."""
+    import torch
+
+    from paper_1409_5574_amd import api
+    from paper_1409_5574_amd import _lib as L
+
+    cfg = synth.config("c6")
+    n = cfg.n_particles
+    grid = api.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    cells = int(np.prod(cfg.grid))
+    table = api.Table()
+    st = synth.gen_particles(cfg)
+    st["w"][:] = np.float32(synth.plasma_weight(cfg, synth.C6_DENSITY))
+    parts = api.Particles.from_numpy(st, dim=3)
+    del st
+    alt = parts.empty_like()
+    E, B = synth.laser_pulse_grid(cfg)
+    fields = api.Fields(E, B)
+    del E, B
+    J = [torch.zeros(cells, device="cuda", dtype=torch.float32) for _ in range(3)]
+    x_old = [torch.empty(n, device="cuda", dtype=torch.float32) for _ in range(3)]
+    status = torch.zeros(1, device="cuda", dtype=torch.int32)
+    photons = api.PhotonBuffer(n, cfg.photons_per_particle, dim=3)
+    n_chunks = api.n_chunks_uniform(n)
+    warm, steps = 3, args.pic_steps
+    ledger = api.LedgerBuf(warm + steps, n_chunks)
+    tile = (16, 4, 4)
+    sw = api.sort_work(grid, tile, n)
+    prm = api.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, kin_cut=cfg.kin_cut)
+    stream = torch.cuda.current_stream()
+    names = ("sort", "copy_x", "emission", "current", "field", "photons", "ledger")
+    times = {k: [] for k in names}
+    pending = []
+
+    def timed(name, fn, on):
+        if not on:
+            fn()
+            return
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        pending.append((name, a, b))
+
+    t0 = t1 = None
+    for i in range(warm + steps):
+        on = i >= warm
+        if i == warm:
+            t0 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+        if i % 10 == 0:
+            timed("sort", lambda: api.sort_particles(parts, alt, grid, tile, sw), on)
+            parts, alt = alt, parts
+        timed("copy_x", lambda: [d.copy_(s) for d, s in zip(x_old, parts.x)], on)
+        timed("emission", lambda: api.gather_push_emit(parts, fields, grid, cfg.dt, 0xC6, i, prm,
+                                                       table, photons, ledger, None), on)
+        timed("current", lambda: ([t.zero_() for t in J],
+                                  api.deposit_current(parts, x_old, grid, cfg.dt, -1.0, J, status)), on)
+        timed("field", lambda: api.field_step(fields, grid, cfg.dt, J), on)
+        timed("photons", lambda: api.photon_advance(photons, n, grid, cfg.dt), on)
+        timed("ledger", lambda: api.ledger_reduce(ledger, n_chunks, i), on)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    for name, a, b in pending:
+        times[name].append(a.elapsed_time(b))
+    total_ms = t0.elapsed_time(t1) / steps
+    rows = ledger.rows.cpu().numpy()[warm:]
+    per = {k: (float(np.sum(v)) / steps if v else 0.0) for k, v in times.items()}
+    field_bytes = 120.0 * cells        # B half: 36 B, E: 48 B, B half: 36 B per cell
+    f_ms = per["field"]
+    return {"workload": f"{cfg.name}: {cfg.grid[0]}x{cfg.grid[1]}x{cfg.grid[2]} Yee grid of lambda/32, "
+                        f"{n} electrons (2 per cell, {synth.C6_DENSITY} n_c, 1 keV), a0={cfg.a0:g} "
+                        f"pulse along x, K={cfg.n_samples}, kinematic cut, {steps} timed steps "
+                        f"after {warm}",
+            "ms_per_step": total_ms,
+            "particle_steps_per_s": n / (total_ms * 1e-3),
+            "breakdown_ms_per_step": per,
+            "field_step": {"ms": f_ms, "algorithmic_bytes": field_bytes,
+                           "GB_per_s": field_bytes / (f_ms * 1e-3) / 1e9 if f_ms > 0 else None,
+                           "frac_of_8TBps": field_bytes / (f_ms * 1e-3) / 8e12 if f_ms > 0 else None},
+            "photons_per_step": float(rows[:, L.SR_LED_PHOTONS].mean()),
+            "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
+            "status_bits": int(status.item()) | int(ledger.read_status()),
+            "timing": "HIP events on the stream around each part; sort amortised over its "
+                      "every-10-steps calls"}
 
 
 def samplers_leg(args):
@@ -479,6 +578,9 @@ def main():
                     help="skip the plain-vs-surrogate sampler comparison on the 3D K=8 workload")
     ap.add_argument("--sampler-steps", type=int, default=12)
     ap.add_argument("--mlp-steps", type=int, default=30000)
+    ap.add_argument("--no-pic", action="store_true",
+                    help="skip the closed PIC loop on the wakefield-shaped workload")
+    ap.add_argument("--pic-steps", type=int, default=20)
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
     args = ap.parse_args()

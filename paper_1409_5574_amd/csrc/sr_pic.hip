@@ -178,6 +178,140 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 //   2D  W_x = Dx (S0y + Dy/2),  W_y = Dy (S0x + Dx/2),
 //       Jz = q w v_z (S0x S0y + Dx S0y/2 + S0x Dy/2 + Dx Dy/3) / dV on the nodes.
 // Zero contributions are skipped.  A move of a cell or more sets *status.
+//
+// Sorted particles put the lanes of a block on the same few cells, where
+// global float atomics serialise.  So the block first finds the box of nodes
+// its particles touch; if that box fits in LDS (kDepCells cells, three
+// components) the block accumulates there (LDS atomics) and adds the box's
+// non-zero entries to the grid at the end; otherwise every lane adds to the
+// grid directly.
+constexpr int kDepCells = 3072;
+
+struct Stencil {
+    int I[3];              // old cell of the particle on each axis
+    float S0[3][4], D[3][4];
+    float cx, cy, cz;      // -q w (dx_a/dt)/dV (3D), and q w v_z / dV for 2D Jz in cz
+    bool live;             // active, finite move below one cell
+};
+
+template <int DIM>
+__device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const float *const xo[3],
+                                                const PicGrid &G, float qv, float inv_dt,
+                                                uint32_t u, bool active, bool &bad) {
+    Stencil s;
+    s.live = active;
+    bad = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.I[a] = 0;
+        for (int c = 0; c < 4; ++c) { s.S0[a][c] = (a >= DIM && c == 1) ? 1.0f : 0.0f; s.D[a][c] = 0.0f; }
+    }
+    s.cx = s.cy = s.cz = 0.0f;
+    if (!active) return s;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float x0 = ld(xo[a], u), x1 = ld(P.x[a], u);
+        float d = x1 - x0;                       // the shorter way round the box
+        if (d > 0.5f * G.L[a]) d -= G.L[a];
+        else if (d < -0.5f * G.L[a]) d += G.L[a];
+        float f0;
+        locate(x0, G.inv_hi[a], G.inv_lo[a], G.n[a], s.I[a], f0);
+        const float du = d * G.inv_hi[a];
+        ok = ok && fabsf(du) < 1.0f;
+        const float r1 = f0 + du;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            s.S0[a][c] = cic_w(f0, c);
+            s.D[a][c] = cic_w(r1, c) - s.S0[a][c];
+        }
+    }
+    if (!ok) {
+        bad = true;
+        s.live = false;
+        return s;
+    }
+    const float qw = qv * ld(P.w, u);
+    const float inv_dV = 1.0f / G.dV;
+    s.cx = -qw * inv_dt * inv_dV / (G.inv_hi[0] + G.inv_lo[0]);
+    s.cy = -qw * inv_dt * inv_dV / (G.inv_hi[1] + G.inv_lo[1]);
+    if (DIM == 3) {
+        s.cz = -qw * inv_dt * inv_dV / (G.inv_hi[2] + G.inv_lo[2]);
+    } else {
+        // v_z of the move from the momentum the position push used
+        const float pz = ld(P.p[2], u), px = ld(P.p[0], u), py = ld(P.p[1], u);
+        s.cz = qw * pz * __builtin_amdgcn_rsqf(1.0f + px * px + py * py + pz * pz) * inv_dV;
+    }
+    return s;
+}
+
+// Every non-zero contribution of one particle, as add(component, node offsets
+// ci, cj, ck in 0..3 relative to I - 1, value).
+template <int DIM, typename ADD>
+__device__ __forceinline__ void esirkepov(const Stencil &s, ADD &&add) {
+    if (DIM == 3) {
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 4; ++j) {
+                const float f = s.S0[1][j] * s.S0[2][k] + 0.5f * s.D[1][j] * s.S0[2][k] +
+                                0.5f * s.S0[1][j] * s.D[2][k] + s.D[1][j] * s.D[2][k] * (1.0f / 3.0f);
+                if (f == 0.0f) continue;
+                float acc = 0.0f;
+                for (int i = 0; i < 3; ++i) {
+                    acc += s.cx * s.D[0][i] * f;
+                    if (acc != 0.0f) add(0, i, j, k, acc);
+                }
+            }
+        for (int k = 0; k < 4; ++k)
+            for (int i = 0; i < 4; ++i) {
+                const float f = s.S0[0][i] * s.S0[2][k] + 0.5f * s.D[0][i] * s.S0[2][k] +
+                                0.5f * s.S0[0][i] * s.D[2][k] + s.D[0][i] * s.D[2][k] * (1.0f / 3.0f);
+                if (f == 0.0f) continue;
+                float acc = 0.0f;
+                for (int j = 0; j < 3; ++j) {
+                    acc += s.cy * s.D[1][j] * f;
+                    if (acc != 0.0f) add(1, i, j, k, acc);
+                }
+            }
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i) {
+                const float f = s.S0[0][i] * s.S0[1][j] + 0.5f * s.D[0][i] * s.S0[1][j] +
+                                0.5f * s.S0[0][i] * s.D[1][j] + s.D[0][i] * s.D[1][j] * (1.0f / 3.0f);
+                if (f == 0.0f) continue;
+                float acc = 0.0f;
+                for (int k = 0; k < 3; ++k) {
+                    acc += s.cz * s.D[2][k] * f;
+                    if (acc != 0.0f) add(2, i, j, k, acc);
+                }
+            }
+    } else {
+        for (int j = 0; j < 4; ++j) {
+            const float f = s.S0[1][j] + 0.5f * s.D[1][j];
+            if (f == 0.0f) continue;
+            float acc = 0.0f;
+            for (int i = 0; i < 3; ++i) {
+                acc += s.cx * s.D[0][i] * f;
+                if (acc != 0.0f) add(0, i, j, 0, acc);
+            }
+        }
+        for (int i = 0; i < 4; ++i) {
+            const float f = s.S0[0][i] + 0.5f * s.D[0][i];
+            if (f == 0.0f) continue;
+            float acc = 0.0f;
+            for (int j = 0; j < 3; ++j) {
+                acc += s.cy * s.D[1][j] * f;
+                if (acc != 0.0f) add(1, i, j, 0, acc);
+            }
+        }
+        if (s.cz != 0.0f)
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i) {
+                    const float wt = s.S0[0][i] * s.S0[1][j] + 0.5f * s.D[0][i] * s.S0[1][j] +
+                                     0.5f * s.S0[0][i] * s.D[1][j] + s.D[0][i] * s.D[1][j] * (1.0f / 3.0f);
+                    if (wt != 0.0f) add(2, i, j, 0, s.cz * wt);
+                }
+    }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const float *xo0,
                                                       const float *xo1, const float *xo2,
@@ -185,115 +319,83 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
                                                       float *__restrict__ jx, float *__restrict__ jy,
                                                       float *__restrict__ jz,
                                                       uint32_t *__restrict__ status) {
+    __shared__ float box[3 * kDepCells];
+    __shared__ int red[2][3][kWaves];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
-    const uint32_t u = (uint32_t)p;
-    const float *xo[3] = {xo0, xo1, xo2};
-    int I[3] = {0, 0, 0};
-    float S0[3][4], D[3][4];
-    bool ok = true;
+    const bool active = p < P.n;
+    const uint32_t u = active ? (uint32_t)p : 0u;
+    const float *const xo[3] = {xo0, xo1, xo2};
+    bool bad;
+    const Stencil s = make_stencil<DIM>(P, xo, G, qv, inv_dt, u, active, bad);
+    if (bad) atomicOr(status, SR_W_CFL);
+    float *const J[3] = {jx, jy, jz};
+
+    // the block's box of nodes: [min I - 1, max I + 2] on each axis (unwrapped)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (a >= DIM) {
-            for (int c = 0; c < 4; ++c) { S0[a][c] = c == 1 ? 1.0f : 0.0f; D[a][c] = 0.0f; }
-            continue;
+        int lo = s.live ? s.I[a] : 0x3fffffff, hi = s.live ? s.I[a] : -0x3fffffff;
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
         }
-        const float x0 = ld(xo[a], u), x1 = ld(P.x[a], u);
-        float d = x1 - x0;                       // the shorter way round the box
-        if (d > 0.5f * G.L[a]) d -= G.L[a];
-        else if (d < -0.5f * G.L[a]) d += G.L[a];
-        float f0;
-        locate(x0, G.inv_hi[a], G.inv_lo[a], G.n[a], I[a], f0);
-        const float du = d * G.inv_hi[a];
-        ok = ok && fabsf(du) < 1.0f;
-        const float r1 = f0 + du;
+        if (lane == 0) { red[0][a][wave] = lo; red[1][a][wave] = hi; }
+    }
+    __syncthreads();
+    int org[3], ext[3];
+    bool any = true;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            S0[a][c] = cic_w(f0, c);
-            D[a][c] = cic_w(r1, c) - S0[a][c];
+    for (int a = 0; a < 3; ++a) {
+        int lo = red[0][a][0], hi = red[1][a][0];
+        for (int w = 1; w < kWaves; ++w) { lo = min(lo, red[0][a][w]); hi = max(hi, red[1][a][w]); }
+        any = any && hi >= lo;      // no live particle: lo > hi
+        if (a < DIM) {
+            org[a] = lo - 1;
+            ext[a] = hi - lo + 4;
+        } else {
+            org[a] = 0;
+            ext[a] = 1;
         }
     }
-    if (!ok) {
-        atomicOr(status, SR_W_CFL);
+    // size test in 64 bits (extents can be as large as the grid)
+    const bool use_box = any && (int64_t)ext[0] * ext[1] * ext[2] <= kDepCells;
+    const int cells = use_box ? ext[0] * ext[1] * ext[2] : 0;
+    if (!use_box) {
+        if (!s.live) return;
+        esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
+            const int i = node(s.I[0], ci, G.n[0]), j = node(s.I[1], cj, G.n[1]);
+            const int k = DIM == 3 ? node(s.I[2], ck, G.n[2]) : 0;
+            unsafeAtomicAdd(&J[comp][cell(i, j, k, G)], v);
+        });
         return;
     }
-    const float qw = qv * ld(P.w, u);
-    const float inv_dV = 1.0f / G.dV;
-    int ix[4], iy[4], iz[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        ix[c] = node(I[0], c, G.n[0]);
-        iy[c] = node(I[1], c, G.n[1]);
-        iz[c] = DIM == 3 ? node(I[2], c, G.n[2]) : 0;
+    for (int e = threadIdx.x; e < 3 * cells; e += blockDim.x) box[e] = 0.0f;
+    __syncthreads();
+    if (s.live) {
+        const int b0 = s.I[0] - 1 - org[0], b1 = s.I[1] - 1 - org[1];
+        const int b2 = DIM == 3 ? s.I[2] - 1 - org[2] : 0;
+        esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
+            const int l = (b0 + ci) + ext[0] * ((b1 + cj) + ext[1] * (b2 + ck));
+            atomicAdd(&box[comp * cells + l], v);
+        });
     }
-    // dx/dt = L/(n dt); with the split inverse, dx = 1/inv (exact enough for the scale)
-    const float cx = -qw * inv_dt * inv_dV / (G.inv_hi[0] + G.inv_lo[0]);
-    const float cy = -qw * inv_dt * inv_dV / (G.inv_hi[1] + G.inv_lo[1]);
-    if (DIM == 3) {
-        const float cz = -qw * inv_dt * inv_dV / (G.inv_hi[2] + G.inv_lo[2]);
-        for (int k = 0; k < 4; ++k)
-            for (int j = 0; j < 4; ++j) {
-                const float f = S0[1][j] * S0[2][k] + 0.5f * D[1][j] * S0[2][k] +
-                                0.5f * S0[1][j] * D[2][k] + D[1][j] * D[2][k] * (1.0f / 3.0f);
-                if (f == 0.0f) continue;
-                float acc = 0.0f;
-                for (int i = 0; i < 3; ++i) {
-                    acc += cx * D[0][i] * f;
-                    if (acc != 0.0f) unsafeAtomicAdd(&jx[cell(ix[i], iy[j], iz[k], G)], acc);
-                }
-            }
-        for (int k = 0; k < 4; ++k)
-            for (int i = 0; i < 4; ++i) {
-                const float f = S0[0][i] * S0[2][k] + 0.5f * D[0][i] * S0[2][k] +
-                                0.5f * S0[0][i] * D[2][k] + D[0][i] * D[2][k] * (1.0f / 3.0f);
-                if (f == 0.0f) continue;
-                float acc = 0.0f;
-                for (int j = 0; j < 3; ++j) {
-                    acc += cy * D[1][j] * f;
-                    if (acc != 0.0f) unsafeAtomicAdd(&jy[cell(ix[i], iy[j], iz[k], G)], acc);
-                }
-            }
-        for (int j = 0; j < 4; ++j)
-            for (int i = 0; i < 4; ++i) {
-                const float f = S0[0][i] * S0[1][j] + 0.5f * D[0][i] * S0[1][j] +
-                                0.5f * S0[0][i] * D[1][j] + D[0][i] * D[1][j] * (1.0f / 3.0f);
-                if (f == 0.0f) continue;
-                float acc = 0.0f;
-                for (int k = 0; k < 3; ++k) {
-                    acc += cz * D[2][k] * f;
-                    if (acc != 0.0f) unsafeAtomicAdd(&jz[cell(ix[i], iy[j], iz[k], G)], acc);
-                }
-            }
-    } else {
-        for (int j = 0; j < 4; ++j) {
-            const float f = S0[1][j] + 0.5f * D[1][j];
-            if (f == 0.0f) continue;
-            float acc = 0.0f;
-            for (int i = 0; i < 3; ++i) {
-                acc += cx * D[0][i] * f;
-                if (acc != 0.0f) unsafeAtomicAdd(&jx[cell(ix[i], iy[j], 0, G)], acc);
-            }
-        }
-        for (int i = 0; i < 4; ++i) {
-            const float f = S0[0][i] + 0.5f * D[0][i];
-            if (f == 0.0f) continue;
-            float acc = 0.0f;
-            for (int j = 0; j < 3; ++j) {
-                acc += cy * D[1][j] * f;
-                if (acc != 0.0f) unsafeAtomicAdd(&jy[cell(ix[i], iy[j], 0, G)], acc);
-            }
-        }
-        // v_z of the move from the momentum the position push used
-        const float pz = ld(P.p[2], u), px = ld(P.p[0], u), py = ld(P.p[1], u);
-        const float vz = pz * __builtin_amdgcn_rsqf(1.0f + px * px + py * py + pz * pz);
-        const float cz = qw * vz * inv_dV;
-        for (int j = 0; j < 4; ++j)
-            for (int i = 0; i < 4; ++i) {
-                const float wt = S0[0][i] * S0[1][j] + 0.5f * D[0][i] * S0[1][j] +
-                                 0.5f * S0[0][i] * D[1][j] + D[0][i] * D[1][j] * (1.0f / 3.0f);
-                if (wt != 0.0f && cz != 0.0f)
-                    unsafeAtomicAdd(&jz[cell(ix[i], iy[j], 0, G)], cz * wt);
-            }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * cells; e += blockDim.x) {
+        const float v = box[e];
+        if (v == 0.0f) continue;
+        const int comp = e / cells, l = e - comp * cells;
+        const int li = l % ext[0], r = l / ext[0];
+        const int lj = r % ext[1], lk = r / ext[1];
+        // the box's nodes wrapped onto the periodic grid (org may be -1 or the
+        // box may run past n - 1)
+        int i = org[0] + li, j = org[1] + lj, k = org[2] + lk;
+        i = i < 0 ? i + G.n[0] : (i >= G.n[0] ? i - G.n[0] : i);
+        j = j < 0 ? j + G.n[1] : (j >= G.n[1] ? j - G.n[1] : j);
+        k = DIM == 3 ? (k < 0 ? k + G.n[2] : (k >= G.n[2] ? k - G.n[2] : k)) : 0;
+        i = min(max(i, 0), G.n[0] - 1);
+        j = min(max(j, 0), G.n[1] - 1);
+        k = min(max(k, 0), G.n[2] - 1);
+        unsafeAtomicAdd(&J[comp][cell(i, j, k, G)], v);
     }
 }
 

@@ -83,7 +83,20 @@ CONFIGS = {
     "c5": Config("c5_3d_768x768x384_64M", 3, 1 << 26, 20, 0.5 * _DX, 1, HBAR_N_08UM,
                  grid=(768, 768, 384), dx=_DX, a0=800.0, kin_cut=True, photons_per_particle=1,
                  momentum="loguniform_gamma", gamma_range=(1.0, 3e4), seed=0x5EED0005),
+    # wakefield-shaped PIC-loop workload: 512x128x64 cells of lambda/32, an
+    # underdense plasma (0.01 n_c, 2 electrons per cell, 1 keV) and a linearly
+    # polarised laser pulse (a0 = 50) launched along x; the fields evolve
+    # self-consistently (Yee solve, Esirkepov current)
+    "c6": Config("c6_pic_wakefield_512x128x64", 3, 2 * 512 * 128 * 64, 40, 0.5 * TWO_PI / 32.0, 1,
+                 HBAR_N_08UM, grid=(512, 128, 64), dx=TWO_PI / 32.0, a0=50.0, kin_cut=True,
+                 photons_per_particle=1, seed=0x5EED0006),
 }
+
+# c6 plasma and pulse
+C6_DENSITY = 0.01          # electron density in units of the critical density
+C6_PULSE_X0 = 4.0 * TWO_PI  # pulse centre along x
+C6_PULSE_SIGMA = 1.5 * TWO_PI   # rms length of the envelope
+C6_PULSE_WAIST = 1.0 * TWO_PI   # transverse rms size
 
 
 def config(name: str, **overrides) -> Config:
@@ -169,3 +182,39 @@ def standing_wave_grid(cfg: Config, t: float, dtype=np.float32):
         arr[...] = prof[None, None, :]
         (E_out if c < 3 else B_out).append(arr.reshape(-1))
     return E_out, B_out
+
+
+def plasma_weight(cfg: Config, density: float) -> float:
+    """Weight of each of cfg.n_particles electrons spread uniformly over the box
+    so that they make `density` (in units of n_r, (c/omega_r)^-3)."""
+    vol = 1.0
+    for L in cfg.box[:cfg.dim]:
+        vol *= L
+    return density * vol / cfg.n_particles
+
+
+def laser_pulse_grid(cfg: Config, t: float = 0.0, dtype=np.float32):
+    """A linearly polarised (E along y) pulse moving along +x in vacuum form,
+    sampled at the Yee points: Ey = a0 cos(x - t) g, Bz = Ey (at its own
+    points), g a Gaussian envelope centred at C6_PULSE_X0 + t (rms length
+    C6_PULSE_SIGMA) times a transverse Gaussian of rms size C6_PULSE_WAIST about
+    the box axis.  Returns (E, B) as flat arrays, x fastest."""
+    nx, ny, nz = cfg.grid
+    L = cfg.box
+    out = []
+    for c in range(6):
+        off = _YEE[c]
+        x = (np.arange(nx, dtype=np.float64) + off[0]) * cfg.dx
+        y = (np.arange(ny, dtype=np.float64) + off[1]) * cfg.dx - 0.5 * L[1]
+        z = (np.arange(nz, dtype=np.float64) + off[2]) * cfg.dx - 0.5 * L[2]
+        if c not in (1, 5):
+            out.append(np.zeros(nx * ny * nz, dtype=dtype))
+            continue
+        phase = x - t
+        gx = cfg.a0 * np.cos(phase) * np.exp(-0.5 * ((x - C6_PULSE_X0 - t) / C6_PULSE_SIGMA) ** 2)
+        gy = np.exp(-0.5 * (y / C6_PULSE_WAIST) ** 2)
+        gz = np.exp(-0.5 * (z / C6_PULSE_WAIST) ** 2)
+        arr = gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+        out.append(arr.astype(dtype).reshape(-1))
+    return out[:3], out[3:]
+
