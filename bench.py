@@ -343,7 +343,7 @@ def pic_leg(args):
     n_chunks = api.n_chunks_uniform(n)
     warm, steps = 3, args.pic_steps
     ledger = api.LedgerBuf(warm + steps, n_chunks)
-    tile = (16, 4, 4)
+    tile = tuple(int(v) for v in args.pic_tile.split(","))
     sw = api.sort_work(grid, tile, n)
     prm = api.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, kin_cut=cfg.kin_cut)
     stream = torch.cuda.current_stream()
@@ -391,7 +391,7 @@ def pic_leg(args):
     return {"workload": f"{cfg.name}: {cfg.grid[0]}x{cfg.grid[1]}x{cfg.grid[2]} Yee grid of lambda/32, "
                         f"{n} electrons (2 per cell, {synth.C6_DENSITY} n_c, 1 keV), a0={cfg.a0:g} "
                         f"pulse along x, K={cfg.n_samples}, kinematic cut, {steps} timed steps "
-                        f"after {warm}",
+                        f"after {warm}, sort tile {tile} every 10 steps",
             "ms_per_step": total_ms,
             "particle_steps_per_s": n / (total_ms * 1e-3),
             "breakdown_ms_per_step": per,
@@ -581,6 +581,7 @@ def main():
     ap.add_argument("--no-pic", action="store_true",
                     help="skip the closed PIC loop on the wakefield-shaped workload")
     ap.add_argument("--pic-steps", type=int, default=20)
+    ap.add_argument("--pic-tile", default="8,4,2", help="sort tile of the PIC leg, in cells")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
     args = ap.parse_args()
