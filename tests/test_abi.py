@@ -201,3 +201,48 @@ def test_validity_and_floor_reject_bad_arguments_on_host(lib):
         rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), 0.1, 1, 0, C.byref(bad), d,
                                      C.byref(ch), C.byref(ph), C.byref(led), None)
         assert rc == L.SR_E_INVAL
+
+
+def test_pic_calls_reject_bad_arguments_on_host(lib):
+    from paper_1409_5574_amd import _lib as L
+    d = C.c_void_p(16)
+    g = L.Grid()
+    g.dim = 3
+    for a in range(3):
+        g.n[a] = 8
+        g.dx[a] = 0.1
+    e = L.P3(d, d, d)
+    b = L.P3(d, d, d)
+    none = L.P3(None, None, None)
+    # the Courant condition dt^2 sum 1/dx^2 < 1: 0.1/sqrt(3) = 0.0577
+    assert lib.sr_field_step(e, b, none, C.byref(g), 0.06, None) == L.SR_E_INVAL
+    assert lib.sr_field_step(e, b, none, C.byref(g), 0.0, None) == L.SR_E_INVAL
+    assert lib.sr_field_step(L.P3(d, None, d), b, none, C.byref(g), 0.05, None) == L.SR_E_INVAL
+    # a current with a missing component
+    assert lib.sr_field_step(e, b, L.P3(d, None, d), C.byref(g), 0.05, None) == L.SR_E_INVAL
+    g0 = L.Grid()
+    g0.dim = 0
+    assert lib.sr_field_step(e, b, none, C.byref(g0), 0.05, None) == L.SR_E_INVAL
+    p = L.Particles32()
+    p.n = 10
+    for a in range(3):
+        p.x[a] = d
+        p.p[a] = d
+    p.w = d
+    p.id = d
+    j = L.P3(d, d, d)
+    xo = L.P3(d, d, d)
+    # status, current and old positions are required; dt > 0
+    assert lib.sr_deposit_current(C.byref(p), xo, C.byref(g), 0.05, -1.0, j, None, None) == L.SR_E_INVAL
+    assert lib.sr_deposit_current(C.byref(p), xo, C.byref(g), 0.05, -1.0, L.P3(d, None, d), d,
+                                  None) == L.SR_E_INVAL
+    assert lib.sr_deposit_current(C.byref(p), L.P3(d, None, d), C.byref(g), 0.05, -1.0, j, d,
+                                  None) == L.SR_E_INVAL
+    assert lib.sr_deposit_current(C.byref(p), xo, C.byref(g), 0.0, -1.0, j, d, None) == L.SR_E_INVAL
+    assert lib.sr_deposit_rho(C.byref(p), C.byref(g0), -1.0, d, None) == L.SR_E_INVAL
+    assert lib.sr_deposit_rho(C.byref(p), C.byref(g), -1.0, None, None) == L.SR_E_INVAL
+    ph = L.PhotonBuf()
+    ch = L.Chunking(1, None)
+    assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), 0.05, None) == L.SR_E_INVAL
+    ph.seg_count = d
+    assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), -1.0, None) == L.SR_E_INVAL
