@@ -268,10 +268,21 @@ struct StepSmem<KMAX, SR_SAMPLER_QUANTUM> {
 template <typename S>
 __device__ __forceinline__ LedgerSmem &ledger_smem(S &s) { return s.led; }
 
+// Occupancy target: the FP32 3D kernels with 4 to 8 trials sit a couple of
+// VGPRs above the 96 that five waves per SIMD allow; asking for five costs no
+// spills and gives them a fifth wave.
+template <typename R, int DIM, int KMAX, int SAMPLER>
+constexpr int step_waves_per_eu() {
+    return (sizeof(R) == 4 && DIM == 3 && KMAX >= 4 && KMAX <= 8 && SAMPLER != SR_SAMPLER_MLP) ? 5
+                                                                                              : 1;
+}
+
 // FLOOR: the grid-frequency floor is on (a.e_grid > 0); a template flag, so the
 // kernels without it carry none of its code.
 template <typename R, int DIM, int KMAX, int SAMPLER, bool FLOOR>
-__global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(step_waves_per_eu<R, DIM, KMAX, SAMPLER>())))
+void push_emit_kernel(const StepArgs<R> a) {
     __shared__ StepSmem<KMAX, SAMPLER> sm;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -307,13 +318,28 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
     const int K = a.K;
     const float invK = 1.0f / (float)K;
 
-    double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0;
-    float acc_w = 0.0f;
+    // Ledger sums of the lane.  With the proposal and table samplers each
+    // round's sums are added to the lane's own LDS ledger slot at the end of
+    // the round, so no FP64 sum stays in registers across rounds (it would
+    // hold VGPRs through the next round's gather and cost a wave per SIMD);
+    // the learned sampler shares that LDS with the network and keeps them in
+    // registers.
+    constexpr bool kLdsAcc = SAMPLER != SR_SAMPLER_MLP;
+    double tot_emit = 0.0, tot_ll = 0.0, tot_de = 0.0, tot_clamp = 0.0, tot_drop = 0.0;
+    float tot_w = 0.0f;
+    if constexpr (kLdsAcc) {
+        LedgerSmem &rs = ledger_smem(sm);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rs.d[q][tid] = 0.0;
+        rs.f[0][tid] = 0.0f;
+    }
     float chi_max = 0.0f;
     uint32_t flags = 0;
     uint32_t run_base = 0;
 
     for (uint32_t base = s0; base < e0; base += kChunk) {
+        double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0;
+        float acc_w = 0.0f;
         const uint32_t i = base + lane;
         const bool active = i < e0;
         float eps_unit = 0.0f, wi_f = 0.0f, chif = 0.0f, Hf = 0.0f;
@@ -578,6 +604,22 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
             acc_w += wi_f;
         }
         run_base += wave_tot;
+        if constexpr (kLdsAcc) {
+            LedgerSmem &rs = ledger_smem(sm);
+            rs.d[0][tid] += acc_emit;
+            rs.d[1][tid] += acc_ll;
+            rs.d[2][tid] += acc_de;
+            rs.d[3][tid] += acc_clamp;
+            rs.d[4][tid] += acc_drop;
+            rs.f[0][tid] += acc_w;
+        } else {
+            tot_emit += acc_emit;
+            tot_ll += acc_ll;
+            tot_de += acc_de;
+            tot_clamp += acc_clamp;
+            tot_drop += acc_drop;
+            tot_w += acc_w;
+        }
     }
 
     if (have && lane == 0) cold_args<R>().seg_count[c] = run_base;
@@ -598,12 +640,14 @@ __global__ __launch_bounds__(kBlock) void push_emit_kernel(const StepArgs<R> a) 
     // are rare: reduced only when some lane has them.
     if constexpr (SAMPLER == SR_SAMPLER_MLP) __syncthreads();   // LDS shared with the sampler
     LedgerSmem &rs = ledger_smem(sm);
-    rs.d[0][tid] = acc_emit;
-    rs.d[1][tid] = acc_ll;
-    rs.d[2][tid] = acc_de;
-    rs.d[3][tid] = acc_clamp;
-    rs.d[4][tid] = acc_drop;
-    rs.f[0][tid] = acc_w;
+    if constexpr (!kLdsAcc) {
+        rs.d[0][tid] = tot_emit;
+        rs.d[1][tid] = tot_ll;
+        rs.d[2][tid] = tot_de;
+        rs.d[3][tid] = tot_clamp;
+        rs.d[4][tid] = tot_drop;
+        rs.f[0][tid] = tot_w;
+    }
     rs.f[1][tid] = chi_max;
     if (lane == 0) {
         rs.cnt[wave] = run_base;
