@@ -145,7 +145,8 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"libsr.so not found at {path}: build it with __graft_entry__.build()")
+        raise RuntimeError(f"libsr.so not found at {path}: build it with "
+                           "python -m paper_1409_5574_amd.build")
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
