@@ -298,13 +298,17 @@ def _host_grid(profiles, cfg):
             for p in profiles]
 
 
-@pytest.mark.parametrize("name,sample", [("c2", 20000), ("c3", 6000), ("c5", 4000)])
-def test_full_size_one_step_sampled(sr, table, oracle, name, sample):
+@pytest.mark.parametrize("name,sample,sampler", [("c2", 20000, 0), ("c3", 6000, 0), ("c5", 4000, 0),
+                                                 ("c3", 6000, 3)])
+def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler):
+    """One step at the workload's full size in the benchmark's launch
+    configuration, checked against the oracle on sampled particles (sampler 3:
+    the quantum-corrected kernel on the same workload)."""
     cfg = synth.config(name)
     n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
     seed, step, t = 99, 7, 0.3
     st = synth.gen_particles(cfg)
-    _say(f"full size {name}: n={n} grid={cfg.grid}")
+    _say(f"full size {name}: n={n} grid={cfg.grid} sampler={sampler}")
     parts = sr.Particles.from_numpy(st, dim=dim)
     grid = sr.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
     # the launch configuration the benchmark times: tile-sorted particles, uniform chunks
@@ -316,7 +320,8 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample):
     fields, profiles = _device_fields(sr, cfg, t)
     photons = sr.PhotonBuffer(n, cfg.photons_per_particle, dim=dim)
     ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
-    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, recoil=cfg.recoil, kin_cut=cfg.kin_cut)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler=sampler, recoil=cfg.recoil,
+                           kin_cut=cfg.kin_cut)
     sr.gather_push_emit(sorted_parts, fields, grid, cfg.dt, seed, step, prm, table, photons,
                         ledger, 0)
     torch.cuda.synchronize()
@@ -336,16 +341,21 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample):
     host = _host_grid(profiles, cfg)
     fo = oracle.Field(dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=host[:3], B=host[3:])
     ph_o, led_o, det = oracle.step(orc, fo, cfg.dt, seed, step, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
-                                   n_samples=K, recoil=cfg.recoil, kin_cut=cfg.kin_cut, detail=True)
+                                   n_samples=K, recoil=cfg.recoil, kin_cut=cfg.kin_cut,
+                                   sampler=oracle.SAMPLER_QUANTUM if sampler == 3 else 0,
+                                   detail=True)
     del host, fo
     gi = np.argsort(g["id"])[ids]
     gs = {k: (v[gi] if v is not None else None) for k, v in g.items()}
     keep = np.isin(ph_all["parent"], ids)
     ph_g = {k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in ph_all.items()}
-    xcut = None
-    if cfg.kin_cut:
+    xcut = dn_tol = None
+    if sampler == 3:
+        dn_tol = parity.quantum_dn_tol(np.repeat(det["chi"], K), det["xs"])
+    elif cfg.kin_cut:
         xcut = np.abs(1.5 * np.repeat(det["chi"], K) * det["xs"] - 1.0) <= 1e-5
-    rep = parity.compare_step(gs, orc, old, ph_g, ph_o, det, K, box=cfg.box, xcut_band=xcut)
+    rep = parity.compare_step(gs, orc, old, ph_g, ph_o, det, K, box=cfg.box, xcut_band=xcut,
+                              dn_tol=dn_tol)
     e_gpu = float((ph_g["w"].astype(np.float64) * ph_g["eps"]).sum())
     assert e_gpu == pytest.approx(led_o[0], rel=parity.LEDGER_TOL) or rep["decision_flips"]
     print(f"{name}: sampled {sample}, photons {rep['photons_oracle']}, flips "

@@ -267,3 +267,65 @@ def test_loop_with_emission_keeps_gauss_law(sr, dim):
     g1 = gauss()
     scale = max(np.max(np.abs(g0)), np.max(np.abs(_host(rho, shape))))
     assert np.max(np.abs(g1 - g0)) <= 1e-4 * scale
+
+
+def test_pic_loop_full_size_keeps_gauss_law(sr):
+    """The PIC loop at the benchmark's size and launch configuration (the
+    wakefield-shaped workload: 512x128x64 cells, 8.4M electrons, sort tile
+    8x4x2): three steps keep div E - rho to FP32 rounding everywhere."""
+    cfg = synth.config("c6")
+    n = cfg.n_particles
+    dx = (cfg.dx,) * 3
+    shape = (cfg.grid[2], cfg.grid[1], cfg.grid[0])
+    cells = int(np.prod(cfg.grid))
+    grid = sr.grid_struct(3, n=cfg.grid, dx=dx)
+    st = synth.gen_particles(cfg)
+    st["w"][:] = np.float32(synth.plasma_weight(cfg, synth.C6_DENSITY))
+    parts = sr.Particles.from_numpy(st, dim=3)
+    del st
+    alt = parts.empty_like()
+    E, B = synth.laser_pulse_grid(cfg)
+    fields = sr.Fields(E, B)
+    max_e = float(max(np.abs(a).max() for a in E))
+    del E, B
+    tile = (8, 4, 2)
+    sw = sr.sort_work(grid, tile, n)
+    sr.sort_particles(parts, alt, grid, tile, sw)
+    parts, alt = alt, parts
+    del alt, sw
+    J = [torch.zeros(cells, device="cuda", dtype=torch.float32) for _ in range(3)]
+    x_old = [torch.empty(n, device="cuda", dtype=torch.float32) for _ in range(3)]
+    rho = torch.zeros(cells, device="cuda", dtype=torch.float32)
+    status = torch.zeros(1, device="cuda", dtype=torch.int32)
+    photons = sr.PhotonBuffer(n, cfg.photons_per_particle, dim=3)
+    ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
+    table = sr.Table()
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, kin_cut=cfg.kin_cut)
+
+    def gauss():
+        rho.zero_()
+        sr.deposit_rho(parts, grid, -1.0, rho)
+        torch.cuda.synchronize()
+        Eh = [_host(t, shape) for t in fields.e]
+        return pic.div_E(Eh, dx) - _host(rho, shape), float(np.abs(_host(rho, shape)).max())
+
+    g0, rho_max = gauss()
+    steps = 3
+    _say("pic loop full size")
+    for s in range(steps):
+        for d, src in zip(x_old, parts.x):
+            d.copy_(src)
+        sr.gather_push_emit(parts, fields, grid, cfg.dt, 0xC6, s, prm, table, photons, ledger, 0)
+        for t in J:
+            t.zero_()
+        sr.deposit_current(parts, x_old, grid, cfg.dt, -1.0, J, status)
+        sr.field_step(fields, grid, cfg.dt, J)
+        sr.photon_advance(photons, n, grid, cfg.dt)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert ledger.read_status() & ~2 == 0
+    g1, _ = gauss()
+    # FP32 rounding of E (three differences of neighbours per node and step)
+    # and of the current, against a charge density of about 1e-2
+    tol = steps * 6 * float(np.spacing(np.float32(max_e))) / cfg.dx + 1e-5 * rho_max
+    assert np.max(np.abs(g1 - g0)) <= tol, (np.max(np.abs(g1 - g0)), tol)
