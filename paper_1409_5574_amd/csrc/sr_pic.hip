@@ -142,6 +142,15 @@ __device__ __forceinline__ int node(int i, int c, int n) {
     return min(max(v, 0), n - 1);
 }
 
+// i in [-2n, 3n) onto [0, n)
+__device__ __forceinline__ int wrap2(int i, int n) {
+    if (i < 0) i += n;
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    if (i >= n) i -= n;
+    return i;
+}
+
 // CIC weight of a particle at relative coordinate r (cells from node i) on the
 // node i - 1 + c.
 __device__ __forceinline__ float cic_w(float r, int c) {
@@ -181,16 +190,31 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 //
 // Sorted particles put the lanes of a block on the same few cells, where
 // global float atomics serialise.  So the block first finds the box of nodes
-// its particles touch; if that box fits in LDS (kDepCells cells, three
-// components) the block accumulates there (LDS atomics) and adds the box's
-// non-zero entries to the grid at the end; otherwise every lane adds to the
-// grid directly.
+// its particles touch, with cells taken relative to the block's first particle
+// across the periodic boundary (a block whose sorted particles run from the end
+// of one tile row into the next keeps a compact box).  If that box fits in LDS
+// (kDepCells cells, three components) the block accumulates there and adds the
+// box's non-zero entries to the grid at the end; otherwise every lane adds to
+// the grid directly.
+//
+// The box holds fixed-point integers, not floats: on gfx950 an LDS float
+// atomic add takes about 40 times as long as an integer one, and it was the
+// bulk of the deposit's time.  Each contribution v is rounded to an integer
+// multiple of 2^(e-22), where 2^e bounds every contribution of the block: on
+// each axis |v| <= |c_a| |du_a| (the partial sums of D over a hat shape are
+// bounded by the move du in cells, the transverse factor lies in [0, 1]), and
+// |v| <= |c_z| for the 2D Jz.  A node takes at most one contribution per
+// particle and component, so a sum stays below 256 * 2^22 = 2^30, and the
+// integer adds are exact and independent of order.  The rounding error per
+// contribution is at most 2^-22 of the block's largest bound.
 constexpr int kDepCells = 3072;
+constexpr int kDepFracBits = 22;
 
 struct Stencil {
     int I[3];              // old cell of the particle on each axis
     float S0[3][4], D[3][4];
     float cx, cy, cz;      // -q w (dx_a/dt)/dV (3D), and q w v_z / dV for 2D Jz in cz
+    float bound;           // bound on |contribution| (with a margin for rounding)
     bool live;             // active, finite move below one cell
 };
 
@@ -207,8 +231,10 @@ __device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const
         for (int c = 0; c < 4; ++c) { s.S0[a][c] = (a >= DIM && c == 1) ? 1.0f : 0.0f; s.D[a][c] = 0.0f; }
     }
     s.cx = s.cy = s.cz = 0.0f;
+    s.bound = 0.0f;
     if (!active) return s;
     bool ok = true;
+    float du_abs[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const float x0 = ld(xo[a], u), x1 = ld(P.x[a], u);
@@ -219,6 +245,7 @@ __device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const
         locate(x0, G.inv_hi[a], G.inv_lo[a], G.n[a], s.I[a], f0);
         const float du = d * G.inv_hi[a];
         ok = ok && fabsf(du) < 1.0f;
+        du_abs[a] = fabsf(du);
         const float r1 = f0 + du;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -242,6 +269,12 @@ __device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const
         const float pz = ld(P.p[2], u), px = ld(P.p[0], u), py = ld(P.p[1], u);
         s.cz = qw * pz * __builtin_amdgcn_rsqf(1.0f + px * px + py * py + pz * pz) * inv_dV;
     }
+    // |v| <= |c_a| |du_a| per axis (2D Jz: |c_z|); the margin covers the
+    // rounding of the weights and of their partial sums
+    constexpr float kPad = 1.0f / (1 << 20);
+    float b = fmaxf(fabsf(s.cx) * (du_abs[0] + kPad), fabsf(s.cy) * (du_abs[1] + kPad));
+    b = fmaxf(b, DIM == 3 ? fabsf(s.cz) * (du_abs[2] + kPad) : fabsf(s.cz));
+    s.bound = b * 1.001f;
     return s;
 }
 
@@ -319,8 +352,10 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
                                                       float *__restrict__ jx, float *__restrict__ jy,
                                                       float *__restrict__ jz,
                                                       uint32_t *__restrict__ status) {
-    __shared__ float box[3 * kDepCells];
+    __shared__ int box[3 * kDepCells];
     __shared__ int red[2][3][kWaves];
+    __shared__ float bmax[kWaves];
+    __shared__ int ref[3];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < P.n;
     const uint32_t u = active ? (uint32_t)p : 0u;
@@ -330,16 +365,38 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
     if (bad) atomicOr(status, SR_W_CFL);
     float *const J[3] = {jx, jy, jz};
 
-    // the block's box of nodes: [min I - 1, max I + 2] on each axis (unwrapped)
+    // the cells relative to the block's first particle (always active: the
+    // grid has ceil(n / 256) blocks), unwrapped across the periodic boundary
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) ref[a] = s.I[a];
+    __syncthreads();
+    int U[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int d = s.I[a] - ref[a];
+        if (a < DIM) {
+            if (2 * d > G.n[a]) d -= G.n[a];
+            else if (2 * d < -G.n[a]) d += G.n[a];
+        }
+        U[a] = ref[a] + d;
+    }
+
+    // the block's box of nodes [min U - 1, max U + 2] and its largest bound
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int lo = s.live ? s.I[a] : 0x3fffffff, hi = s.live ? s.I[a] : -0x3fffffff;
+        int lo = s.live ? U[a] : 0x3fffffff, hi = s.live ? U[a] : -0x3fffffff;
         for (int o = 32; o > 0; o >>= 1) {
             lo = min(lo, __shfl_xor(lo, o, 64));
             hi = max(hi, __shfl_xor(hi, o, 64));
         }
         if (lane == 0) { red[0][a][wave] = lo; red[1][a][wave] = hi; }
+    }
+    {
+        // a non-finite bound (a NaN or infinite weight) counts as infinite
+        float b = s.live ? (s.bound <= 3.0e38f ? s.bound : __builtin_inff()) : 0.0f;
+        for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o, 64));
+        if (lane == 0) bmax[wave] = b;
     }
     __syncthreads();
     int org[3], ext[3];
@@ -357,9 +414,16 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
             ext[a] = 1;
         }
     }
-    // size test in 64 bits (extents can be as large as the grid)
-    const bool use_box = any && (int64_t)ext[0] * ext[1] * ext[2] <= kDepCells;
-    const int cells = use_box ? ext[0] * ext[1] * ext[2] : 0;
+    float bnd = bmax[0];
+    for (int w = 1; w < kWaves; ++w) bnd = fmaxf(bnd, bmax[w]);
+    // bnd < 2^e: contributions in units of 2^(e - kDepFracBits).  A
+    // non-finite bound, or one so small that 2^(kDepFracBits - e) would not
+    // be a finite float, takes the float path; so does a box that does not
+    // fit (size test in 64 bits: extents can be as large as the grid).
+    int e = 0;
+    if (bnd > 0.0f) (void)frexpf(bnd, &e);
+    const bool use_box = any && (int64_t)ext[0] * ext[1] * ext[2] <= kDepCells &&
+                         bnd <= 3.0e38f && e >= -100;
     if (!use_box) {
         if (!s.live) return;
         esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
@@ -369,33 +433,36 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
         });
         return;
     }
-    for (int e = threadIdx.x; e < 3 * cells; e += blockDim.x) box[e] = 0.0f;
+    if (!(bnd > 0.0f)) return;      // every contribution is zero
+    const float to_fix = ldexpf(1.0f, kDepFracBits - e), from_fix = ldexpf(1.0f, e - kDepFracBits);
+    const int cells = ext[0] * ext[1] * ext[2];
+    for (int q = threadIdx.x; q < 3 * cells; q += blockDim.x) box[q] = 0;
     __syncthreads();
     if (s.live) {
-        const int b0 = s.I[0] - 1 - org[0], b1 = s.I[1] - 1 - org[1];
-        const int b2 = DIM == 3 ? s.I[2] - 1 - org[2] : 0;
+        const int b0 = U[0] - 1 - org[0], b1 = U[1] - 1 - org[1];
+        const int b2 = DIM == 3 ? U[2] - 1 - org[2] : 0;
         esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
             const int l = (b0 + ci) + ext[0] * ((b1 + cj) + ext[1] * (b2 + ck));
-            atomicAdd(&box[comp * cells + l], v);
+            atomicAdd(&box[comp * cells + l], __float2int_rn(v * to_fix));
         });
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 3 * cells; e += blockDim.x) {
-        const float v = box[e];
-        if (v == 0.0f) continue;
-        const int comp = e / cells, l = e - comp * cells;
+    for (int q = threadIdx.x; q < 3 * cells; q += blockDim.x) {
+        const int sum = box[q];
+        if (sum == 0) continue;
+        const int comp = q / cells, l = q - comp * cells;
         const int li = l % ext[0], r = l / ext[0];
         const int lj = r % ext[1], lk = r / ext[1];
-        // the box's nodes wrapped onto the periodic grid (org may be -1 or the
-        // box may run past n - 1)
+        // the box's nodes wrapped onto the periodic grid: they lie in
+        // [-n/2 - 1, 3n/2 + 1], so two wraps each way reach [0, n) for any n
         int i = org[0] + li, j = org[1] + lj, k = org[2] + lk;
-        i = i < 0 ? i + G.n[0] : (i >= G.n[0] ? i - G.n[0] : i);
-        j = j < 0 ? j + G.n[1] : (j >= G.n[1] ? j - G.n[1] : j);
-        k = DIM == 3 ? (k < 0 ? k + G.n[2] : (k >= G.n[2] ? k - G.n[2] : k)) : 0;
+        i = wrap2(i, G.n[0]);
+        j = wrap2(j, G.n[1]);
+        k = DIM == 3 ? wrap2(k, G.n[2]) : 0;
         i = min(max(i, 0), G.n[0] - 1);
         j = min(max(j, 0), G.n[1] - 1);
         k = min(max(k, 0), G.n[2] - 1);
-        unsafeAtomicAdd(&J[comp][cell(i, j, k, G)], v);
+        unsafeAtomicAdd(&J[comp][cell(i, j, k, G)], (float)sum * from_fix);
     }
 }
 

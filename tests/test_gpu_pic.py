@@ -118,15 +118,11 @@ def _parts(sr, dim, pos, p, w):
     return sr.Particles.from_numpy(st, dim=dim)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_current_matches_oracle_and_conserves_charge(sr, dim):
-    n, dx = _geom(dim)
+def _check_current(sr, dim, n, dx, p0, p1, mom, w, label):
+    """Deposit the moves p0 -> p1 on the GPU; compare J with the oracle and
+    check the discrete continuity equation on the GPU's own rho and J."""
     shape = (n[2], n[1], n[0])
-    rng = np.random.default_rng(20 + dim)
-    count = 20000
-    p0, p1 = _moves(dim, n, dx, count, rng)
-    w = rng.uniform(0.5, 2.0, count).astype(np.float32)
-    mom = rng.normal(0, 3.0, (count, 3)).astype(np.float32)
+    count = p0.shape[0]
     grid = sr.grid_struct(dim, n=n, dx=dx)
     parts = _parts(sr, dim, p1, mom, w)
     x_old = [_dev(p0[:, a]) for a in range(dim)] + [None] * (3 - dim)
@@ -134,7 +130,7 @@ def test_current_matches_oracle_and_conserves_charge(sr, dim):
     J = [torch.zeros(cells, device="cuda", dtype=torch.float32) for _ in range(3)]
     status = torch.zeros(1, device="cuda", dtype=torch.int32)
     q, dt = -1.0, 0.11
-    _say(f"deposit current {dim}D {count}")
+    _say(f"deposit current {label} {dim}D {count} grid {n}")
     sr.deposit_current(parts, x_old, grid, dt, q, J, status)
     r0 = torch.zeros(cells, device="cuda", dtype=torch.float32)
     r1 = torch.zeros(cells, device="cuda", dtype=torch.float32)
@@ -156,6 +152,65 @@ def test_current_matches_oracle_and_conserves_charge(sr, dim):
     # discrete continuity on the GPU's own charge and current
     resid = rg1 - rg0 + dt * pic.div_E(Jg, dx)
     assert np.max(np.abs(resid)) <= 2e-5 * np.max(np.abs(rg0))
+
+
+def _tile_order(p0, dim, n, dx, tile):
+    """Indices that sort the particles by tile of their old cell, tiles x
+    fastest (the layout the tile sort produces, which puts a block's particles
+    in a compact box)."""
+    key = np.zeros(p0.shape[0], np.int64)
+    mul = 1
+    for a in range(dim):
+        c = np.clip(np.floor(p0[:, a].astype(np.float64) / dx[a]).astype(np.int64), 0, n[a] - 1)
+        key += (c // tile[a]) * mul
+        mul *= -(-n[a] // tile[a])
+    return np.argsort(key, kind="stable")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_current_matches_oracle_and_conserves_charge(sr, dim):
+    # unsorted moves over the whole grid: blocks add to the grid directly
+    n, dx = _geom(dim)
+    rng = np.random.default_rng(20 + dim)
+    count = 20000
+    p0, p1 = _moves(dim, n, dx, count, rng)
+    w = rng.uniform(0.5, 2.0, count).astype(np.float32)
+    mom = rng.normal(0, 3.0, (count, 3)).astype(np.float32)
+    _check_current(sr, dim, n, dx, p0, p1, mom, w, "unsorted")
+
+
+@pytest.mark.parametrize("case", ["sorted", "mixed", "small_grid"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_current_box_path_matches_oracle(sr, dim, case):
+    """Tile-sorted moves, so that blocks accumulate in their LDS box (integer
+    sums in units set by the block's largest contribution bound):
+      sorted      uniform weights, moves up to 0.9 cell;
+      mixed       weights log-uniform over 1e-3 .. 1e3, 90% of the moves
+                  below 1e-3 cell and 10% up to 0.95 cell, so one block holds
+                  contributions six orders of magnitude apart;
+      small_grid  two cells along x (and three along y), where the box runs
+                  around the periodic grid more than once."""
+    rng = np.random.default_rng(40 + 3 * dim + len(case))
+    if case == "small_grid":
+        n, dx = ((2, 3, 1), (0.3, 0.25, 1.0)) if dim == 2 else ((2, 3, 16), (0.3, 0.25, 0.35))
+        count = 6000
+    else:
+        n, dx = _geom(dim)
+        count = 30000
+    if case == "mixed":
+        box = np.array([n[a] * dx[a] for a in range(dim)])
+        p0 = (rng.uniform(0, 1, (count, dim)) * box).astype(np.float32)
+        frac = np.where(rng.uniform(size=count) < 0.9, 1e-3, 0.95)[:, None]
+        d = rng.uniform(-1, 1, (count, dim)) * frac * np.array(dx[:dim])
+        p1 = np.mod(p0.astype(np.float64) + d, box).astype(np.float32)
+        p1 = np.where(p1 >= box.astype(np.float32), 0.0, p1).astype(np.float32)
+        w = np.exp(rng.uniform(np.log(1e-3), np.log(1e3), count)).astype(np.float32)
+    else:
+        p0, p1 = _moves(dim, n, dx, count, rng)
+        w = np.ones(count, np.float32)
+    mom = rng.normal(0, 3.0, (count, 3)).astype(np.float32)
+    o = _tile_order(p0, dim, n, dx, (4, 4, 2))
+    _check_current(sr, dim, n, dx, p0[o], p1[o], mom[o], w[o], case)
 
 
 def test_current_flags_long_moves(sr):
