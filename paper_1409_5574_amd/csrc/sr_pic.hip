@@ -180,8 +180,9 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 }
 
 // Esirkepov's current of the move x_old -> x (one lane per particle).  On each
-// axis the old shape S0 and the new shape S1 live on nodes i-1 .. i+2 of the
-// old cell i (moves below one cell); D = S1 - S0.  Per node of the stencil
+// axis the old shape S0 and the new shape S1 of a move below one cell lie on
+// three consecutive nodes among i-1 .. i+2 of the old cell i, and the loops
+// run over those three; D = S1 - S0.  Per node of the stencil
 //   3D  W_x = Dx (S0y S0z + Dy S0z/2 + S0y Dz/2 + Dy Dz/3)  (and cyclically),
 //   Jx(i+1/2) = Jx(i-1/2) - q w (dx/dt) W_x / dV, summed along x;
 //   2D  W_x = Dx (S0y + Dy/2),  W_y = Dy (S0x + Dx/2),
@@ -212,7 +213,8 @@ constexpr int kDepFracBits = 22;
 
 struct Stencil {
     int I[3];              // old cell of the particle on each axis
-    float S0[3][4], D[3][4];
+    int o[3];              // the move's three nodes on each axis: I - 1 + o .. I + 1 + o
+    float S0[3][3], D[3][3];   // old shape and its change on those nodes
     float cx, cy, cz;      // -q w (dx_a/dt)/dV (3D), and q w v_z / dV for 2D Jz in cz
     float bound;           // bound on |contribution| (with a margin for rounding)
     bool live;             // active, finite move below one cell
@@ -228,7 +230,8 @@ __device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         s.I[a] = 0;
-        for (int c = 0; c < 4; ++c) { s.S0[a][c] = (a >= DIM && c == 1) ? 1.0f : 0.0f; s.D[a][c] = 0.0f; }
+        s.o[a] = 1;
+        for (int c = 0; c < 3; ++c) { s.S0[a][c] = (a >= DIM && c == 0) ? 1.0f : 0.0f; s.D[a][c] = 0.0f; }
     }
     s.cx = s.cy = s.cz = 0.0f;
     s.bound = 0.0f;
@@ -247,10 +250,14 @@ __device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const
         ok = ok && fabsf(du) < 1.0f;
         du_abs[a] = fabsf(du);
         const float r1 = f0 + du;
+        // old shape on nodes i, i+1; new shape on i-1, i (r1 < 0) or on
+        // i, i+1 or i+1, i+2: three nodes from i - 1 + o
+        const int o = r1 < 0.0f ? 0 : 1;
+        s.o[a] = o;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            s.S0[a][c] = cic_w(f0, c);
-            s.D[a][c] = cic_w(r1, c) - s.S0[a][c];
+        for (int c = 0; c < 3; ++c) {
+            s.S0[a][c] = cic_w(f0, c + o);
+            s.D[a][c] = cic_w(r1, c + o) - s.S0[a][c];
         }
     }
     if (!ok) {
@@ -279,65 +286,67 @@ __device__ __forceinline__ Stencil make_stencil(const sr_particles_f32 &P, const
 }
 
 // Every non-zero contribution of one particle, as add(component, node offsets
-// ci, cj, ck in 0..3 relative to I - 1, value).
+// ci, cj, ck in 0..2 relative to I - 1 + o, value).  Along the component's own
+// axis only the first two partial sums are stored: the third is the sum of D,
+// which is zero.
 template <int DIM, typename ADD>
 __device__ __forceinline__ void esirkepov(const Stencil &s, ADD &&add) {
     if (DIM == 3) {
-        for (int k = 0; k < 4; ++k)
-            for (int j = 0; j < 4; ++j) {
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) {
                 const float f = s.S0[1][j] * s.S0[2][k] + 0.5f * s.D[1][j] * s.S0[2][k] +
                                 0.5f * s.S0[1][j] * s.D[2][k] + s.D[1][j] * s.D[2][k] * (1.0f / 3.0f);
                 if (f == 0.0f) continue;
                 float acc = 0.0f;
-                for (int i = 0; i < 3; ++i) {
+                for (int i = 0; i < 2; ++i) {
                     acc += s.cx * s.D[0][i] * f;
                     if (acc != 0.0f) add(0, i, j, k, acc);
                 }
             }
-        for (int k = 0; k < 4; ++k)
-            for (int i = 0; i < 4; ++i) {
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 3; ++i) {
                 const float f = s.S0[0][i] * s.S0[2][k] + 0.5f * s.D[0][i] * s.S0[2][k] +
                                 0.5f * s.S0[0][i] * s.D[2][k] + s.D[0][i] * s.D[2][k] * (1.0f / 3.0f);
                 if (f == 0.0f) continue;
                 float acc = 0.0f;
-                for (int j = 0; j < 3; ++j) {
+                for (int j = 0; j < 2; ++j) {
                     acc += s.cy * s.D[1][j] * f;
                     if (acc != 0.0f) add(1, i, j, k, acc);
                 }
             }
-        for (int j = 0; j < 4; ++j)
-            for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
                 const float f = s.S0[0][i] * s.S0[1][j] + 0.5f * s.D[0][i] * s.S0[1][j] +
                                 0.5f * s.S0[0][i] * s.D[1][j] + s.D[0][i] * s.D[1][j] * (1.0f / 3.0f);
                 if (f == 0.0f) continue;
                 float acc = 0.0f;
-                for (int k = 0; k < 3; ++k) {
+                for (int k = 0; k < 2; ++k) {
                     acc += s.cz * s.D[2][k] * f;
                     if (acc != 0.0f) add(2, i, j, k, acc);
                 }
             }
     } else {
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 3; ++j) {
             const float f = s.S0[1][j] + 0.5f * s.D[1][j];
             if (f == 0.0f) continue;
             float acc = 0.0f;
-            for (int i = 0; i < 3; ++i) {
+            for (int i = 0; i < 2; ++i) {
                 acc += s.cx * s.D[0][i] * f;
                 if (acc != 0.0f) add(0, i, j, 0, acc);
             }
         }
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 3; ++i) {
             const float f = s.S0[0][i] + 0.5f * s.D[0][i];
             if (f == 0.0f) continue;
             float acc = 0.0f;
-            for (int j = 0; j < 3; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 acc += s.cy * s.D[1][j] * f;
                 if (acc != 0.0f) add(1, i, j, 0, acc);
             }
         }
         if (s.cz != 0.0f)
-            for (int j = 0; j < 4; ++j)
-                for (int i = 0; i < 4; ++i) {
+            for (int j = 0; j < 3; ++j)
+                for (int i = 0; i < 3; ++i) {
                     const float wt = s.S0[0][i] * s.S0[1][j] + 0.5f * s.D[0][i] * s.S0[1][j] +
                                      0.5f * s.S0[0][i] * s.D[1][j] + s.D[0][i] * s.D[1][j] * (1.0f / 3.0f);
                     if (wt != 0.0f) add(2, i, j, 0, s.cz * wt);
@@ -427,8 +436,8 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
     if (!use_box) {
         if (!s.live) return;
         esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
-            const int i = node(s.I[0], ci, G.n[0]), j = node(s.I[1], cj, G.n[1]);
-            const int k = DIM == 3 ? node(s.I[2], ck, G.n[2]) : 0;
+            const int i = node(s.I[0], s.o[0] + ci, G.n[0]), j = node(s.I[1], s.o[1] + cj, G.n[1]);
+            const int k = DIM == 3 ? node(s.I[2], s.o[2] + ck, G.n[2]) : 0;
             unsafeAtomicAdd(&J[comp][cell(i, j, k, G)], v);
         });
         return;
@@ -439,8 +448,8 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
     for (int q = threadIdx.x; q < 3 * cells; q += blockDim.x) box[q] = 0;
     __syncthreads();
     if (s.live) {
-        const int b0 = U[0] - 1 - org[0], b1 = U[1] - 1 - org[1];
-        const int b2 = DIM == 3 ? U[2] - 1 - org[2] : 0;
+        const int b0 = U[0] - 1 + s.o[0] - org[0], b1 = U[1] - 1 + s.o[1] - org[1];
+        const int b2 = DIM == 3 ? U[2] - 1 + s.o[2] - org[2] : 0;
         esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
             const int l = (b0 + ci) + ext[0] * ((b1 + cj) + ext[1] * (b2 + ck));
             atomicAdd(&box[comp * cells + l], __float2int_rn(v * to_fix));
