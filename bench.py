@@ -581,7 +581,7 @@ def main():
     ap.add_argument("--no-pic", action="store_true",
                     help="skip the closed PIC loop on the wakefield-shaped workload")
     ap.add_argument("--pic-steps", type=int, default=20)
-    ap.add_argument("--pic-tile", default="8,4,2", help="sort tile of the PIC leg, in cells")
+    ap.add_argument("--pic-tile", default="4,4,4", help="sort tile of the PIC leg, in cells")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
     args = ap.parse_args()

@@ -195,8 +195,10 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 // across the periodic boundary (a block whose sorted particles run from the end
 // of one tile row into the next keeps a compact box).  If that box fits in LDS
 // (kDepCells cells, three components) the block accumulates there and adds the
-// box's non-zero entries to the grid at the end; otherwise every lane adds to
-// the grid directly.
+// box's non-zero entries to the grid at the end.  A larger box (particles that
+// have drifted far since the last sort) shrinks to a window of at most
+// kDepCells cells about the block's mean cell, and only the particles whose
+// nodes leave the window add to the grid directly.
 //
 // The box holds fixed-point integers, not floats: on gfx950 an LDS float
 // atomic add takes about 40 times as long as an integer one, and it was the
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 // particle and component, so a sum stays below 256 * 2^22 = 2^30, and the
 // integer adds are exact and independent of order.  The rounding error per
 // contribution is at most 2^-22 of the block's largest bound.
-constexpr int kDepCells = 3072;
+constexpr int kDepCells = 2048;
 constexpr int kDepFracBits = 22;
 
 struct Stencil {
@@ -423,31 +425,67 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
             ext[a] = 1;
         }
     }
+    if (!any) return;               // no live particle (the condition is block-wide)
     float bnd = bmax[0];
     for (int w = 1; w < kWaves; ++w) bnd = fmaxf(bnd, bmax[w]);
     // bnd < 2^e: contributions in units of 2^(e - kDepFracBits).  A
     // non-finite bound, or one so small that 2^(kDepFracBits - e) would not
-    // be a finite float, takes the float path; so does a box that does not
-    // fit (size test in 64 bits: extents can be as large as the grid).
+    // be a finite float, sends the whole block to the float path.
     int e = 0;
     if (bnd > 0.0f) (void)frexpf(bnd, &e);
-    const bool use_box = any && (int64_t)ext[0] * ext[1] * ext[2] <= kDepCells &&
-                         bnd <= 3.0e38f && e >= -100;
-    if (!use_box) {
-        if (!s.live) return;
+    const bool fixed = bnd <= 3.0e38f && e >= -100;
+    // A box too large for LDS shrinks, widest axis first, to a window about
+    // the block's mean cell (kept inside the box); the particles whose nodes
+    // leave the window add to the grid directly.  Volumes in 64 bits: extents
+    // can be as large as the grid.
+    int64_t vol = (int64_t)ext[0] * ext[1] * ext[2];
+    if (fixed && vol > kDepCells) {
+        __shared__ float msum[3][kWaves];
+        __shared__ int mcnt[kWaves];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float v = s.live ? (float)(U[a] - ref[a]) : 0.0f;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) msum[a][wave] = v;
+        }
+        int live = s.live ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) live += __shfl_xor(live, o, 64);
+        if (lane == 0) mcnt[wave] = live;
+        __syncthreads();
+        int cnt = 0;
+        for (int w = 0; w < kWaves; ++w) cnt += mcnt[w];
+        for (int it = 0; it < DIM && vol > kDepCells; ++it) {
+            int a = 0;
+            for (int b = 1; b < DIM; ++b)
+                if (ext[b] > ext[a]) a = b;
+            const int64_t other = vol / ext[a];
+            const int wdt = (int)min<int64_t>(ext[a], max<int64_t>(4, kDepCells / other));
+            float sum = 0.0f;
+            for (int w = 0; w < kWaves; ++w) sum += msum[a][w];
+            const int c = ref[a] + (int)floorf(sum / (float)max(cnt, 1) + 0.5f);
+            org[a] = min(max(c - wdt / 2, org[a]), org[a] + ext[a] - wdt);
+            ext[a] = wdt;
+            vol = other * wdt;
+        }
+    }
+    bool in_win = s.live && fixed;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int b = U[a] - 1 + s.o[a] - org[a];
+        in_win = in_win && b >= 0 && b + 2 <= ext[a] - 1;
+    }
+    if (s.live && !in_win)
         esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {
             const int i = node(s.I[0], s.o[0] + ci, G.n[0]), j = node(s.I[1], s.o[1] + cj, G.n[1]);
             const int k = DIM == 3 ? node(s.I[2], s.o[2] + ck, G.n[2]) : 0;
             unsafeAtomicAdd(&J[comp][cell(i, j, k, G)], v);
         });
-        return;
-    }
-    if (!(bnd > 0.0f)) return;      // every contribution is zero
+    if (!fixed || !(bnd > 0.0f)) return;      // block-wide; bnd = 0: every contribution is zero
     const float to_fix = ldexpf(1.0f, kDepFracBits - e), from_fix = ldexpf(1.0f, e - kDepFracBits);
     const int cells = ext[0] * ext[1] * ext[2];
     for (int q = threadIdx.x; q < 3 * cells; q += blockDim.x) box[q] = 0;
     __syncthreads();
-    if (s.live) {
+    if (in_win) {
         const int b0 = U[0] - 1 + s.o[0] - org[0], b1 = U[1] - 1 + s.o[1] - org[1];
         const int b2 = DIM == 3 ? U[2] - 1 + s.o[2] - org[2] : 0;
         esirkepov<DIM>(s, [&](int comp, int ci, int cj, int ck, float v) {

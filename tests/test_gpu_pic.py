@@ -343,7 +343,7 @@ def test_pic_loop_full_size_keeps_gauss_law(sr):
     fields = sr.Fields(E, B)
     max_e = float(max(np.abs(a).max() for a in E))
     del E, B
-    tile = (8, 4, 2)
+    tile = (4, 4, 4)
     sw = sr.sort_work(grid, tile, n)
     sr.sort_particles(parts, alt, grid, tile, sw)
     parts, alt = alt, parts
