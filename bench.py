@@ -165,8 +165,8 @@ def run(args):
         api.gather_push_emit(parts, fields, grid, cfg.dt, seed, i, prm, table, photons, ledger,
                              None, structs=s,
                              events=ev[timed_idx] if timed_idx is not None else None)
-        api.ledger_reduce(ledger, n_chunks, i, s[4])
-        api.spectrum_histogram(photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist, hwork)
+        api.step_epilogue(ledger, n_chunks, i, photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist, hwork,
+                          ls=s[4])
 
     for i in range(1, args.warmup + 1):
         one_step(i)
@@ -481,8 +481,8 @@ def samplers_leg(args):
             api.gather_push_emit(parts, fields, grid, cfg.dt, seed, i, prm, table, photons,
                                  ledger, None, structs=structs)
             ev[i][1].record(stream)
-            api.ledger_reduce(ledger, n_chunks, i, structs[4])
-            api.spectrum_histogram(photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist, hwork)
+            api.step_epilogue(ledger, n_chunks, i, photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist,
+                              hwork, ls=structs[4])
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         k_ms = np.array([a.elapsed_time(b) for a, b in ev])[1:]

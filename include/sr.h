@@ -22,8 +22,9 @@
  *    its ledger partials; sr_ledger_reduce latches them as bits in the
  *    caller's status word, read back by sr_status().
  *  - Hot calls (sr_gather_push_emit*, sr_ledger_reduce, sr_spectrum_histogram,
- *    sr_field_standing_wave, sr_sort_particles, sr_mlp_*) allocate nothing.
- *    Only sr_table_build allocates device memory (released by sr_table_free).
+ *    sr_step_epilogue, sr_field_standing_wave, sr_sort_particles, sr_mlp_*)
+ *    allocate nothing.  Only sr_table_build allocates device memory (released
+ *    by sr_table_free).
  *  - Calls that share device buffers must be ordered by the caller (same
  *    stream or events); the library keeps no global mutable state apart from
  *    the tables it hands out.
@@ -406,6 +407,19 @@ int sr_spectrum_histogram(const sr_photon_buf *photons, const sr_chunking *chunk
                           double eps_lo, double eps_hi, int32_t n_bins, double *hist,
                           double *work, void *stream);
 int64_t sr_hist_work(int32_t n_bins);
+
+/* The end of a step in two launches instead of four: exactly
+ *   sr_ledger_reduce(ledger, n_chunks, row) and
+ *   sr_spectrum_histogram(photons, chunks, n, eps_lo, eps_hi, n_bins, hist, work),
+ * with the same arguments, argument checks and results (the ledger row
+ * bit-identical; the histogram equal up to the order of its FP64 additions).
+ * The first launch runs the ledger's first level beside the histogram's
+ * accumulation, the second the ledger's last level beside the histogram's
+ * reduction. */
+int sr_step_epilogue(const sr_ledger *ledger, int64_t n_chunks, int64_t row,
+                     const sr_photon_buf *photons, const sr_chunking *chunks, int64_t n,
+                     double eps_lo, double eps_hi, int32_t n_bins, double *hist, double *work,
+                     void *stream);
 
 /* Angular distribution of the emitted energy over the front hemisphere around
  * `axis` (section "Comparison and benchmarking", Fig. 4: the front hemisphere

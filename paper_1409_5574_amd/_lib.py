@@ -116,6 +116,8 @@ SIGNATURES = {
     "sr_status": (C.c_int, [C.POINTER(Ledger), C.POINTER(C.c_uint32), _I32, _P]),
     "sr_spectrum_histogram": (C.c_int, [C.POINTER(PhotonBuf), C.POINTER(Chunking), _I64, _D, _D,
                                         _I32, _P, _P, _P]),
+    "sr_step_epilogue": (C.c_int, [C.POINTER(Ledger), _I64, _I64, C.POINTER(PhotonBuf),
+                                   C.POINTER(Chunking), _I64, _D, _D, _I32, _P, _P, _P]),
     "sr_hist_work": (C.c_int64, [_I32]),
     "sr_angular_histogram": (C.c_int, [C.POINTER(PhotonBuf), C.POINTER(Chunking), _I64,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), _I32, _I32,

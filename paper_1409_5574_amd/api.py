@@ -533,6 +533,21 @@ def spectrum_histogram(photons: PhotonBuffer, n: int, eps_lo: float, eps_hi: flo
                                         _ptr(hist), _ptr(work), _stream()), "sr_spectrum_histogram")
 
 
+def step_epilogue(ledger: "LedgerBuf", n_chunks: int, row: int, photons: PhotonBuffer, n: int,
+                  eps_lo: float, eps_hi: float, n_bins: int, hist: torch.Tensor,
+                  work: torch.Tensor, start: torch.Tensor | None = None, ls=None):
+    """ledger_reduce(ledger, n_chunks, row) and spectrum_histogram(photons, n,
+    ...) in two launches instead of four (same results)."""
+    ls = ledger.struct() if ls is None else ls
+    cs = L.Chunking()
+    cs.n_chunks = n_chunks_uniform(n) if start is None else start.numel() - 1
+    cs.start = None if start is None else start.data_ptr()
+    phs = photons.struct()
+    L.check(lib().sr_step_epilogue(C.byref(ls), int(n_chunks), int(row), C.byref(phs), C.byref(cs),
+                                   n, eps_lo, eps_hi, n_bins, _ptr(hist), _ptr(work), _stream()),
+            "sr_step_epilogue")
+
+
 def angular_histogram(photons: PhotonBuffer, n: int, axis, ref, n_theta: int, n_phi: int,
                       hist: torch.Tensor, work: torch.Tensor, start: torch.Tensor | None = None):
     """hist[n_theta*n_phi + 1] += energy-weighted (theta, phi) map of the stored

@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include "sr_common.hpp"
+#include "sr_hist.hpp"
 
 namespace sr {
 namespace {
@@ -184,67 +185,17 @@ __global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const u
 }
 
 // ------------------------------------------------------------ histogram
-constexpr int kHistBlocks = 512;
-constexpr int kMaxBins = 1024;
-
-// One lane per chunk: each lane walks the stored photons of its chunk and adds
-// them to the block's LDS histogram (FP64 LDS atomics); blocks stride over
-// groups of 256 chunks and flush their histogram to work[block].
+// The block work lives in sr_hist.hpp (the step epilogue uses it too).
 __global__ __launch_bounds__(256) void hist_kernel(sr_photon_buf ph, const int64_t *start,
                                                    int64_t n_chunks, int64_t n, float l2lo,
                                                    float scale, int nbins, double *work) {
     extern __shared__ double sh[];   // [2*nbins]
-    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) sh[b] = 0.0;
-    __syncthreads();
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s0 = start ? start[c] : c * (int64_t)kChunk;
-        const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kChunk, n);
-        const int64_t cap = (e0 - s0) * ph.per_particle;
-        const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
-        const int64_t base = s0 * ph.per_particle;
-        // eight photons at a time: their loads are in flight together
-        for (int64_t q0 = 0; q0 < cnt; q0 += 8) {
-            float eps[8], w[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                eps[j] = 0.0f;
-                w[j] = 0.0f;
-                if (q0 + j < cnt) {
-                    eps[j] = ph.eps[base + q0 + j];
-                    w[j] = ph.w[base + q0 + j];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (!(eps[j] > 0.0f)) continue;
-                const float u = (__log2f(eps[j]) - l2lo) * scale;
-                if (u < 0.0f || u >= (float)nbins) continue;
-                const int bin = (int)u;
-                atomicAdd(&sh[bin], (double)w[j] * (double)eps[j]);
-                atomicAdd(&sh[nbins + bin], (double)w[j]);
-            }
-        }
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x)
-        work[(int64_t)blockIdx.x * 2 * nbins + b] = sh[b];
+    hist_block(ph, start, n_chunks, n, l2lo, scale, nbins, work, blockIdx.x, gridDim.x, sh);
 }
 
-// hist[b] += sum over blocks of work[block][b]: one block per value, fixed order.
 __global__ __launch_bounds__(256) void hist_reduce(const double *work, int nblocks, int nvals,
                                                    double *hist) {
-    __shared__ double s[256];
-    const int b = blockIdx.x;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < nblocks; k += 256) acc += work[(int64_t)k * nvals + b];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) hist[b] += s[0];
+    hist_reduce_value(work, nblocks, nvals, hist, blockIdx.x);
 }
 
 // Energy-weighted angular map of the stored photons (the angular distribution
@@ -324,8 +275,7 @@ extern "C" int sr_angular_histogram(const sr_photon_buf *ph, const sr_chunking *
     if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
     if (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2]) return SR_E_INVAL;
     const int nvals = n_theta * n_phi + 1;
-    const int64_t groups = (n_chunks + 255) / 256;
-    const int nb = (int)(groups < kHistBlocks ? groups : kHistBlocks);
+    const int nb = hist_blocks(n_chunks);
     hipStream_t st = (hipStream_t)stream;
     angular_kernel<<<nb, 256, sizeof(double) * nvals, st>>>(
         *ph, chunks->start, n_chunks, n, make_float3((float)a[0], (float)a[1], (float)a[2]),
@@ -346,8 +296,9 @@ extern "C" int sr_field_standing_wave(float *e[3], float *b[3], const sr_grid *g
     if (nx < 1 || ny < 1 || nz < 1 || nx > (1 << 24) || !(grid->dx[0] > 0.0)) return SR_E_INVAL;
     const int64_t rows = ny * nz;
     const unsigned bx = (unsigned)((nx + 256 * kWaveXPerThread - 1) / (256 * kWaveXPerThread));
-    // about 1024 blocks, each writing a band of rows with its x profile reused
-    int64_t by = (1024 + bx - 1) / bx;
+    // about 256 blocks (one per CU), each writing a band of rows with its x
+    // profile reused: fewer blocks recompute the FP64 profile less often
+    int64_t by = (256 + bx - 1) / bx;
     if (by > rows) by = rows;
     if (by > 65535) by = 65535;
     const int rows_per_block = (int)((rows + by - 1) / by);
@@ -450,8 +401,7 @@ extern "C" int sr_spectrum_histogram(const sr_photon_buf *ph, const sr_chunking 
     if (!ph->eps || !ph->w) return SR_E_INVAL;
     const float l2lo = (float)log2(eps_lo);
     const float scale = (float)(n_bins / (log2(eps_hi) - log2(eps_lo)));
-    const int64_t groups = (n_chunks + 255) / 256;
-    const int nb = (int)(groups < kHistBlocks ? groups : kHistBlocks);
+    const int nb = hist_blocks(n_chunks);
     hipStream_t st = (hipStream_t)stream;
     hist_kernel<<<nb, 256, sizeof(double) * 2 * n_bins, st>>>(*ph, chunks->start, n_chunks, n,
                                                                l2lo, scale, n_bins, work);

@@ -1,0 +1,80 @@
+// sr_hist.hpp -- the block-level work of the photon energy spectrum (section
+// "Comparison and benchmarking": the energy-weighted spectrum of the emitted
+// photons), shared by the histogram entry point and the step epilogue.
+#pragma once
+
+#include "sr_common.hpp"
+
+namespace sr {
+
+constexpr int kHistBlocks = 512;   // most blocks of the accumulation pass
+constexpr int kMaxBins = 1024;
+
+// One lane per chunk: each lane walks the stored photons of its chunk and adds
+// w eps and w to bins of log2 eps in the block's LDS histogram sh[2 nbins]
+// (FP64 LDS atomics).  Block hb of nblocks strides over groups of 256 chunks
+// and writes its histogram to work[hb].  Call with the whole block.
+__device__ __forceinline__ void hist_block(const sr_photon_buf &ph, const int64_t *start,
+                                           int64_t n_chunks, int64_t n, float l2lo, float scale,
+                                           int nbins, double *work, int hb, int nblocks,
+                                           double *sh) {
+    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) sh[b] = 0.0;
+    __syncthreads();
+    for (int64_t c = (int64_t)hb * blockDim.x + threadIdx.x; c < n_chunks;
+         c += (int64_t)nblocks * blockDim.x) {
+        const int64_t s0 = start ? start[c] : c * (int64_t)kChunk;
+        const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kChunk, n);
+        const int64_t cap = (e0 - s0) * ph.per_particle;
+        const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
+        const int64_t base = s0 * ph.per_particle;
+        // eight photons at a time: their loads are in flight together
+        for (int64_t q0 = 0; q0 < cnt; q0 += 8) {
+            float eps[8], w[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                eps[j] = 0.0f;
+                w[j] = 0.0f;
+                if (q0 + j < cnt) {
+                    eps[j] = ph.eps[base + q0 + j];
+                    w[j] = ph.w[base + q0 + j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (!(eps[j] > 0.0f)) continue;
+                const float u = (__log2f(eps[j]) - l2lo) * scale;
+                if (u < 0.0f || u >= (float)nbins) continue;
+                const int bin = (int)u;
+                atomicAdd(&sh[bin], (double)w[j] * (double)eps[j]);
+                atomicAdd(&sh[nbins + bin], (double)w[j]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x)
+        work[(int64_t)hb * 2 * nbins + b] = sh[b];
+}
+
+// hist[b] += the sum over blocks of work[block][b], in a fixed order (a block
+// of 256 threads per value b).
+__device__ __forceinline__ void hist_reduce_value(const double *work, int nblocks, int nvals,
+                                                  double *hist, int b) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += 256) acc += work[(int64_t)k * nvals + b];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hist[b] += s[0];
+}
+
+// Blocks of the accumulation pass for n_chunks chunks.
+inline int hist_blocks(int64_t n_chunks) {
+    const int64_t groups = (n_chunks + 255) / 256;
+    return (int)(groups < kHistBlocks ? groups : kHistBlocks);
+}
+
+}  // namespace sr

@@ -11,12 +11,15 @@
 // photon buffer, the wave ballot + lane prefix (mbcnt) give every emitted
 // trial its slot inside the wave, and the four wave totals are combined in
 // LDS.  The FP64 ledger is reduced per block and written as one partial row per
-// chunk, then summed in a fixed order by ledger_reduce (deterministic).
+// chunk, then summed in a fixed order by ledger_reduce (deterministic).  The
+// step epilogue runs that reduction and the photon spectrum histogram together
+// in two launches.
 #include <math.h>
 #include <stddef.h>
 
 #include <hip/hip_ext.h>
 
+#include "sr_hist.hpp"
 #include "sr_mlp.hpp"
 
 namespace sr {
@@ -710,17 +713,14 @@ void push_emit_kernel(const StepArgs<R> a) {
 // flags column an OR).  Each thread keeps all columns of a strided set of rows
 // in registers, then the block combines them with wave shuffles and LDS: a
 // fixed order, so the ledger is bit-reproducible.  With status == nullptr the
-// block writes partial row out[b]; otherwise (a single block) it writes the
+// block writes the partial row out[0..kPartCols); otherwise it writes the
 // ledger row out[0..SR_LEDGER_COLS) and ORs the flags into *status (one atomic
-// per reduction).
-__global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__restrict__ in,
-                                                               int64_t n_rows, int64_t per_block,
-                                                               double *__restrict__ out,
-                                                               uint32_t *__restrict__ status) {
+// per reduction).  Call with the whole block.
+__device__ __forceinline__ void ledger_sum_block(const double *__restrict__ in, int64_t lo,
+                                                 int64_t hi, double *__restrict__ out,
+                                                 uint32_t *__restrict__ status) {
     __shared__ double s[kWaves][SR_LEDGER_COLS];
     __shared__ uint32_t sf[kWaves];
-    const int64_t lo = (int64_t)blockIdx.x * per_block;
-    const int64_t hi = min(lo + per_block, n_rows);
     double acc[SR_LEDGER_COLS];
     uint32_t fl = 0;
 #pragma unroll
@@ -753,18 +753,29 @@ __global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__r
         const int c = threadIdx.x;
         double v = s[0][c];
         for (int w = 1; w < kWaves; ++w) v = c == SR_LED_CHI_MAX ? fmax(v, s[w][c]) : v + s[w][c];
-        if (status) out[c] = v;
-        else out[(int64_t)blockIdx.x * kPartCols + c] = v;
+        out[c] = v;
     } else if (threadIdx.x == SR_LEDGER_COLS) {
         uint32_t f = 0;
         for (int w = 0; w < kWaves; ++w) f |= sf[w];
         if (status) {
             if (f) atomicOr(status, f);
         } else {
-            out[(int64_t)blockIdx.x * kPartCols + kPartFlags] = (double)f;
-            out[(int64_t)blockIdx.x * kPartCols + kPartFlags + 1] = 0.0;
+            out[kPartFlags] = (double)f;
+            out[kPartFlags + 1] = 0.0;
         }
     }
+}
+
+// Block b sums rows [b per, (b + 1) per) of the n_rows rows of `in`: into
+// partial row out[b] (status == nullptr), or, as the only block, into the
+// ledger row out.
+__global__ __launch_bounds__(kBlock) void ledger_reduce_kernel(const double *__restrict__ in,
+                                                               int64_t n_rows, int64_t per_block,
+                                                               double *__restrict__ out,
+                                                               uint32_t *__restrict__ status) {
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = min(lo + per_block, n_rows);
+    ledger_sum_block(in, lo, hi, status ? out : out + (int64_t)blockIdx.x * kPartCols, status);
 }
 
 // partial ledger rows written by one step: one per block of kWaves chunks
@@ -778,25 +789,82 @@ constexpr int64_t kReduceL1Blocks = 1024;
 constexpr int64_t kReduceSingle = 512;     // rows one block sums directly
 constexpr int64_t kReducePerBlock = 64;    // rows per block in the first of two levels
 
+// How one step's partial rows are summed: none (a zero row), by one block, or
+// in two levels (first-level rows in the partials buffer after the step's).
+struct LedgerPlan {
+    int mode;          // 0 zero row, 1 one block, 2 two levels
+    int64_t rows;      // partial rows of the step
+    int64_t per, nb;   // two levels: rows per first-level block, blocks
+    double *dst, *mid;
+};
+
+LedgerPlan ledger_plan(const sr_ledger *led, int64_t n_chunks, int64_t row) {
+    LedgerPlan p;
+    p.dst = led->rows + row * SR_LEDGER_COLS;
+    p.rows = partial_rows(n_chunks);   // the step writes one partial row per block
+    p.per = p.rows;
+    p.nb = 1;
+    p.mid = nullptr;
+    p.mode = p.rows == 0 ? 0 : (p.rows <= kReduceSingle ? 1 : 2);
+    if (p.mode == 2) {
+        p.per = (p.rows + kReduceL1Blocks - 1) / kReduceL1Blocks;
+        if (p.per < kReducePerBlock) p.per = kReducePerBlock;
+        p.nb = (p.rows + p.per - 1) / p.per;
+        p.mid = led->partials + p.rows * kPartCols;
+    }
+    return p;
+}
+
 int reduce_ledger(const sr_ledger *led, int64_t n_chunks, int64_t row, hipStream_t st) {
-    double *dst = led->rows + row * SR_LEDGER_COLS;
-    n_chunks = partial_rows(n_chunks);   // the step writes one partial row per block
-    if (n_chunks == 0) {
-        zero_row_kernel<<<1, 64, 0, st>>>(dst);
-    } else if (n_chunks <= kReduceSingle) {
-        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(led->partials, n_chunks, n_chunks, dst,
+    const LedgerPlan p = ledger_plan(led, n_chunks, row);
+    if (p.mode == 0) {
+        zero_row_kernel<<<1, 64, 0, st>>>(p.dst);
+    } else if (p.mode == 1) {
+        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(led->partials, p.rows, p.rows, p.dst,
                                                    led->status);
     } else {
-        int64_t per = (n_chunks + kReduceL1Blocks - 1) / kReduceL1Blocks;
-        if (per < kReducePerBlock) per = kReducePerBlock;
-        const int64_t nb = (n_chunks + per - 1) / per;
-        double *mid = led->partials + n_chunks * kPartCols;
-        ledger_reduce_kernel<<<(unsigned)nb, kBlock, 0, st>>>(led->partials, n_chunks, per, mid,
-                                                              nullptr);
-        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(mid, nb, nb, dst, led->status);
+        ledger_reduce_kernel<<<(unsigned)p.nb, kBlock, 0, st>>>(led->partials, p.rows, p.per,
+                                                                p.mid, nullptr);
+        ledger_reduce_kernel<<<1, kBlock, 0, st>>>(p.mid, p.nb, p.nb, p.dst, led->status);
     }
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
+}
+
+// Step epilogue, first launch: blocks [0, nb_led) do the ledger's only or
+// first level (n_rows == 0: block 0 writes a zero row), the other nb_hist
+// blocks accumulate the photon spectrum.
+__global__ __launch_bounds__(kBlock) void epilogue_first_kernel(
+    const double *__restrict__ in, int64_t n_rows, int64_t per, int nb_led,
+    double *__restrict__ out, uint32_t *__restrict__ status, sr_photon_buf ph,
+    const int64_t *start, int64_t n_chunks, int64_t n, float l2lo, float scale, int nbins,
+    double *__restrict__ work, int nb_hist) {
+    extern __shared__ double sh[];   // [2*nbins], histogram blocks
+    const int b = blockIdx.x;
+    if (b < nb_led) {
+        if (n_rows == 0) {
+            if (threadIdx.x < SR_LEDGER_COLS) out[threadIdx.x] = 0.0;
+            return;
+        }
+        const int64_t lo = (int64_t)b * per;
+        const int64_t hi = min(lo + per, n_rows);
+        ledger_sum_block(in, lo, hi, status ? out : out + (int64_t)b * kPartCols, status);
+        return;
+    }
+    hist_block(ph, start, n_chunks, n, l2lo, scale, nbins, work, b - nb_led, nb_hist, sh);
+}
+
+// Second launch: with led_blocks = 1, block 0 sums the ledger's first-level
+// rows into the ledger row; the other blocks each reduce one histogram value.
+__global__ __launch_bounds__(kBlock) void epilogue_second_kernel(
+    const double *__restrict__ mid, int64_t nb_mid, double *__restrict__ dst,
+    uint32_t *__restrict__ status, int led_blocks, const double *__restrict__ work, int nb_hist,
+    int nvals, double *__restrict__ hist) {
+    if ((int)blockIdx.x < led_blocks) {
+        ledger_sum_block(mid, 0, nb_mid, dst, status);
+        return;
+    }
+    hist_reduce_value(work, nb_hist, nvals, hist, (int)blockIdx.x - led_blocks);
 }
 
 void split_inv(double dx, float &hi, float &lo) {
@@ -1175,6 +1243,41 @@ extern "C" int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64
         row < 0 || row >= ledger->n_rows || ledger->partials_len < sr_ledger_partials(n_chunks))
         return SR_E_INVAL;
     return reduce_ledger(ledger, n_chunks, row, (hipStream_t)stream);
+}
+
+extern "C" int sr_step_epilogue(const sr_ledger *ledger, int64_t n_chunks, int64_t row,
+                                const sr_photon_buf *ph, const sr_chunking *chunks, int64_t n,
+                                double eps_lo, double eps_hi, int32_t n_bins, double *hist,
+                                double *work, void *stream) {
+    // the argument checks of sr_ledger_reduce and of sr_spectrum_histogram
+    if (!ledger || !ledger->rows || !ledger->partials || !ledger->status || n_chunks < 0 ||
+        n_chunks > 0x7FFFFFFF ||
+        row < 0 || row >= ledger->n_rows || ledger->partials_len < sr_ledger_partials(n_chunks))
+        return SR_E_INVAL;
+    if (!ph || !chunks || !hist || !work || n < 0 || n_bins < 1 || n_bins > kMaxBins ||
+        !(eps_lo > 0.0) || !(eps_hi > eps_lo) || !ph->seg_count)
+        return SR_E_INVAL;
+    const int64_t h_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
+    const bool do_hist = h_chunks > 0 && ph->per_particle > 0;
+    if (do_hist && (!ph->eps || !ph->w)) return SR_E_INVAL;
+    const LedgerPlan lp = ledger_plan(ledger, n_chunks, row);
+    const int nb_led = lp.mode == 2 ? (int)lp.nb : 1;
+    const int nb_hist = do_hist ? hist_blocks(h_chunks) : 0;
+    const float l2lo = (float)log2(eps_lo);
+    const float scale = (float)(n_bins / (log2(eps_hi) - log2(eps_lo)));
+    hipStream_t st = (hipStream_t)stream;
+    epilogue_first_kernel<<<nb_led + nb_hist, kBlock, sizeof(double) * 2 * n_bins, st>>>(
+        ledger->partials, lp.rows, lp.per, nb_led, lp.mode == 2 ? lp.mid : lp.dst,
+        lp.mode == 2 ? nullptr : ledger->status, *ph, chunks->start, h_chunks, n, l2lo, scale,
+        n_bins, work, nb_hist);
+    const int led_blocks = lp.mode == 2 ? 1 : 0;
+    const int second = led_blocks + (do_hist ? 2 * n_bins : 0);
+    if (second > 0)
+        epilogue_second_kernel<<<second, kBlock, 0, st>>>(lp.mid, lp.nb, lp.dst, ledger->status,
+                                                          led_blocks, work, nb_hist, 2 * n_bins,
+                                                          hist);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
 }
 
 extern "C" int sr_energy_ledger(const sr_ledger *led, int64_t row, double *out, void *stream) {

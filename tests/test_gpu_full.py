@@ -126,6 +126,31 @@ def test_spectrum_histogram_matches_host(sr, table):
     assert np.abs(h[nb:] - hw).sum() <= 1e-5 * hw.sum() + 2
 
 
+@pytest.mark.parametrize("n", [20000, 300000])
+def test_step_epilogue_equals_separate_calls(sr, table, n):
+    """The fused step epilogue against the ledger reduction and the histogram
+    called one after the other: the ledger row bit for bit, the histogram up to
+    the order of its FP64 additions.  20 000 particles sum the ledger in one
+    block, 300 000 in two levels."""
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    _say(f"step epilogue {n}")
+    parts, photons, ledger = _step_for_photons(sr, table, cfg, n, 2, 2000.0)
+    nb, lo, hi = 48, 1e-6, 1e4
+    nch = sr.n_chunks_uniform(n)
+    h_sep = torch.zeros(2 * nb, device="cuda", dtype=torch.float64)
+    h_fused = torch.zeros(2 * nb, device="cuda", dtype=torch.float64)
+    sr.ledger_reduce(ledger, nch, 0)
+    sr.spectrum_histogram(photons, n, lo, hi, nb, h_sep, sr.hist_work(nb))
+    sr.step_epilogue(ledger, nch, 1, photons, n, lo, hi, nb, h_fused, sr.hist_work(nb))
+    torch.cuda.synchronize()
+    rows = ledger.rows.cpu().numpy()
+    assert rows[0][1] > 0.0
+    assert np.array_equal(rows[0], rows[1])
+    a, b = h_fused.cpu().numpy(), h_sep.cpu().numpy()
+    assert b[:nb].sum() > 0.0
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=0.0)
+
+
 def _angular_reference(ph, axis, ref, nt, nph):
     """FP64 binning of the gathered photons by (theta, phi) about axis, with
     each photon's distance to the nearest bin edge (theta, phi in radians, the
