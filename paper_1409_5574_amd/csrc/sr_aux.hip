@@ -107,15 +107,53 @@ __device__ __forceinline__ WaveRun wave_run(uint32_t k, bool valid) {
     return r;
 }
 
-__global__ void sort_count(const float *x, const float *y, const float *z, int64_t n, SortGeom g,
-                           uint32_t *keys, uint32_t *counts) {
+// The block's smallest and largest valid key; false when no lane is valid.
+// Keys are below 2^31 (the tile count is checked on the host).
+__device__ __forceinline__ bool block_key_range(uint32_t k, bool valid, uint32_t &lo, uint32_t &hi) {
+    __shared__ int rlo[4], rhi[4];
+    int a = valid ? (int)k : 0x7fffffff, b = valid ? (int)k : -1;
+    for (int o = 32; o > 0; o >>= 1) {
+        a = min(a, __shfl_xor(a, o, 64));
+        b = max(b, __shfl_xor(b, o, 64));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { rlo[wave] = a; rhi[wave] = b; }
+    __syncthreads();
+    a = rlo[0];
+    b = rhi[0];
+    for (int w = 1; w < 4; ++w) { a = min(a, rlo[w]); b = max(b, rhi[w]); }
+    lo = (uint32_t)a;
+    hi = (uint32_t)b;
+    return b >= a;
+}
+
+// Keys a block groups in LDS: particles sorted some steps ago fall in a few
+// nearby tiles, so one global atomic per distinct key of the block replaces
+// one per run of equal keys in each wave.  A block whose keys span more
+// (particles far from sorted) takes the per-run atomics.
+constexpr uint32_t kSortSpan = 2048;
+
+__global__ __launch_bounds__(256) void sort_count(const float *x, const float *y, const float *z,
+                                                  int64_t n, SortGeom g, uint32_t *keys,
+                                                  uint32_t *counts) {
+    __shared__ uint32_t lc[kSortSpan];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
     const uint32_t k = valid ? tile_key(g, x[i], y[i], g.dim == 3 ? z[i] : 0.0f) : 0xFFFFFFFFu;
+    if (valid) keys[i] = k;
+    uint32_t lo, hi;
+    if (!block_key_range(k, valid, lo, hi)) return;   // no valid lane (block-wide)
     const WaveRun r = wave_run(k, valid);
-    if (!valid) return;
-    keys[i] = k;
-    if (r.head) atomicAdd(&counts[k], (uint32_t)r.len);
+    if (hi - lo < kSortSpan) {
+        for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) lc[e] = 0u;
+        __syncthreads();
+        if (valid && r.head) atomicAdd(&lc[k - lo], (uint32_t)r.len);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x)
+            if (lc[e]) atomicAdd(&counts[lo + e], lc[e]);
+    } else if (valid && r.head) {
+        atomicAdd(&counts[k], (uint32_t)r.len);
+    }
 }
 
 // exclusive scan in blocks of 1024 (256 threads x 4)
@@ -151,8 +189,14 @@ __global__ void scan_add(uint32_t *out, int64_t n, const uint32_t *block_prefix)
     if (i < n) out[i] += block_prefix[i / 1024];
 }
 
-__global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const uint32_t *keys,
-                             const uint32_t *offsets, uint32_t *cursor) {
+// Each particle goes to offsets[key] + its slot among the tile's particles.
+// Slots are handed out per block and key (LDS), then per block from the
+// tile's cursor (one global atomic per distinct key of the block); a block
+// whose keys span kSortSpan or more takes a global atomic per run.
+__global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst,
+                                                    const uint32_t *keys, const uint32_t *offsets,
+                                                    uint32_t *cursor) {
+    __shared__ uint32_t lc[kSortSpan];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < src.n;
     // the particle's values are read first: they do not depend on where it goes
@@ -168,11 +212,29 @@ __global__ void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst, const u
         id = src.id[i];
     }
     const uint32_t k = valid ? keys[i] : 0xFFFFFFFFu;
+    uint32_t lo, hi;
+    if (!block_key_range(k, valid, lo, hi)) return;   // no valid lane (block-wide)
     const WaveRun r = wave_run(k, valid);
     uint32_t base = 0;
-    if (r.head) base = atomicAdd(&cursor[k], (uint32_t)r.len);
+    const bool local = hi - lo < kSortSpan;
+    if (local) {
+        for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) lc[e] = 0u;
+        __syncthreads();
+        // the run's place among the block's particles of its tile
+        if (valid && r.head) base = atomicAdd(&lc[k - lo], (uint32_t)r.len);
+        __syncthreads();
+        // the block's place among the tile's particles
+        for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) {
+            const uint32_t c = lc[e];
+            if (c) lc[e] = atomicAdd(&cursor[lo + e], c);
+        }
+        __syncthreads();
+    } else if (valid && r.head) {
+        base = atomicAdd(&cursor[k], (uint32_t)r.len);
+    }
     base = (uint32_t)__shfl((int)base, r.head_lane, 64);
     if (!valid) return;
+    if (local) base += lc[k - lo];
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)offsets[k] + base + (lane - r.head_lane);
 #pragma unroll

@@ -61,24 +61,52 @@ def test_standing_wave_refresh_matches_generator(sr):
             assert np.all(np.abs(g - ref) <= np.spacing(np.abs(ref).astype(np.float32)) + 1e-30)
 
 
-def test_sort_particles_is_tile_ordered_permutation(sr):
-    cfg = synth.config("c3", grid=(40, 32, 24), slab=None)
-    n = 50001
+@pytest.mark.parametrize("case", ["few_tiles", "many_tiles", "nearly_sorted"])
+def test_sort_particles_is_tile_ordered_permutation(sr, case):
+    """few_tiles: 120 tiles, so every block groups its keys in LDS;
+    many_tiles: 2^21 one-cell tiles and unsorted particles, so blocks span
+    more keys than they group and take per-run global atomics;
+    nearly_sorted: sorted, then moved by up to two cells (the state of a
+    resort in the loop), 2^14 tiles."""
+    if case == "few_tiles":
+        cfg = synth.config("c3", grid=(40, 32, 24), slab=None)
+        tile, n = (8, 8, 4), 50001
+    elif case == "many_tiles":
+        cfg = synth.config("c3", grid=(256, 128, 64), slab=None)
+        tile, n = (1, 1, 1), 200003
+    else:
+        cfg = synth.config("c3", grid=(128, 64, 64), slab=None)
+        tile, n = (4, 4, 8), 300007
     st = synth.gen_particles(cfg, n=n)
+    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    work = sr.sort_work(grid, tile, n)
+    if case == "nearly_sorted":
+        parts0 = sr.Particles.from_numpy(st, dim=3)
+        tmp = parts0.empty_like()
+        sr.sort_particles(parts0, tmp, grid, tile, work)
+        torch.cuda.synchronize()
+        st = tmp.to_numpy()
+        rng = np.random.default_rng(7)
+        for a, k in enumerate(("x", "y", "z")):
+            L = cfg.grid[a] * cfg.dx
+            moved = st[k] + rng.uniform(-2, 2, n) * cfg.dx
+            st[k] = np.mod(moved, L).astype(np.float32)
+            st[k] = np.where(st[k] >= np.float32(L), np.float32(0), st[k])
+        for k in ("px", "py", "pz", "w"):
+            st[k] = st[k].astype(np.float32)
+        del parts0, tmp
     parts = sr.Particles.from_numpy(st, dim=3)
     dst = parts.empty_like()
-    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
-    tile = (8, 8, 4)
-    work = sr.sort_work(grid, tile, n)
-    _say("sort 50001")
+    _say(f"sort {case} {n}")
     sr.sort_particles(parts, dst, grid, tile, work)
     torch.cuda.synchronize()
     g = dst.to_numpy()
-    assert np.array_equal(np.sort(g["id"]), np.arange(n, dtype=np.uint32))
+    assert np.array_equal(np.sort(g["id"]), np.sort(np.asarray(st["id"], np.uint32)))
     # every particle keeps its own state
     o = np.argsort(g["id"])
+    oi = np.argsort(np.asarray(st["id"]))
     for k in ("x", "y", "z", "px", "py", "pz"):
-        assert np.array_equal(g[k][o], st[k].astype(np.float64))
+        assert np.array_equal(g[k][o], np.asarray(st[k], np.float32)[oi].astype(np.float64))
     cell = [np.clip(np.floor(g[k].astype(np.float32) * np.float32(1 / cfg.dx)).astype(np.int64), 0,
                     cfg.grid[a] - 1) for a, k in enumerate(("x", "y", "z"))]
     nt = [-(-cfg.grid[a] // tile[a]) for a in range(3)]
