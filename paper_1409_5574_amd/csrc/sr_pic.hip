@@ -203,15 +203,20 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 // The box holds fixed-point integers, not floats: on gfx950 an LDS float
 // atomic add takes about 40 times as long as an integer one, and it was the
 // bulk of the deposit's time.  Each contribution v is rounded to an integer
-// multiple of 2^(e-22), where 2^e bounds every contribution of the block: on
+// multiple of 2^(e-21), where 2^e bounds every contribution of the block: on
 // each axis |v| <= |c_a| |du_a| (the partial sums of D over a hat shape are
 // bounded by the move du in cells, the transverse factor lies in [0, 1]), and
 // |v| <= |c_z| for the 2D Jz.  A node takes at most one contribution per
-// particle and component, so a sum stays below 256 * 2^22 = 2^30, and the
+// particle and component, so a sum stays below 512 * 2^21 = 2^30, and the
 // integer adds are exact and independent of order.  The rounding error per
-// contribution is at most 2^-22 of the block's largest bound.
-constexpr int kDepCells = 2048;
-constexpr int kDepFracBits = 22;
+// contribution is at most 2^-21 of the block's largest bound.
+constexpr int kDepThreads = 512;   // particles per block
+constexpr int kDepWaves = kDepThreads / 64;
+constexpr int kDepCells = 3072;
+// 2^kDepFracBits units per bound and at most kDepThreads contributions per
+// node: sums stay below 2^30
+constexpr int kDepFracBits = 30 - 9;
+static_assert(kDepThreads == 512, "kDepFracBits assumes 2^9 particles per block");
 
 struct Stencil {
     int I[3];              // old cell of the particle on each axis
@@ -357,15 +362,15 @@ __device__ __forceinline__ void esirkepov(const Stencil &s, ADD &&add) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const float *xo0,
+__global__ __launch_bounds__(kDepThreads) void current_kernel(sr_particles_f32 P, const float *xo0,
                                                       const float *xo1, const float *xo2,
                                                       PicGrid G, float qv, float inv_dt,
                                                       float *__restrict__ jx, float *__restrict__ jy,
                                                       float *__restrict__ jz,
                                                       uint32_t *__restrict__ status) {
     __shared__ int box[3 * kDepCells];
-    __shared__ int red[2][3][kWaves];
-    __shared__ float bmax[kWaves];
+    __shared__ int red[2][3][kDepWaves];
+    __shared__ float bmax[kDepWaves];
     __shared__ int ref[3];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < P.n;
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
     float *const J[3] = {jx, jy, jz};
 
     // the cells relative to the block's first particle (always active: the
-    // grid has ceil(n / 256) blocks), unwrapped across the periodic boundary
+    // grid has ceil(n / kDepThreads) blocks), unwrapped across the periodic boundary
     if (threadIdx.x == 0)
         for (int a = 0; a < 3; ++a) ref[a] = s.I[a];
     __syncthreads();
@@ -415,7 +420,7 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int lo = red[0][a][0], hi = red[1][a][0];
-        for (int w = 1; w < kWaves; ++w) { lo = min(lo, red[0][a][w]); hi = max(hi, red[1][a][w]); }
+        for (int w = 1; w < kDepWaves; ++w) { lo = min(lo, red[0][a][w]); hi = max(hi, red[1][a][w]); }
         any = any && hi >= lo;      // no live particle: lo > hi
         if (a < DIM) {
             org[a] = lo - 1;
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
     }
     if (!any) return;               // no live particle (the condition is block-wide)
     float bnd = bmax[0];
-    for (int w = 1; w < kWaves; ++w) bnd = fmaxf(bnd, bmax[w]);
+    for (int w = 1; w < kDepWaves; ++w) bnd = fmaxf(bnd, bmax[w]);
     // bnd < 2^e: contributions in units of 2^(e - kDepFracBits).  A
     // non-finite bound, or one so small that 2^(kDepFracBits - e) would not
     // be a finite float, sends the whole block to the float path.
@@ -440,8 +445,8 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
     // can be as large as the grid.
     int64_t vol = (int64_t)ext[0] * ext[1] * ext[2];
     if (fixed && vol > kDepCells) {
-        __shared__ float msum[3][kWaves];
-        __shared__ int mcnt[kWaves];
+        __shared__ float msum[3][kDepWaves];
+        __shared__ int mcnt[kDepWaves];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             float v = s.live ? (float)(U[a] - ref[a]) : 0.0f;
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
         if (lane == 0) mcnt[wave] = live;
         __syncthreads();
         int cnt = 0;
-        for (int w = 0; w < kWaves; ++w) cnt += mcnt[w];
+        for (int w = 0; w < kDepWaves; ++w) cnt += mcnt[w];
         for (int it = 0; it < DIM && vol > kDepCells; ++it) {
             int a = 0;
             for (int b = 1; b < DIM; ++b)
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(256) void current_kernel(sr_particles_f32 P, const 
             const int64_t other = vol / ext[a];
             const int wdt = (int)min<int64_t>(ext[a], max<int64_t>(4, kDepCells / other));
             float sum = 0.0f;
-            for (int w = 0; w < kWaves; ++w) sum += msum[a][w];
+            for (int w = 0; w < kDepWaves; ++w) sum += msum[a][w];
             const int c = ref[a] + (int)floorf(sum / (float)max(cnt, 1) + 0.5f);
             org[a] = min(max(c - wdt / 2, org[a]), org[a] + ext[a] - wdt);
             ext[a] = wdt;
@@ -619,13 +624,13 @@ extern "C" int sr_deposit_current(const sr_particles_f32 *parts, const float *x_
         if (!parts->x[a] || !x_old[a]) return SR_E_INVAL;
     if (!parts->w || (dim == 2 && (!parts->p[0] || !parts->p[1] || !parts->p[2])))
         return SR_E_INVAL;
-    const unsigned nb = (unsigned)((parts->n + 255) / 256);
+    const unsigned nb = (unsigned)((parts->n + kDepThreads - 1) / kDepThreads);
     hipStream_t st = (hipStream_t)stream;
     if (dim == 3)
-        current_kernel<3><<<nb, 256, 0, st>>>(*parts, x_old[0], x_old[1], x_old[2], G, (float)charge,
+        current_kernel<3><<<nb, kDepThreads, 0, st>>>(*parts, x_old[0], x_old[1], x_old[2], G, (float)charge,
                                               (float)(1.0 / dt), j[0], j[1], j[2], status);
     else
-        current_kernel<2><<<nb, 256, 0, st>>>(*parts, x_old[0], x_old[1], nullptr, G, (float)charge,
+        current_kernel<2><<<nb, kDepThreads, 0, st>>>(*parts, x_old[0], x_old[1], nullptr, G, (float)charge,
                                               (float)(1.0 / dt), j[0], j[1], j[2], status);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
