@@ -44,7 +44,7 @@ typedef enum {
     SR_E_INVAL = -1,       /* bad argument (null pointer, size, mode)          */
     SR_E_HIP = -2,         /* a HIP runtime call failed                         */
     SR_E_NOMEM = -3,       /* sr_table_build could not allocate                 */
-    SR_E_UNSUPPORTED = -4  /* valid request this build does not provide         */
+    SR_E_UNSUPPORTED = -4  /* valid request the library does not provide      */
 } sr_error;
 
 /* Bits latched in the device status word (sr_ledger.status). */
