@@ -179,6 +179,55 @@ def test_step_epilogue_equals_separate_calls(sr, table, n):
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=0.0)
 
 
+def test_step_epilogue_ragged_chunks_and_empty_histogram(sr, table):
+    """Explicit (ragged) chunks, including empty ones, through the fused
+    epilogue against the separate calls; and a photon buffer with no slots,
+    where the histogram part does nothing and the ledger row is still summed."""
+    cfg = synth.config("c2", grid=(64, 64, 1))
+    n, K = 40000, 2
+    rng = np.random.default_rng(3)
+    sizes = rng.integers(0, 65, 2000)
+    sizes[:5] = 0
+    cuts = np.concatenate([[0], np.cumsum(sizes)])
+    cuts = cuts[cuts <= n]
+    if cuts[-1] != n:
+        cuts = np.concatenate([cuts, [n]])
+    nch = len(cuts) - 1
+    start = torch.from_numpy(cuts.astype(np.int64)).to("cuda")
+    st = synth.gen_particles(cfg, n=n)
+    for k in ("px", "py", "pz"):
+        st[k] = (st[k] * 2000.0).astype(np.float32)
+    E, B = synth.standing_wave_grid(cfg, 0.2)
+    parts = sr.Particles.from_numpy(st, dim=2)
+    fields = sr.Fields(E, B)
+    grid = sr.grid_struct(2, n=cfg.grid, dx=(cfg.dx,) * 3)
+    photons = sr.PhotonBuffer(n, K, n_chunks=nch, dim=2)
+    ledger = sr.LedgerBuf(3, nch)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, kin_cut=cfg.kin_cut)
+    _say(f"step epilogue ragged {nch} chunks")
+    sr.gather_push_emit(parts, fields, grid, cfg.dt, 5, 0, prm, table, photons, ledger, None,
+                        start=start)
+    nb, lo, hi = 40, 1e-6, 1e4
+    h_sep = torch.zeros(2 * nb, device="cuda", dtype=torch.float64)
+    h_fused = torch.zeros(2 * nb, device="cuda", dtype=torch.float64)
+    sr.ledger_reduce(ledger, nch, 0)
+    sr.spectrum_histogram(photons, n, lo, hi, nb, h_sep, sr.hist_work(nb), start=start)
+    sr.step_epilogue(ledger, nch, 1, photons, n, lo, hi, nb, h_fused, sr.hist_work(nb), start=start)
+    # no photon slots: the histogram is left alone, the ledger row is summed
+    empty = sr.PhotonBuffer(n, 0, n_chunks=nch, dim=2)
+    h_none = torch.full((2 * nb,), 7.0, device="cuda", dtype=torch.float64)
+    sr.step_epilogue(ledger, nch, 2, empty, n, lo, hi, nb, h_none, sr.hist_work(nb), start=start)
+    torch.cuda.synchronize()
+    rows = ledger.rows.cpu().numpy()
+    assert rows[0][1] > 0.0
+    assert np.array_equal(rows[0], rows[1])
+    assert np.array_equal(rows[0], rows[2])
+    a, b = h_fused.cpu().numpy(), h_sep.cpu().numpy()
+    assert b[:nb].sum() > 0.0
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=0.0)
+    assert np.all(h_none.cpu().numpy() == 7.0)
+
+
 def _angular_reference(ph, axis, ref, nt, nph):
     """FP64 binning of the gathered photons by (theta, phi) about axis, with
     each photon's distance to the nearest bin edge (theta, phi in radians, the

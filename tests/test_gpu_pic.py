@@ -213,6 +213,49 @@ def test_current_box_path_matches_oracle(sr, dim, case):
     _check_current(sr, dim, n, dx, p0[o], p1[o], mom[o], w[o], case)
 
 
+@pytest.mark.parametrize("count", [1, 513])
+def test_current_single_particle_and_partial_block(sr, count):
+    """One particle, and one particle past a full block, against the oracle."""
+    dim = 3
+    n, dx = _geom(dim)
+    rng = np.random.default_rng(60 + count)
+    p0, p1 = _moves(dim, n, dx, count, rng)
+    w = rng.uniform(0.5, 2.0, count).astype(np.float32)
+    mom = rng.normal(0, 3.0, (count, 3)).astype(np.float32)
+    o = _tile_order(p0, dim, n, dx, (4, 4, 2))
+    _check_current(sr, dim, n, dx, p0[o], p1[o], mom[o], w[o], f"n={count}")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_current_of_resting_or_weightless_particles_is_zero(sr, dim):
+    """Every contribution zero (resting particles with p_z = 0, and moving
+    particles of zero weight): the block's bound is zero and nothing is added."""
+    n, dx = _geom(dim)
+    shape = (n[2], n[1], n[0])
+    rng = np.random.default_rng(70 + dim)
+    count = 3000
+    p0, p1 = _moves(dim, n, dx, count, rng)
+    half = count // 2
+    p1[:half] = p0[:half]                       # resting
+    w = np.ones(count, np.float32)
+    w[half:] = 0.0                              # weightless movers
+    mom = rng.normal(0, 3.0, (count, 3)).astype(np.float32)
+    mom[:half, 2] = 0.0
+    o = _tile_order(p0, dim, n, dx, (4, 4, 2))
+    grid = sr.grid_struct(dim, n=n, dx=dx)
+    parts = _parts(sr, dim, p1[o], mom[o], w[o])
+    x_old = [_dev(p0[o][:, a]) for a in range(dim)] + [None] * (3 - dim)
+    cells = int(np.prod(shape))
+    J = [torch.full((cells,), 0.0, device="cuda", dtype=torch.float32) for _ in range(3)]
+    status = torch.zeros(1, device="cuda", dtype=torch.int32)
+    _say(f"deposit current zero contributions {dim}D")
+    sr.deposit_current(parts, x_old, grid, 0.11, -1.0, J, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    for a in range(3):
+        assert torch.count_nonzero(J[a]).item() == 0
+
+
 def test_current_flags_long_moves(sr):
     dim = 2
     n, dx = _geom(dim)
