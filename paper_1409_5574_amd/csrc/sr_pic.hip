@@ -142,6 +142,15 @@ __device__ __forceinline__ int node(int i, int c, int n) {
     return min(max(v, 0), n - 1);
 }
 
+// l / d for 0 <= l < 2^22 and d >= 1, from a float reciprocal: the product
+// is within one of the quotient, and one step each way corrects it
+__device__ __forceinline__ int div_small(int l, int d, float inv_d) {
+    int q = (int)((float)l * inv_d);
+    q -= q * d > l ? 1 : 0;
+    q += (q + 1) * d <= l ? 1 : 0;
+    return q;
+}
+
 // i in [-2n, 3n) onto [0, n)
 __device__ __forceinline__ int wrap2(int i, int n) {
     if (i < 0) i += n;
@@ -499,12 +508,14 @@ __global__ __launch_bounds__(kDepThreads) void current_kernel(sr_particles_f32 P
         });
     }
     __syncthreads();
+    const float inv_cells = 1.0f / (float)cells, inv_e0 = 1.0f / (float)ext[0];
+    const float inv_e1 = 1.0f / (float)ext[1];
     for (int q = threadIdx.x; q < 3 * cells; q += blockDim.x) {
         const int sum = box[q];
         if (sum == 0) continue;
-        const int comp = q / cells, l = q - comp * cells;
-        const int li = l % ext[0], r = l / ext[0];
-        const int lj = r % ext[1], lk = r / ext[1];
+        const int comp = div_small(q, cells, inv_cells), l = q - comp * cells;
+        const int r = div_small(l, ext[0], inv_e0), li = l - r * ext[0];
+        const int lk = div_small(r, ext[1], inv_e1), lj = r - lk * ext[1];
         // the box's nodes wrapped onto the periodic grid: they lie in
         // [-n/2 - 1, 3n/2 + 1], so two wraps each way reach [0, n) for any n
         int i = org[0] + li, j = org[1] + lj, k = org[2] + lk;
