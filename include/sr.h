@@ -285,8 +285,12 @@ int sr_deposit_rho(const sr_particles_f32 *parts, const sr_grid *grid, double ch
  * further deposits nothing and sets SR_W_CFL in *status (device uint32).  In
  * 2D, Jz is charge w v_z S / dV with v_z = p_z / gamma(p) of parts->p, the
  * momentum the position push used.  x_old: device arrays of the positions at
- * the start of the step (x_old[2] unused in 2D).  Float atomics: the order of
- * the sums is not fixed. */
+ * the start of the step (x_old[2] unused in 2D).  Each block of particles sums
+ * its contributions exactly in fixed point, in units of 2^(e-21) where 2^e is
+ * the power of two just above the largest bound B of a contribution in the
+ * block (|c_a du_a| per axis, |c_z| for the 2D Jz), so that a contribution is
+ * rounded by at most 2^-21 B; the block sums are then added to j with float
+ * atomics, whose order is not fixed. */
 int sr_deposit_current(const sr_particles_f32 *parts, const float *x_old[3], const sr_grid *grid,
                        double dt, double charge, float *j[3], uint32_t *status, void *stream);
 
