@@ -189,13 +189,13 @@ __global__ void scan_add(uint32_t *out, int64_t n, const uint32_t *block_prefix)
     if (i < n) out[i] += block_prefix[i / 1024];
 }
 
-// Each particle goes to offsets[key] + its slot among the tile's particles.
-// Slots are handed out per block and key (LDS), then per block from the
-// tile's cursor (one global atomic per distinct key of the block); a block
+// Each particle goes to its slot among the tile's particles, counted from the
+// tile's offset: offsets[key] serves as the tile's cursor (it ends as the
+// tile's end).  Slots are handed out per block and key (LDS), then per block
+// from the cursor (one global atomic per distinct key of the block); a block
 // whose keys span kSortSpan or more takes a global atomic per run.
 __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst,
-                                                    const uint32_t *keys, const uint32_t *offsets,
-                                                    uint32_t *cursor) {
+                                                    const uint32_t *keys, uint32_t *cursor) {
     __shared__ uint32_t lc[kSortSpan];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < src.n;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
         // the run's place among the block's particles of its tile
         if (valid && r.head) base = atomicAdd(&lc[k - lo], (uint32_t)r.len);
         __syncthreads();
-        // the block's place among the tile's particles
+        // the block's first slot in the tile
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) {
             const uint32_t c = lc[e];
             if (c) lc[e] = atomicAdd(&cursor[lo + e], c);
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
     if (!valid) return;
     if (local) base += lc[k - lo];
     const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)offsets[k] + base + (lane - r.head_lane);
+    const int64_t j = (int64_t)base + (lane - r.head_lane);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (src.x[a] && dst.x[a]) dst.x[a][j] = v[a];
@@ -396,7 +396,7 @@ extern "C" int64_t sr_sort_work(const sr_grid *grid, const int32_t tile[3], int6
     int64_t nt;
     if (n < 0 || !sort_geom(grid, tile, g, nt)) return -1;
     const int64_t nblk = (nt + 1023) / 1024;
-    // counts, offsets, cursor (n_tiles each), block sums + their prefix, keys (n)
+    // counts, offsets, one spare (n_tiles each), block sums + their prefix, keys (n)
     return (int64_t)sizeof(uint32_t) * (3 * nt + 2 * (nblk + 1024) + n);
 }
 
@@ -418,14 +418,12 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
     if (nblk > 1024 * 1024) return SR_E_UNSUPPORTED;
     uint32_t *counts = (uint32_t *)work;
     uint32_t *offsets = counts + nt;
-    uint32_t *cursor = offsets + nt;
-    uint32_t *bsum = cursor + nt;
+    uint32_t *bsum = offsets + 2 * nt;   // after the spare n_tiles words
     uint32_t *bpre = bsum + nblk + 1024;
     uint32_t *keys = bpre + nblk + 1024;
     hipStream_t st = (hipStream_t)stream;
     const unsigned g256 = (unsigned)((nt + 255) / 256);
     fill_u32<<<g256, 256, 0, st>>>(counts, nt, 0u);
-    fill_u32<<<g256, 256, 0, st>>>(cursor, nt, 0u);
     sort_count<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src->x[0], src->x[1], src->x[2], n, g,
                                                             keys, counts);
     scan_blocks<<<(unsigned)nblk, 256, 0, st>>>(counts, offsets, nt, bsum);
@@ -442,7 +440,7 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
         }
         scan_add<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(offsets, nt, bpre);
     }
-    sort_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(*src, *dst, keys, offsets, cursor);
+    sort_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(*src, *dst, keys, offsets);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }
