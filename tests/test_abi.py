@@ -246,3 +246,36 @@ def test_pic_calls_reject_bad_arguments_on_host(lib):
     assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), 0.05, None) == L.SR_E_INVAL
     ph.seg_count = d
     assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), -1.0, None) == L.SR_E_INVAL
+
+
+def test_step_epilogue_rejects_bad_arguments_on_host(lib):
+    """The epilogue takes the checks of both calls it fuses, before any launch."""
+    from paper_1409_5574_amd import _lib as L
+    d = C.c_void_p(16)
+    led = L.Ledger()
+    led.rows, led.partials, led.status = d, d, d
+    led.n_rows = 2
+    led.partials_len = lib.sr_ledger_partials(8)
+    ph = L.PhotonBuf()
+    ph.seg_count = d
+    ch = L.Chunking(8, None)
+
+    def call(ledger=C.byref(led), n_chunks=8, row=0, photons=C.byref(ph), chunks=C.byref(ch),
+             n=500, lo=1e-6, hi=1e4, bins=16, hist=d, work=d):
+        return lib.sr_step_epilogue(ledger, n_chunks, row, photons, chunks, n, lo, hi, bins, hist,
+                                    work, None)
+
+    assert call(ledger=None) == L.SR_E_INVAL
+    assert call(row=2) == L.SR_E_INVAL                 # past the ledger's rows
+    assert call(n_chunks=-1) == L.SR_E_INVAL
+    assert call(n_chunks=1 << 20) == L.SR_E_INVAL      # partials too short
+    assert call(photons=None) == L.SR_E_INVAL
+    assert call(chunks=None) == L.SR_E_INVAL
+    assert call(hist=None) == L.SR_E_INVAL
+    assert call(work=None) == L.SR_E_INVAL
+    assert call(bins=0) == L.SR_E_INVAL
+    assert call(bins=1025) == L.SR_E_INVAL
+    assert call(lo=0.0) == L.SR_E_INVAL
+    assert call(hi=1e-7) == L.SR_E_INVAL                # hi below lo
+    ph.per_particle = 2                                 # slots but no eps / w arrays
+    assert call() == L.SR_E_INVAL
