@@ -337,7 +337,8 @@ extern "C" int sr_angular_histogram(const sr_photon_buf *ph, const sr_chunking *
     if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
     if (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2]) return SR_E_INVAL;
     const int nvals = n_theta * n_phi + 1;
-    const int nb = hist_blocks(n_chunks);
+    const int64_t groups = (n_chunks + 255) / 256;   // one lane per chunk
+    const int nb = (int)(groups < kHistBlocks ? groups : kHistBlocks);
     hipStream_t st = (hipStream_t)stream;
     angular_kernel<<<nb, 256, sizeof(double) * nvals, st>>>(
         *ph, chunks->start, n_chunks, n, make_float3((float)a[0], (float)a[1], (float)a[2]),

@@ -9,38 +9,42 @@ namespace sr {
 
 constexpr int kHistBlocks = 512;   // most blocks of the accumulation pass
 constexpr int kMaxBins = 1024;
+constexpr int kHistChunks = 64;    // chunks per block and group (four lanes each)
 
-// One lane per chunk: each lane walks the stored photons of its chunk and adds
-// w eps and w to bins of log2 eps in the block's LDS histogram sh[2 nbins]
-// (FP64 LDS atomics).  Block hb of nblocks strides over groups of 256 chunks
-// and writes its histogram to work[hb].  Call with the whole block.
+// Four lanes per chunk: the lanes of a chunk walk its stored photons in turn
+// and add w eps and w to bins of log2 eps in the block's LDS histogram
+// sh[2 nbins] (FP64 LDS atomics, which cost about one lane per few cycles, so
+// the photons are spread over many blocks).  Block hb of nblocks strides over
+// groups of kHistChunks chunks and writes its histogram to work[hb].  Call
+// with the whole block of 256 threads.
 __device__ __forceinline__ void hist_block(const sr_photon_buf &ph, const int64_t *start,
                                            int64_t n_chunks, int64_t n, float l2lo, float scale,
                                            int nbins, double *work, int hb, int nblocks,
                                            double *sh) {
     for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) sh[b] = 0.0;
     __syncthreads();
-    for (int64_t c = (int64_t)hb * blockDim.x + threadIdx.x; c < n_chunks;
-         c += (int64_t)nblocks * blockDim.x) {
+    const int sub = threadIdx.x & 3;
+    for (int64_t c = (int64_t)hb * kHistChunks + (threadIdx.x >> 2); c < n_chunks;
+         c += (int64_t)nblocks * kHistChunks) {
         const int64_t s0 = start ? start[c] : c * (int64_t)kChunk;
         const int64_t e0 = start ? start[c + 1] : min(s0 + (int64_t)kChunk, n);
         const int64_t cap = (e0 - s0) * ph.per_particle;
         const int64_t cnt = min((int64_t)ph.seg_count[c], cap);
         const int64_t base = s0 * ph.per_particle;
-        // eight photons at a time: their loads are in flight together
-        for (int64_t q0 = 0; q0 < cnt; q0 += 8) {
-            float eps[8], w[8];
+        // photons sub, sub + 4, ...: two of the lane's at a time, loads in flight
+        for (int64_t q0 = sub; q0 < cnt; q0 += 8) {
+            float eps[2], w[2];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 eps[j] = 0.0f;
                 w[j] = 0.0f;
-                if (q0 + j < cnt) {
-                    eps[j] = ph.eps[base + q0 + j];
-                    w[j] = ph.w[base + q0 + j];
+                if (q0 + 4 * j < cnt) {
+                    eps[j] = ph.eps[base + q0 + 4 * j];
+                    w[j] = ph.w[base + q0 + 4 * j];
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 if (!(eps[j] > 0.0f)) continue;
                 const float u = (__log2f(eps[j]) - l2lo) * scale;
                 if (u < 0.0f || u >= (float)nbins) continue;
@@ -73,7 +77,7 @@ __device__ __forceinline__ void hist_reduce_value(const double *work, int nblock
 
 // Blocks of the accumulation pass for n_chunks chunks.
 inline int hist_blocks(int64_t n_chunks) {
-    const int64_t groups = (n_chunks + 255) / 256;
+    const int64_t groups = (n_chunks + kHistChunks - 1) / kHistChunks;
     return (int)(groups < kHistBlocks ? groups : kHistBlocks);
 }
 
