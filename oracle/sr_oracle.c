@@ -432,8 +432,15 @@ static void step_one(int64_t i, double *x, double *y, double *z,
 
     /* steps 1-2: H_eff (limited), then omega_c = 1.5 H gamma^2 and chi */
     double gb = 0.0, ratio = 0.0;
-    const double H = orc_heff(p_old, p_new, dt, &gb, &ratio);
-    const double chi = prm->hbar_n * H * gb;
+    double H = orc_heff(p_old, p_new, dt, &gb, &ratio);
+    /* The paper assumes finite fields and momenta.  A particle whose push is not
+       finite (a non-finite field value or momentum) is given H_eff = chi = 0:
+       it emits nothing and adds nothing to the ledger, and its momentum and
+       position are stored as computed. */
+    const int bad = !(isfinite(p_new[0]) && isfinite(p_new[1]) && isfinite(p_new[2]) &&
+                      isfinite(H) && isfinite(gb));
+    if (bad) H = 0.0;
+    const double chi = bad ? 0.0 : prm->hbar_n * H * gb;
     double pbar[3], pbm;
     for (int c = 0; c < 3; ++c) pbar[c] = 0.5 * (p_old[c] + p_new[c]);
     pbm = sqrt(pbar[0] * pbar[0] + pbar[1] * pbar[1] + pbar[2] * pbar[2]);
@@ -517,11 +524,11 @@ static void step_one(int64_t i, double *x, double *y, double *z,
 
     /* Landau-Lifshitz loss (eq:LLformOfRRForce): |f.v| dt = (2/3)(alpha/hbar_n) chi^2 beta^2 dt */
     const double beta2 = (gb > 0.0) ? (pbm * pbm) / (gb * gb) : 0.0;
-    const double ll = wi * (2.0 / 3.0) * (prm->alpha / prm->hbar_n) * chi * chi * beta2 * dt;
+    const double ll = bad ? 0.0 : wi * (2.0 / 3.0) * (prm->alpha / prm->hbar_n) * chi * chi * beta2 * dt;
 
     /* recoil: reduce |p| along the post-push momentum */
     double clamped = 0.0, dE = 0.0;
-    if (prm->recoil == ORC_RECOIL_LL)
+    if (prm->recoil == ORC_RECOIL_LL && !bad)
         delta = dt * (2.0 / 3.0) * (prm->alpha / prm->hbar_n) * chi * chi * (gb > 0.0 ? pbm / gb : 0.0);
     else if (prm->recoil == ORC_RECOIL_NONE)
         delta = 0.0;

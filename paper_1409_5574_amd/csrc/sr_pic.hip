@@ -606,7 +606,9 @@ extern "C" int sr_deposit_rho(const sr_particles_f32 *parts, const sr_grid *grid
     PicGrid G;
     const int rc = pic_grid(grid, G);
     if (rc != SR_OK) return rc;
-    if (!parts || !rho || parts->n < 0 || parts->n >= ((int64_t)1 << 31)) return SR_E_INVAL;
+    if (!parts || !rho || parts->n < 0) return SR_E_INVAL;
+    // element offsets are formed as 32-bit byte offsets (below 2^31 bytes)
+    if (parts->n >= ((int64_t)1 << 29)) return SR_E_UNSUPPORTED;
     if (parts->n == 0) return SR_OK;
     if (!parts->x[0] || !parts->x[1] || (grid->dim == 3 && !parts->x[2]) || !parts->w)
         return SR_E_INVAL;
@@ -624,9 +626,9 @@ extern "C" int sr_deposit_current(const sr_particles_f32 *parts, const float *x_
     PicGrid G;
     const int rc = pic_grid(grid, G);
     if (rc != SR_OK) return rc;
-    if (!parts || !x_old || !j || !status || !(dt > 0.0) || parts->n < 0 ||
-        parts->n >= ((int64_t)1 << 31))
-        return SR_E_INVAL;
+    if (!parts || !x_old || !j || !status || !(dt > 0.0) || parts->n < 0) return SR_E_INVAL;
+    // element offsets are formed as 32-bit byte offsets (below 2^31 bytes)
+    if (parts->n >= ((int64_t)1 << 29)) return SR_E_UNSUPPORTED;
     for (int q = 0; q < 3; ++q)
         if (!j[q]) return SR_E_INVAL;
     if (parts->n == 0) return SR_OK;
@@ -656,7 +658,8 @@ extern "C" int sr_photon_advance(const sr_photon_buf *ph, const sr_chunking *chu
     const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
     if (n_chunks == 0 || ph->per_particle == 0) return SR_OK;
     if (!ph->dir[0] || !ph->dir[1] || !ph->dir[2]) return SR_E_INVAL;
-    if (n * ph->per_particle >= ((int64_t)1 << 32)) return SR_E_UNSUPPORTED;
+    // photon slots are addressed with 32-bit byte offsets (below 2^32 bytes)
+    if (n * ph->per_particle >= ((int64_t)1 << 30)) return SR_E_UNSUPPORTED;
     const unsigned nb = (unsigned)((n_chunks + 255) / 256);
     photon_advance_kernel<<<nb, 256, 0, (hipStream_t)stream>>>(*ph, chunks->start, n_chunks, n, G,
                                                                grid->dim, (float)dt);

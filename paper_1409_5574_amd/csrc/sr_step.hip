@@ -115,6 +115,7 @@ struct Pushed {
     R pbm;        // |pb|
     R H;          // H_eff
     R chi;        // hbar_n H_eff gamma_bar
+    bool bad;     // the push is not finite (a non-finite field value or momentum)
 };
 
 template <typename R, int DIM>
@@ -154,11 +155,16 @@ __device__ __forceinline__ Pushed<R> push_heff(const StepArgs<R> &a, const R pos
     o.g_new = sqrt_r<R>((R)1 + o.pn[0] * o.pn[0] + o.pn[1] * o.pn[1] + o.pn[2] * o.pn[2]);
     o.gb = (R)0.5 * (g_old + o.g_new);
     o.pbm = sqrt_r<R>(o.p2);
-    const R inv_p2 = o.p2 > (R)0 ? rcp_r<R>(o.p2) : (R)0;
-    R ratio = sqrt_r<R>(c2) * inv_p2;
+    // H_eff = 0 when the mean momentum vanishes (no direction of motion)
+    R ratio = o.p2 > (R)0 ? sqrt_r<R>(c2) * rcp_r<R>(o.p2) : (R)0;
     if (ratio > (R)1) ratio = (R)1;
-    o.H = o.gb * ratio * a.inv_dt;
-    o.chi = a.hbar_n * o.H * o.gb;
+    o.H = o.p2 > (R)0 ? o.gb * ratio * a.inv_dt : (R)0;
+    // A push that is not finite gives H_eff = chi = 0: the particle emits
+    // nothing and adds nothing to the ledger; the caller flags it.
+    o.bad = !(isfinite(o.pn[0]) && isfinite(o.pn[1]) && isfinite(o.pn[2]) && isfinite(o.H) &&
+              isfinite(o.gb));
+    if (o.bad) o.H = (R)0;
+    o.chi = o.bad ? (R)0 : a.hbar_n * o.H * o.gb;
     return o;
 }
 
@@ -351,6 +357,7 @@ void push_emit_kernel(const StepArgs<R> a) {
         // state carried from the push to the recoil
         R wi = (R)0, pos[3] = {(R)0, (R)0, (R)0}, pn[3] = {(R)0, (R)0, (R)0};
         R chi = (R)0, gb = (R)1, g_new = (R)1, p2 = (R)0, pbm = (R)0;
+        bool bad = false;
         if (active) {
             wi = ld(a.w, i);
             pid = ld(a.id, i);
@@ -371,7 +378,8 @@ void push_emit_kernel(const StepArgs<R> a) {
             const R pb[3] = {q.pb[0], q.pb[1], q.pb[2]};
             Hf = (float)H;
             chif = (float)chi;
-            if (!isfinite(H)) flags |= SR_W_NONFINITE;
+            bad = q.bad;
+            if (bad) flags |= SR_W_NONFINITE;
             if (pbm > (R)0) {
                 const R inv = rcp_r<R>(pbm);
                 dirf[0] = (float)(pb[0] * inv); dirf[1] = (float)(pb[1] * inv);
@@ -565,7 +573,7 @@ void push_emit_kernel(const StepArgs<R> a) {
             acc_emit += (double)wi_f * (double)delta_ph;
             // Landau-Lifshitz loss of the step (eq:LLformOfRRForce)
             const R beta2 = p2 * rcp_r<R>(gb * gb);
-            acc_ll += (double)(wi * a.ll_c * chi * chi * beta2);
+            if (!bad) acc_ll += (double)(wi * a.ll_c * chi * chi * beta2);
 
             // ---- recoil along the post-push momentum
             R delta = (R)0;

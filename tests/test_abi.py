@@ -246,6 +246,16 @@ def test_pic_calls_reject_bad_arguments_on_host(lib):
     assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), 0.05, None) == L.SR_E_INVAL
     ph.seg_count = d
     assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), -1.0, None) == L.SR_E_INVAL
+    # sizes whose byte offsets would not fit the kernels' 32-bit offsets
+    p.n = 1 << 29
+    assert lib.sr_deposit_rho(C.byref(p), C.byref(g), -1.0, d, None) == L.SR_E_UNSUPPORTED
+    assert lib.sr_deposit_current(C.byref(p), xo, C.byref(g), 0.05, -1.0, j, d,
+                                  None) == L.SR_E_UNSUPPORTED
+    ph.per_particle = 4
+    ph.dir[0] = ph.dir[1] = ph.dir[2] = d
+    ch = L.Chunking(1 << 23, None)
+    assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 1 << 28, C.byref(g), 0.05,
+                                 None) == L.SR_E_UNSUPPORTED
 
 
 def test_step_epilogue_rejects_bad_arguments_on_host(lib):

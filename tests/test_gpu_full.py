@@ -373,8 +373,9 @@ def test_config1_full_run(sr, table, oracle):
           f"{abs(e_gpu / e_orc - 1):.2e}, LL rel {abs(ll_gpu / ll_orc - 1):.2e}, |dp|/p median "
           f"{np.median(rel):.2e} max {rel.max():.2e}", flush=True)
     del n_ph_orc
+    # the stated tolerances: 1e-3 on binned spectra, 1e-4 on the energy balance
     assert spec_err <= 1e-3
-    assert abs(e_gpu / e_orc - 1) <= 1e-3
+    assert abs(e_gpu / e_orc - 1) <= 1e-4
     assert abs(ll_gpu / ll_orc - 1) <= 1e-4
     # 1000 FP32 steps: errors accumulate at most linearly from the per-step bound
     assert np.median(rel) <= 1e-5

@@ -120,13 +120,15 @@ def _orc_state(d):
 
 def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=None, dtype=np.float32,
                   p_scale=1.0, seed=777, step=3, t=0.4, sampler=0, chunks=None, dn_policy=0,
-                  label="", omega_grid=0.0):
+                  label="", omega_grid=0.0, edit_state=None, edit_fields=None, status_ok=2):
     K = cfg.n_samples if K is None else K
     recoil = cfg.recoil if recoil is None else recoil
     kin_cut = cfg.kin_cut if kin_cut is None else kin_cut
     st = synth.gen_particles(cfg, n=n)
     for k in ("px", "py", "pz"):
         st[k] = (st[k].astype(np.float64) * p_scale).astype(np.float32)
+    if edit_state is not None:
+        edit_state(st)
     old = _orc_state(st)
     dim = cfg.dim
     if dim == 0:
@@ -136,6 +138,8 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
         fields = None
     else:
         E, B = synth.standing_wave_grid(cfg, t)
+        if edit_fields is not None:
+            edit_fields(E, B)
         fo = oracle.Field(dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
         grid = sr.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
         fields = sr.Fields(E, B)
@@ -192,12 +196,17 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
     if rep["decision_flips"]:
         flips_e = float(np.abs(ph_o["w"] * ph_o["eps"]).max()) * rep["decision_flips"]
     parity.compare_ledger(led_g, led_o, flips_e,
-                          cols=(0, 1) + ((2,) if recoil != 0 and abs(led_o[2]) > 0 else ()))
+                          cols=(0, 1, 3, 4) + ((2,) if recoil != 0 and abs(led_o[2]) > 0 else ()))
     assert led_g[5] == ph_g["count"]
     assert ph_g["count"] == ph_g["stored"]
-    assert status & ~2 == 0, status
+    assert status & ~status_ok == 0, status
+    # the clamp bit is set exactly when the oracle clamped some recoil
+    assert bool(status & 2) == (led_o[3] > 0), (status, led_o[3])
     rep["ledger_gpu"] = led_g
     rep["ledger_orc"] = led_o
+    rep["status"] = status
+    rep["det"] = det
+    rep["ph_g"] = ph_g
     return rep
 
 
@@ -236,9 +245,58 @@ def test_step_3d_fp64_path(sr, table, oracle):
     assert rep["p_rel_err"] < 1e-6
 
 
-def test_step_dn_above_one_weighting(sr, table, oracle):
+@pytest.mark.parametrize("dn_policy", [0, 1])
+def test_step_dn_above_one(sr, table, oracle, dn_policy):
+    # B = 3e4 at gamma 200..2000: many trials have dN >= 1 (policy 0 gives
+    # them weight w dN/K, policy 1 the literal min(dN, 1) of the comparison
+    # with R), and the turn per step is large enough for the limiter
+    # dp_perp/p <= 1 of eq:effective_H to act
     cfg = synth.config("c1", b0=(0.0, 0.0, 3e4), gamma_range=(200.0, 2000.0))
-    rep = run_step_case(sr, table, oracle, cfg, 2000, K=2, label="dN>=1")
+    rep = run_step_case(sr, table, oracle, cfg, 2000, K=2, dn_policy=dn_policy,
+                        label=f"dN>=1 policy {dn_policy}")
+    det = rep["det"]
+    assert rep["photons_oracle"] > 1000
+    assert (det["dn"] >= 1.0).sum() > 500
+    assert (det["ratio"] > 1.0).sum() > 100, "the limiter is not reached"
+    w = rep["ph_g"]["w"]
+    if dn_policy == 1:
+        assert np.all(w == np.float32(0.5))      # every photon carries w/K
+    else:
+        assert (w > 0.5).sum() > 100              # dN >= 1 photons carry w dN/K
+
+
+def test_step_zero_momentum_particles(sr, table, oracle):
+    # p = 0 in a pure magnetic field: the mean momentum vanishes, so H_eff = 0
+    # (no direction of motion): no photons, no LL loss, the momentum stays 0
+    cfg = synth.config("c1", b0=(0.0, 0.0, 40.0))
+    zero = np.arange(0, 3000, 3)
+
+    def edit(st):
+        for k in ("px", "py", "pz"):
+            st[k][zero] = 0.0
+
+    rep = run_step_case(sr, table, oracle, cfg, 3000, K=4, edit_state=edit, label="p = 0")
+    det = rep["det"]
+    assert np.all(det["heff"][zero] == 0.0)
+    assert rep["photons_oracle"] > 50
+
+
+def test_step_nonfinite_field_value(sr, table, oracle):
+    # one NaN Ex value and one infinite Bz value: the particles whose stencil
+    # holds them are non-finite on both sides, flagged, emit nothing and add
+    # nothing to the ledger; every other particle is unaffected
+    cfg = synth.config("c3", grid=(24, 20, 16), slab=None)
+    nx, ny = cfg.grid[0], cfg.grid[1]
+
+    def edit(E, B):
+        E[0][7 + nx * (5 + ny * 4)] = np.float32(np.nan)
+        B[2][15 + nx * (12 + ny * 9)] = np.float32(np.inf)
+
+    rep = run_step_case(sr, table, oracle, cfg, 4099, p_scale=3000.0, edit_fields=edit,
+                        status_ok=2 | 4, label="3d NaN/inf field")
+    assert rep["status"] & 4
+    assert 0 < rep["nonfinite"] < 200
+    assert np.all(np.isfinite(rep["ledger_gpu"][:5]))
     assert rep["photons_oracle"] > 1000
 
 

@@ -562,3 +562,48 @@ def test_step_is_order_independent(oracle):
     assert ph1["eps"].size > 0
     assert np.array_equal(ph1["eps"][o1], ph2["eps"][o2])
     assert np.allclose(led1, led2, rtol=1e-13)
+
+
+def test_step_nonfinite_field_value_is_contained(oracle):
+    # A NaN grid value reaches only the particles whose cloud-in-cell stencil
+    # holds that node (found here geometrically): they come out non-finite,
+    # emit nothing and add nothing to the ledger; every other particle, its
+    # photons and the ledger are those of the same step without the NaN.
+    cfg = synth.config("c3", grid=(12, 10, 8), slab=None)
+    E, B = synth.standing_wave_grid(cfg, 0.4)
+    base = {k: v.astype(np.float64) if v.dtype != np.uint32 else v.copy()
+            for k, v in synth.gen_particles(cfg, n=3000).items()}
+    for k in ("px", "py", "pz"):
+        base[k] *= 3000.0
+    node = (5, 4, 3)                 # Ex node (i + 1/2, j, k)
+    nx, ny, nz = cfg.grid
+    j_flat = node[0] + nx * (node[1] + ny * node[2])
+    E_bad = [a.copy() for a in E]
+    E_bad[0][j_flat] = np.float32(np.nan)
+    kw = dict(hbar_n=cfg.hbar_n, alpha=cfg.alpha, n_samples=4, kin_cut=True)
+    f_ok = oracle.Field(3, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
+    f_bad = oracle.Field(3, n=cfg.grid, dx=(cfg.dx,) * 3, E=E_bad, B=B)
+    # stencil of Ex: base node floor(x/dx - 1/2), floor(y/dx), floor(z/dx) and +1, periodic
+    u = np.stack([base["x"] / cfg.dx - 0.5, base["y"] / cfg.dx, base["z"] / cfg.dx], 1)
+    i0 = np.floor(u).astype(np.int64)
+    hit = np.ones(3000, bool)
+    for a, (nn, c) in enumerate(zip(cfg.grid, node)):
+        hit &= (((i0[:, a] - c) % nn) == 0) | (((i0[:, a] + 1 - c) % nn) == 0)
+    assert 0 < hit.sum() < 100
+    s_ok = {k: v.copy() for k, v in base.items()}
+    s_bad = {k: v.copy() for k, v in base.items()}
+    s_sub = {k: v[~hit].copy() for k, v in base.items()}
+    ph_ok, led_ok, _ = oracle.step(s_ok, f_ok, cfg.dt, 5, 2, **kw)
+    ph_bad, led_bad, det = oracle.step(s_bad, f_bad, cfg.dt, 5, 2, detail=True, **kw)
+    _, led_sub, _ = oracle.step(s_sub, f_ok, cfg.dt, 5, 2, **kw)
+    p_bad = np.stack([s_bad[k] for k in ("px", "py", "pz")], 1)
+    assert np.array_equal(~np.isfinite(p_bad).all(1), hit)
+    assert np.all(det["heff"][hit] == 0) and np.all(det["chi"][hit] == 0)
+    for k in ("x", "y", "z", "px", "py", "pz"):
+        assert np.array_equal(s_bad[k][~hit], s_ok[k][~hit])
+    assert not np.isin(ph_bad["parent"], base["id"][hit]).any()
+    keep = ~np.isin(ph_ok["parent"], base["id"][hit])
+    assert ph_bad["eps"].size == keep.sum() > 0
+    assert np.array_equal(ph_bad["eps"], ph_ok["eps"][keep])
+    assert np.all(np.isfinite(led_bad))
+    np.testing.assert_allclose(led_bad, led_sub, rtol=1e-12, atol=0)
