@@ -387,6 +387,26 @@ int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_f32 *fields
                             const sr_params *prm, const sr_table *tab, const sr_chunking *chunks,
                             sr_photon_buf *photons, sr_ledger *ledger, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): sr_gather_push_emit followed by
+ * sr_ledger_reduce into *ledger_row (device double[SR_LEDGER_COLS]), with the
+ * step's partial ledger rows kept in a device array inside the library instead
+ * of a caller workspace.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call).  Results are those of the two calls with the same
+ * arguments; the condition bits are ORed into *status (device uint32, zeroed
+ * by the caller).  At most SR_NOALLOC_MAX_CHUNKS chunks (2^26 particles with
+ * uniform chunks): SR_E_UNSUPPORTED above.  The array (about 21 MB) is held
+ * by every device the library runs on until the process ends; all calls on
+ * one device share it, so calls that overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.  stream must belong
+ * to the current device (SR_E_INVAL otherwise). */
+#define SR_NOALLOC_MAX_CHUNKS (1 << 20)
+int sr_gather_push_emit_noalloc(sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                                const sr_grid *grid, double dt, uint64_t seed, uint64_t step,
+                                const sr_params *prm, const sr_table *tab,
+                                const sr_chunking *chunks, sr_photon_buf *photons,
+                                double *ledger_row, uint32_t *status, void *stream);
+
 /* Sum the partial rows a step over n_chunks chunks wrote into ledger->rows[row]
  * (FP64, fixed order, so the result is reproducible; column SR_LED_CHI_MAX is
  * a maximum) and OR the step's condition bits into *ledger->status.  The

@@ -18,6 +18,7 @@ SR_W_PHOTON_OVERFLOW, SR_W_RECOIL_CLAMP, SR_W_NONFINITE, SR_W_CFL = 1, 2, 4, 8
  SR_LED_WEIGHT, SR_LED_CHI_MAX) = range(8)
 SR_LEDGER_COLS = 8
 SR_CHUNK = 64
+SR_NOALLOC_MAX_CHUNKS = 1 << 20
 SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP, SR_SAMPLER_QUANTUM = 0, 1, 2, 3
 SR_RECOIL_NONE, SR_RECOIL_PHOTON, SR_RECOIL_LL = 0, 1, 2
 SR_DN_WEIGHT, SR_DN_CLAMP = 0, 1
@@ -110,6 +111,10 @@ SIGNATURES = {
                                C.POINTER(Params), _P, _P, _P, _P]),
     "sr_eval_push_f64": (C.c_int, [C.POINTER(Particles64), C.POINTER(Fields32), C.POINTER(Grid),
                                    _D, C.POINTER(Params), _P, _P, _P, _P]),
+    "sr_gather_push_emit_noalloc": (C.c_int, [C.POINTER(Particles32), C.POINTER(Fields32),
+                                              C.POINTER(Grid), _D, _U64, _U64,
+                                              C.POINTER(Params), _P, C.POINTER(Chunking),
+                                              C.POINTER(PhotonBuf), _P, _P, _P]),
     "sr_ledger_reduce": (C.c_int, [C.POINTER(Ledger), _I64, _I64, _P]),
     "sr_ledger_partials": (C.c_int64, [_I64]),
     "sr_energy_ledger": (C.c_int, [C.POINTER(Ledger), _I64, _P, _P]),

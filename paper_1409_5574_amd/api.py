@@ -470,6 +470,31 @@ def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: 
         ledger_reduce(ledger, cs.n_chunks, row, ls)
 
 
+def gather_push_emit_noalloc(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float,
+                             seed: int, step: int, prm: L.Params, table: Table,
+                             photons: PhotonBuffer, ledger_row: torch.Tensor,
+                             status: torch.Tensor, start: torch.Tensor | None = None):
+    """sr_gather_push_emit_noalloc: one emission step and its ledger row
+    (device float64[SR_LEDGER_COLS]); the step's partial rows live in the
+    library's own device array, so the call allocates nothing."""
+    if parts.dtype != torch.float32:
+        raise ValueError("the no-allocation step exists for the FP32 path only")
+    if ledger_row.dtype != torch.float64 or ledger_row.numel() < L.SR_LEDGER_COLS:
+        raise ValueError("ledger_row: a device float64 tensor of SR_LEDGER_COLS values")
+    if status.numel() < 1 or status.element_size() != 4:
+        raise ValueError("status: a device 32-bit word")
+    cs = L.Chunking()
+    cs.n_chunks = n_chunks_uniform(parts.n) if start is None else start.numel() - 1
+    cs.start = None if start is None else start.data_ptr()
+    ps = parts.struct()
+    fs = fields.struct() if fields is not None else None
+    phs = photons.struct()
+    L.check(lib().sr_gather_push_emit_noalloc(
+        C.byref(ps), C.byref(fs) if fs is not None else None, C.byref(grid), float(dt),
+        seed & 0xFFFFFFFFFFFFFFFF, int(step), C.byref(prm), table.handle, C.byref(cs),
+        C.byref(phs), _ptr(ledger_row), _ptr(status), _stream()), "sr_gather_push_emit_noalloc")
+
+
 def eval_push(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float, hbar_n: float,
               alpha: float) -> dict:
     """H_eff, chi and the mean gamma of one push of every particle (the step's

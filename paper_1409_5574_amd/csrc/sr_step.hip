@@ -17,6 +17,8 @@
 #include <math.h>
 #include <stddef.h>
 
+#include <mutex>
+
 #include <hip/hip_ext.h>
 
 #include "sr_hist.hpp"
@@ -1180,6 +1182,37 @@ int launch_eval_push(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *g
     return SR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the step that allocates nothing (sr_gather_push_emit_noalloc):
+// the partial ledger rows of one step and the first level of their reduction,
+// for up to kNoallocMaxChunks chunks, in one file-scope device array.  Each
+// device holds its own copy at its own address; host code reaches it only
+// through the address hipGetSymbolAddress gives on that device.
+constexpr int64_t kNoallocMaxChunks = SR_NOALLOC_MAX_CHUNKS;
+constexpr int64_t kNoallocDoubles =
+    ((kNoallocMaxChunks + kWaves - 1) / kWaves + kReduceL1Blocks + 1) * kPartCols;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+std::mutex g_scratch_mu;
+double *g_scratch[kNoallocMaxDevices] = {};
+
+// The device address of `scratch` on the current device, taken once per
+// device (with that device current) and kept.
+int scratch_on_current_device(double **out) {
+    int dev = -1;
+    SR_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return SR_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SR_E_HIP;
+        g_scratch[dev] = (double *)ptr;
+    }
+    *out = g_scratch[dev];
+    return SR_OK;
+}
+
 }  // namespace
 }  // namespace sr
 
@@ -1242,6 +1275,40 @@ extern "C" int sr_gather_push_emit_f64(sr_particles_f64 *parts, const sr_fields_
                                        sr_ledger *ledger, void *stream) {
     return launch_step<double>(parts, fields, grid, dt, seed, step, prm, tab, chunks, photons,
                                ledger, stream);
+}
+
+extern "C" int sr_gather_push_emit_noalloc(sr_particles_f32 *parts, const sr_fields_f32 *fields,
+                                           const sr_grid *grid, double dt, uint64_t seed,
+                                           uint64_t step, const sr_params *prm,
+                                           const sr_table *tab, const sr_chunking *chunks,
+                                           sr_photon_buf *photons, double *ledger_row,
+                                           uint32_t *status, void *stream) {
+    if (!parts || !chunks || !ledger_row || !status || parts->n < 0) return SR_E_INVAL;
+    const int64_t n_chunks =
+        chunks->start ? chunks->n_chunks : (parts->n + kChunk - 1) / kChunk;
+    if (n_chunks < 0) return SR_E_INVAL;
+    if (n_chunks > kNoallocMaxChunks) return SR_E_UNSUPPORTED;
+    // the scratch belongs to the current device; the stream must run there
+    if (stream) {
+        int cur = -1;
+        hipDevice_t sdev = -1;
+        SR_HIP_CHECK(hipGetDevice(&cur));
+        SR_HIP_CHECK(hipStreamGetDevice((hipStream_t)stream, &sdev));
+        if ((int)sdev != cur) return SR_E_INVAL;
+    }
+    double *ws = nullptr;
+    const int rs = scratch_on_current_device(&ws);
+    if (rs != SR_OK) return rs;
+    sr_ledger led;
+    led.rows = ledger_row;
+    led.n_rows = 1;
+    led.partials = ws;
+    led.partials_len = kNoallocDoubles;
+    led.status = status;
+    const int rc = launch_step<float>(parts, fields, grid, dt, seed, step, prm, tab, chunks,
+                                      photons, &led, stream);
+    if (rc != SR_OK) return rc;
+    return reduce_ledger(&led, n_chunks, 0, (hipStream_t)stream);
 }
 
 extern "C" int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row,
