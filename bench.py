@@ -1,19 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the synchrotron-emission step on one MI355X.
 
-A step is one pass of the whole hot path over the particle ensemble:
-  standing-wave field at t^n on the Yee grid (stand-in for the PIC field solve),
+Headline (default --config c3): the 3D workload the metric is quoted on,
+512^3 Yee grid, standing wave a0 = 500, 2^24 electrons in a 2-lambda slab,
+K = 8 trials per particle and step, kinematic cut, S-proposal sampler (the
+paper's scheme).  A step is one pass of the hot path over the ensemble:
   tile sort of the particles every --sort-every steps (gather locality),
   gather + Boris + H_eff + Monte-Carlo emission + photon append + recoil +
-  position push (sr_gather_push_emit), the FP64 energy ledger reduction, and
-  the photon-spectrum histogram that drains the photon buffer.
-The K timed steps run twice from the same warm state: once as eager launches,
-with HIP events recorded by every emission-kernel dispatch on its stream (the
-roofline figure), and once captured into a HIP graph and run as one graph
-launch.  `value` is particle-steps/s of the graph pass (wall clock between
-device synchronisations; --no-graph reports the eager pass); both passes are
-in `timing`.  The CPU baseline is the FP64 oracle on a bounded sample of the
-same workload.
+  position push (sr_gather_push_emit), the FP64 energy ledger reduction and
+  the photon-spectrum histogram (sr_step_epilogue).
+Each step reads its own field snapshot E, B(t^n), written into HBM before the
+timed region (the fields are an input of the step, as the particles are); a
+separate pass that also rewrites the field every step gives the end-to-end
+figure with the field refresh.  The K timed steps run twice from the same warm
+state: once as eager launches with HIP events recorded by every emission-kernel
+dispatch on its stream (the roofline figure: median per dispatch), once
+captured into a HIP graph and run as one graph launch (`value`).
+
+Other legs in the same line: the plain-vs-surrogate sampler comparison on the
+same 3D workload (the learned sampler of the metric), the uniform-field
+workload (16 384 electrons, 1000 steps), the 64M-electron precision-stress
+workload, the 2D workload, and the closed PIC loop.  The CPU baseline is the
+FP64 oracle on a bounded sample of the headline workload.
 
 Prints one JSON line.
 """
@@ -37,16 +45,19 @@ import synth  # noqa: E402
 METRIC = "particle-steps/s with emission (plain vs surrogate) at ≤1e-3 spectrum error"
 HBM_PEAK_GBS = 8000.0
 SPEC_BINS, SPEC_LO, SPEC_HI = 64, 1e-8, 1e5
-
+YEE = synth.yee_offsets()
 
 # HBM traffic of the emission kernel from hardware counters: a summary under
 # profiles/ records FETCH_SIZE and WRITE_SIZE per dispatch (scaled by a plain
 # copy of known size) together with a digest of the sources the kernel is built
 # from.  The figure is reported only while those sources are unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_emit_c2_traffic.md")
 KERNEL_SOURCES = ["paper_1409_5574_amd/csrc/sr_step.hip", "paper_1409_5574_amd/csrc/sr_common.hpp",
                   "paper_1409_5574_amd/csrc/sr_mlp.hpp", "include/sr.h",
                   "paper_1409_5574_amd/build.py"]
+
+
+def traffic_file(config: str) -> str:
+    return os.path.join(ROOT, "profiles", f"push_emit_{config}_traffic.md")
 
 
 def kernel_sources_digest() -> str:
@@ -58,11 +69,11 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def counter_traffic():
+def counter_traffic(config: str):
     """Bytes per launch from the committed counter summary, or None when there
     is none or the kernel sources changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(traffic_file(config)).read()
     except OSError:
         return None
     vals = {}
@@ -76,6 +87,16 @@ def counter_traffic():
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def photon_bytes(dim: int) -> int:
@@ -96,218 +117,377 @@ def energy_hist(eps, w, edges):
     return h
 
 
-def run(args):
+def stats_ms(ms):
+    a = np.asarray(ms, np.float64)
+    return {"median": float(np.median(a)), "mean": float(a.mean()), "min": float(a.min()),
+            "max": float(a.max()), "n": int(a.size)}
+
+
+def touched_grid_values(parts, cfg) -> int:
+    """Distinct grid values the gather of one step reads: for each of the six
+    Yee components, the union over the particles of the 2^dim nodes of its
+    cloud-in-cell stencil (periodic).  Counted on the device with torch from
+    the particles' positions (outside any timed region)."""
+    import torch
+    dim = cfg.dim
+    n = [int(v) for v in cfg.grid[:dim]]
+    total = 0
+    for c in range(6):
+        base = torch.zeros(n[::-1], device="cuda", dtype=torch.bool)
+        idx = []
+        for a in range(dim):
+            u = parts.x[a].double() / cfg.dx - YEE[c][a]
+            idx.append(torch.remainder(torch.floor(u).long(), n[a]))
+        base[tuple(idx[::-1])] = True
+        node = base.clone()
+        for s in range(1, 1 << dim):
+            shift = tuple(((s >> a) & 1) for a in range(dim))[::-1]
+            node |= torch.roll(base, shifts=shift, dims=tuple(range(dim)))
+        total += int(node.sum().item())
+        del base, node, idx
+    return total
+
+
+# ---------------------------------------------------------------- the headline
+def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
+             end_to_end: bool = True, graph: bool = True) -> dict:
+    """The whole step (sort, emission, epilogue) on a grid workload, with the
+    field of each timed step resident in HBM; see the module docstring."""
     import torch
 
     from paper_1409_5574_amd import api
     from paper_1409_5574_amd import _lib as L
 
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU (HIP device) -- none visible")
-    torch.cuda.set_device(0)
-    cfg = synth.config(args.config)
-    if cfg.dim not in (2, 3) or cfg.sampler != 0:
-        raise SystemExit(f"bench workload {args.config}: only the grid S-sampler workloads are timed")
-    n = cfg.n_particles
-    K = cfg.n_samples
-    dim = cfg.dim
+    cfg = synth.config(cfg_name)
+    n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
     grid = api.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
     ncells = int(np.prod(cfg.grid[:dim]))
-    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else \
-        ((64, 4, 1) if dim == 2 else (16, 4, 4))
-
-    # ---------------- inputs resident in HBM
+    tile = (64, 4, 1) if dim == 2 else (16, 4, 4)
     st0 = synth.gen_particles(cfg)
     parts = api.Particles.from_numpy(st0, dim=dim)
+    del st0
     alt = parts.empty_like()
     sort_work = api.sort_work(grid, tile, n)
-    fields = api.Fields(ncells=ncells)
     table = api.Table()
     photons = api.PhotonBuffer(n, cfg.photons_per_particle, dim=dim)
-    total_steps = args.warmup + args.steps + 1
-    ledger = api.LedgerBuf(total_steps, api.n_chunks_uniform(n))
     n_chunks = api.n_chunks_uniform(n)
+    total_steps = warmup + timed_steps + 1
+    ledger = api.LedgerBuf(total_steps, n_chunks)
     hist = torch.zeros(2 * SPEC_BINS, device="cuda", dtype=torch.float64)
     hwork = api.hist_work(SPEC_BINS)
     prm = api.params_struct(cfg.hbar_n, cfg.alpha, K, 0, cfg.recoil, 0, cfg.kin_cut, True)
     seed = 0xC0FFEE
-
-    api.standing_wave(fields, grid, cfg.a0, 0.0)
-    api.sort_particles(parts, alt, grid, tile, sort_work)
-    parts, alt = alt, parts
+    stream = torch.cuda.current_stream()
+    base = warmup + 1
+    # one field buffer for the warm-up steps (and the end-to-end pass), then one
+    # snapshot per timed step, all written before the timed region
+    work_fields = api.Fields(ncells=ncells)
+    snaps = []
+    for j in range(timed_steps):
+        f = api.Fields(ncells=ncells)
+        api.standing_wave(f, grid, cfg.a0, (base + j) * cfg.dt)
+        snaps.append(f)
     torch.cuda.synchronize()
 
-    structs = {id(parts): api.make_structs(parts, fields, photons, ledger),
-               id(alt): api.make_structs(alt, fields, photons, ledger)}
-    stream = torch.cuda.current_stream()
-    # events the emission kernel's dispatch records at its start and end (they
-    # are recorded once here so that they exist)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    for a_, b_ in ev:
-        a_.record(stream)
-        b_.record(stream)
-    ev_wave = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+    structs = {}
 
-    def one_step(i, timed_idx=None):
+    def st_for(p, f):
+        key = (id(p), id(f))
+        if key not in structs:
+            structs[key] = api.make_structs(p, f, photons, ledger)
+        return structs[key]
+
+    def one_step(i, fields, ev=None, refresh=False):
         nonlocal parts, alt
-        t = i * cfg.dt
-        if timed_idx is not None:
-            ev_wave[timed_idx][0].record(stream)
-        api.standing_wave(fields, grid, cfg.a0, t)
-        if timed_idx is not None:
-            ev_wave[timed_idx][1].record(stream)
+        if refresh:
+            api.standing_wave(fields, grid, cfg.a0, i * cfg.dt)
         if args.sort_every > 0 and i % args.sort_every == 0:
             api.sort_particles(parts, alt, grid, tile, sort_work)
             parts, alt = alt, parts
-        s = structs[id(parts)]
+        s = st_for(parts, fields)
         api.gather_push_emit(parts, fields, grid, cfg.dt, seed, i, prm, table, photons, ledger,
-                             None, structs=s,
-                             events=ev[timed_idx] if timed_idx is not None else None)
+                             None, structs=s, events=ev)
         api.step_epilogue(ledger, n_chunks, i, photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist, hwork,
                           ls=s[4])
 
-    for i in range(1, args.warmup + 1):
-        one_step(i)
+    api.sort_particles(parts, alt, grid, tile, sort_work)
+    parts, alt = alt, parts
+    for i in range(1, warmup + 1):
+        one_step(i, work_fields, refresh=True)
     torch.cuda.synchronize()
 
-    # ---------------- spectrum check, kept for the CPU leg: the first timed step
-    # (index warmup+1) run once on a copy of the warm state, its photons of the
-    # sampled ids, and those particles' state before the step
+    # the warm state, restored before every timed pass
+    snap_bufs = (parts, alt)
+    snap = [None if t is None else t.clone() for t in parts.x + parts.p + [parts.w, parts.id]]
+
+    def restore():
+        nonlocal parts, alt
+        parts, alt = snap_bufs
+        for dst, src in zip(parts.x + parts.p + [parts.w, parts.id], snap):
+            if dst is not None:
+                dst.copy_(src)
+
+    # algorithmic grid bytes of the first timed step: the grid values its
+    # particles' stencils read
+    touched = touched_grid_values(parts, cfg)
+
+    # ---------------- spectrum check and CPU-leg state: the first timed step run
+    # once on a copy, its photons of the sampled ids and their state before it
     check = None
-    if not args.no_cpu_baseline:
-        i_chk = args.warmup + 1
-        api.standing_wave(fields, grid, cfg.a0, i_chk * cfg.dt)
+    if with_cpu:
         probe = parts.empty_like()
         for a, b in zip(probe.x + probe.p + [probe.w, probe.id], parts.x + parts.p + [parts.w, parts.id]):
             if a is not None:
                 a.copy_(b)
         sel = torch.nonzero(parts.id.view(torch.int32) < args.cpu_sample).squeeze(1)
-        order = torch.argsort(parts.id.view(torch.int32)[sel])
-        sel = sel[order]
+        sel = sel[torch.argsort(parts.id.view(torch.int32)[sel])]
         state = {k: (t[sel].cpu().numpy() if t is not None else None)
                  for k, t in zip(("x", "y", "z", "px", "py", "pz", "w"), parts.x + parts.p + [parts.w])}
         state["id"] = parts.id[sel].cpu().numpy().view(np.uint32)
-        api.gather_push_emit(probe, fields, grid, cfg.dt, seed, i_chk, prm, table, photons, ledger, 0)
+        api.gather_push_emit(probe, snaps[0], grid, cfg.dt, seed, base, prm, table, photons, ledger, 0)
         torch.cuda.synchronize()
         ph = photons.gather(n)
         keep = ph["parent"] < args.cpu_sample
         check = {"eps": ph["eps"][keep], "w": ph["w"][keep], "count": int(keep.sum()),
-                 "state": state, "step": i_chk}
-        del probe, sel, order
+                 "state": state, "step": base}
+        del probe, sel
         torch.cuda.synchronize()
-    # the warm state, restored before the graph pass so that both timed passes
-    # run the same K steps from the same particles
-    snap_bufs = (parts, alt)
-    snap = [None if t is None else t.clone() for t in parts.x + parts.p + [parts.w, parts.id]]
 
     # ---------------- timed pass 1, eager launches: HIP events recorded by every
-    # emission-kernel launch (the roofline) and every field refresh
+    # emission-kernel dispatch on its stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(timed_steps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        b_.record(stream)
+    restore()
     hist.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in range(args.steps):
-        one_step(args.warmup + 1 + j, j)
+    for j in range(timed_steps):
+        one_step(base + j, snaps[j], ev=ev[j])
     torch.cuda.synchronize()
     wall_eager = time.perf_counter() - t0
-    wall = wall_eager
+    rows = ledger.rows.cpu().numpy()[base: base + timed_steps].copy()
+    k_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    status = ledger.read_status()
 
-    # ---------------- timed pass 2: the next K steps captured once into a HIP
-    # graph (the same kernels and arguments the eager loop launches, without
-    # the per-launch host overhead) and run as one graph launch
+    # ---------------- timed pass 2: the same K steps captured into one HIP graph
+    wall = wall_eager
     graph_info = None
-    rows = ledger.rows.cpu().numpy()[args.warmup + 1: args.warmup + 1 + args.steps]
-    if not args.no_graph:
-        parts, alt = snap_bufs
-        for dst, src in zip(parts.x + parts.p + [parts.w, parts.id], snap):
-            if dst is not None:
-                dst.copy_(src)
-        base = args.warmup + 1
+    if graph:
+        restore()
+        hist.zero_()
         g = torch.cuda.CUDAGraph()
         cap = torch.cuda.Stream()
         cap.wait_stream(torch.cuda.current_stream())
         with torch.cuda.graph(g, stream=cap):
-            for j in range(args.steps):
-                one_step(base + j)
+            for j in range(timed_steps):
+                one_step(base + j, snaps[j])
+        torch.cuda.synchronize()
+        restore()
+        hist.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.replay()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        rows_g = ledger.rows.cpu().numpy()[base: base + args.steps]
-        graph_info = {"steps": [base, base + args.steps - 1], "ms_per_step": wall * 1e3 / args.steps,
-                      "photons_per_step": float(rows_g[:, L.SR_LED_PHOTONS].mean()),
+        rows_g = ledger.rows.cpu().numpy()[base: base + timed_steps]
+        graph_info = {"steps": [base, base + timed_steps - 1], "ms_per_step": wall * 1e3 / timed_steps,
                       "ledger_rel_diff_vs_eager": float(np.max(np.abs(rows_g - rows) /
                                                                np.maximum(np.abs(rows), 1e-300)))}
         del g
-    del snap
 
-    k1_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    k9_ms = np.array([a.elapsed_time(b) for a, b in ev_wave])
-    status = ledger.read_status()
-    photons_per_step = rows[:, L.SR_LED_PHOTONS].mean()
+    # ---------------- pass 3: the same steps with the field rewritten every step
+    # (the standing-wave refresh standing in for a PIC field solve), as a graph
+    e2e = None
+    if end_to_end and graph:
+        restore()
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=cap):
+            for j in range(timed_steps):
+                one_step(base + j, work_fields, refresh=True)
+        torch.cuda.synchronize()
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        w3 = time.perf_counter() - t0
+        e2e = {"particle_steps_per_s": n * timed_steps / w3, "ms_per_step": w3 * 1e3 / timed_steps,
+               "field_refresh_bytes_per_step": 24 * ncells}
+        del g
+
+    photons_per_step = float(rows[:, L.SR_LED_PHOTONS].mean())
     rd, wr = particle_bytes(dim)
-    # particles read + written, every grid value once, photon records, segment
-    # counts and the per-block (4 chunks) ledger partial rows
-    bytes_per_launch = (n * (rd + wr) + 6 * 4 * ncells + photons_per_step * photon_bytes(dim)
-                        + n_chunks * 4 + -(-n_chunks // 4) * 8 * L.SR_LEDGER_COLS)
-    k1_mean = float(k1_ms.mean())
-    achieved = bytes_per_launch / (k1_mean * 1e-3) / 1e9
-
-    value = n * args.steps / wall
+    # particles read + written, the grid values the stencils need, photon
+    # records, segment counts and the per-block (4 chunks) ledger partial rows
+    bytes_per_launch = (n * (rd + wr) + 4 * touched + photons_per_step * photon_bytes(dim)
+                        + n_chunks * 4 + -(-n_chunks // 4) * 8 * (L.SR_LEDGER_COLS + 2))
+    kmed = float(np.median(k_ms))
+    achieved = bytes_per_launch / (kmed * 1e-3) / 1e9
     out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {cfg.grid[0]}x{cfg.grid[1]}"
-                               + (f"x{cfg.grid[2]}" if dim == 3 else "")
-                               + f" Yee grid, standing wave a0={cfg.a0:g}, {n} electrons, "
-                               f"K={K} trials/step, photon buffer {cfg.photons_per_particle}/particle, "
-                               f"S-proposal sampler",
+        "value": n * timed_steps / wall,
+        "ms_per_step": wall * 1e3 / timed_steps,
+        "eager": {"value": n * timed_steps / wall_eager, "ms_per_step": wall_eager * 1e3 / timed_steps},
+        "hip_graph": graph_info,
+        "end_to_end_with_field_refresh": e2e,
+        "config": {"workload": f"{cfg.name}: {'x'.join(str(v) for v in cfg.grid[:dim])} Yee grid, "
+                               f"standing wave a0={cfg.a0:g}, {n} electrons"
+                               + (" in a 2-lambda slab" if cfg.slab else "")
+                               + f", K={K} trials/step, photon buffer {cfg.photons_per_particle}/particle, "
+                               f"S-proposal sampler" + (", kinematic cut" if cfg.kin_cut else ""),
                    "particles": n, "grid": list(cfg.grid[:dim]), "trials_per_step": K,
-                   "dt": cfg.dt, "sort_every": args.sort_every, "tile": list(tile[:dim])},
+                   "dt": cfg.dt, "sort_every": args.sort_every, "tile": list(tile[:dim]),
+                   "fields": "one snapshot per timed step, resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic() if args.config == "c2" else None,
+                     "traffic": counter_traffic(cfg_name),
                      "kernel": "push_emit_kernel<float,%d,%d,0,false>" % (dim, 1 if K <= 1 else K),
-                     "kernel_ms": k1_mean, "algorithmic_bytes_per_launch": bytes_per_launch},
-        "push_emit_particle_steps_per_s": n / (k1_mean * 1e-3),
-        "field_refresh_ms": float(k9_ms.mean()),
-        "photons_per_step": float(photons_per_step),
+                     "kernel_ms": kmed, "kernel_ms_stats": stats_ms(k_ms),
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "bytes": {"particles": n * (rd + wr), "grid_values_read": 4 * touched,
+                               "grid_values": touched, "grid_total": 24 * ncells,
+                               "photons": photons_per_step * photon_bytes(dim),
+                               "segment_counts_and_ledger_partials":
+                                   n_chunks * 4 + -(-n_chunks // 4) * 8 * (L.SR_LEDGER_COLS + 2)},
+                     "kernel_ms_from": "median of the HIP events each emission-kernel dispatch "
+                                       "records at its start and end (hipExtLaunchKernel), on its "
+                                       "stream, over the eager pass"},
+        "push_emit_particle_steps_per_s": n / (kmed * 1e-3),
+        "photons_per_step": photons_per_step,
         "ledger_emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300)),
         "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
         "status_bits": int(status),
-        "timing": {"value_from": "hip_graph" if graph_info else "eager",
-                   "eager": {"value": n * args.steps / wall_eager,
-                             "ms_per_step": wall_eager * 1e3 / args.steps,
-                             "steps": [args.warmup + 1, args.warmup + args.steps]},
-                   "note": "both passes run the same K steps from the same warm state",
-                   "hip_graph": graph_info,
-                   "kernel_ms_from": "HIP events recorded by each emission-kernel dispatch "
-                                     "of the eager pass (hipExtLaunchKernel start/stop), on "
-                                     "its stream"},
     }
     if check is not None:
         out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, check, seed, args)
-    if not args.no_samplers or not args.no_pic:
-        del parts, alt, photons, fields, sort_work
-        torch.cuda.empty_cache()
-    if not args.no_samplers:
-        out["samplers"] = samplers_leg(args)
-        torch.cuda.empty_cache()
-    if not args.no_pic:
-        out["pic_loop"] = pic_leg(args)
+    del parts, alt, photons, snaps, work_fields, sort_work, snap
+    table.free()
+    torch.cuda.empty_cache()
     return out
+
+
+# ---------------------------------------------------------------- kernel-only legs
+def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10) -> dict:
+    """Emission-kernel time (median of per-dispatch HIP events) on a grid
+    workload, sorted every `sort_every` steps; the field of each step is
+    written before its emission launch."""
+    import torch
+
+    from paper_1409_5574_amd import api
+    from paper_1409_5574_amd import _lib as L
+
+    cfg = synth.config(cfg_name)
+    n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
+    grid = api.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
+    ncells = int(np.prod(cfg.grid[:dim]))
+    tile = (64, 4, 1) if dim == 2 else (16, 4, 4)
+    st0 = synth.gen_particles(cfg)
+    parts = api.Particles.from_numpy(st0, dim=dim)
+    del st0
+    alt = parts.empty_like()
+    sw = api.sort_work(grid, tile, n)
+    table = api.Table()
+    photons = api.PhotonBuffer(n, cfg.photons_per_particle, dim=dim)
+    n_chunks = api.n_chunks_uniform(n)
+    ledger = api.LedgerBuf(warmup + steps + 1, n_chunks)
+    fields = api.Fields(ncells=ncells)
+    prm = api.params_struct(cfg.hbar_n, cfg.alpha, K, 0, cfg.recoil, 0, cfg.kin_cut, True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        b_.record(stream)
+    touched = None
+    for i in range(warmup + steps):
+        api.standing_wave(fields, grid, cfg.a0, i * cfg.dt)
+        if i % sort_every == 0:
+            api.sort_particles(parts, alt, grid, tile, sw)
+            parts, alt = alt, parts
+        if i == warmup:
+            torch.cuda.synchronize()
+            touched = touched_grid_values(parts, cfg)
+        j = i - warmup
+        api.gather_push_emit(parts, fields, grid, cfg.dt, 0xC5, i, prm, table, photons, ledger, i,
+                             events=ev[j] if j >= 0 else None)
+    torch.cuda.synchronize()
+    k_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    rows = ledger.rows.cpu().numpy()[warmup: warmup + steps]
+    ph = float(rows[:, L.SR_LED_PHOTONS].mean())
+    rd, wr = particle_bytes(dim)
+    by = (n * (rd + wr) + 4 * touched + ph * photon_bytes(dim) + n_chunks * 4
+          + -(-n_chunks // 4) * 8 * (L.SR_LEDGER_COLS + 2))
+    kmed = float(np.median(k_ms))
+    out = {"workload": f"{cfg.name}: {'x'.join(str(v) for v in cfg.grid[:dim])} Yee grid, standing "
+                       f"wave a0={cfg.a0:g}, {n} electrons, K={K}, {steps} timed steps after {warmup}, "
+                       f"sort every {sort_every}",
+           "particle_steps_per_s": n / (kmed * 1e-3),
+           "kernel": "push_emit_kernel<float,%d,%d,0,false>" % (dim, 1 if K <= 1 else K),
+           "kernel_ms": kmed, "kernel_ms_stats": stats_ms(k_ms),
+           "algorithmic_bytes_per_launch": by,
+           "grid_values_read_bytes": 4 * touched,
+           "roofline_frac": by / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "traffic": counter_traffic(cfg_name),
+           "photons_per_step": ph,
+           "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
+           "status_bits": int(ledger.read_status())}
+    del parts, alt, photons, fields, sw
+    table.free()
+    torch.cuda.empty_cache()
+    return out
+
+
+def c1_leg(args) -> dict:
+    """The uniform-field workload: 16 384 electrons in B = 1 (1e5 T), 1000 steps
+    of dt = 0.01 gyro-periods, K = 1, photon recoil; the whole run timed."""
+    import torch
+
+    from paper_1409_5574_amd import api
+    from paper_1409_5574_amd import _lib as L
+
+    cfg = synth.config("c1")
+    n, steps = cfg.n_particles, cfg.steps
+    st = synth.gen_particles(cfg)
+    parts = api.Particles.from_numpy(st, dim=0)
+    parts.x = [None, None, None]
+    grid = api.grid_struct(0, b0=cfg.b0)
+    table = api.Table()
+    photons = api.PhotonBuffer(n, 1, dim=3)
+    ledger = api.LedgerBuf(steps, api.n_chunks_uniform(n))
+    prm = api.params_struct(cfg.hbar_n, cfg.alpha, 1, recoil=cfg.recoil, push_position=False)
+    s = api.make_structs(parts, None, photons, ledger)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        for i in range(steps):
+            api.gather_push_emit(parts, None, grid, cfg.dt, 0xC1, i, prm, table, photons, ledger, i,
+                                 structs=s)
+
+    run()                       # warm-up pass (the state moves on; timing only)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(stream)
+    with torch.cuda.graph(g, stream=cap):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rows = ledger.rows.cpu().numpy()
+    del g
+    table.free()
+    return {"workload": f"{cfg.name}: {n} electrons, uniform B = 1 (1e5 T), {steps} steps, K=1, "
+                        f"photon recoil, as one HIP graph",
+            "particle_steps_per_s": n * steps / wall, "ms_per_run": wall * 1e3,
+            "us_per_step": wall * 1e6 / steps,
+            "photons_per_run": float(rows[:, L.SR_LED_PHOTONS].sum()),
+            "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300))}
 
 
 def pic_leg(args):
@@ -388,13 +568,15 @@ def pic_leg(args):
     per = {k: (float(np.sum(v)) / steps if v else 0.0) for k, v in times.items()}
     field_bytes = 120.0 * cells        # B half: 36 B, E: 48 B, B half: 36 B per cell
     f_ms = per["field"]
+    table.free()
     return {"workload": f"{cfg.name}: {cfg.grid[0]}x{cfg.grid[1]}x{cfg.grid[2]} Yee grid of lambda/32, "
                         f"{n} electrons (2 per cell, {synth.C6_DENSITY} n_c, 1 keV), a0={cfg.a0:g} "
-                        f"pulse along x, K={cfg.n_samples}, kinematic cut, {steps} timed steps "
-                        f"after {warm}, sort tile {tile} every 10 steps",
+                        f"pulse along x, K={cfg.n_samples}, kinematic cut, {steps} timed steps after {warm}, "
+                        f"sort tile {tile} every 10 steps",
             "ms_per_step": total_ms,
             "particle_steps_per_s": n / (total_ms * 1e-3),
             "breakdown_ms_per_step": per,
+            "emission_ms_median": float(np.median(times["emission"])) if times["emission"] else None,
             "field_step": {"ms": f_ms, "algorithmic_bytes": field_bytes,
                            "GB_per_s": field_bytes / (f_ms * 1e-3) / 1e9 if f_ms > 0 else None,
                            "frac_of_8TBps": field_bytes / (f_ms * 1e-3) / 8e12 if f_ms > 0 else None},
@@ -434,7 +616,7 @@ def samplers_leg(args):
 
     t0 = time.perf_counter()
     net = api.Mlp(api.mlp_init(11))
-    net.train(table, steps=args.mlp_steps, batch=1 << 16, lr=2e-3)
+    net.train(table, steps=args.mlp_steps, batch=1 << 16, lr=2e-3, kin_cut=cfg.kin_cut)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     err = net.judge(table, kin_cut=cfg.kin_cut)
@@ -463,7 +645,7 @@ def samplers_leg(args):
     res, hists = {}, {}
     for name, sampler, fb in variants:
         if fb is not None:
-            net.fallback.copy_(fb)
+            net.set_fallback(fb)
         prm = api.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, cfg.recoil, 0, cfg.kin_cut,
                                 True, mlp=net if sampler == 2 else None)
         for a, b in zip(parts.x + parts.p + [parts.w, parts.id], init.x + init.p + [init.w, init.id]):
@@ -473,14 +655,15 @@ def samplers_leg(args):
         structs = api.make_structs(parts, fields, photons, ledger)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
+        for a_, b_ in ev:
+            a_.record(stream)
+            b_.record(stream)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for i in range(steps):
             api.standing_wave(fields, grid, cfg.a0, i * cfg.dt)
-            ev[i][0].record(stream)
             api.gather_push_emit(parts, fields, grid, cfg.dt, seed, i, prm, table, photons,
-                                 ledger, None, structs=structs)
-            ev[i][1].record(stream)
+                                 ledger, None, structs=structs, events=ev[i])
             api.step_epilogue(ledger, n_chunks, i, photons, n, SPEC_LO, SPEC_HI, SPEC_BINS, hist,
                               hwork, ls=structs[4])
         torch.cuda.synchronize()
@@ -488,8 +671,9 @@ def samplers_leg(args):
         k_ms = np.array([a.elapsed_time(b) for a, b in ev])[1:]
         rows = ledger.rows.cpu().numpy()
         hists[name] = hist[:SPEC_BINS].cpu().numpy()
-        res[name] = {"particle_steps_per_s": n / (float(k_ms.mean()) * 1e-3),
-                     "kernel_ms": float(k_ms.mean()),
+        res[name] = {"particle_steps_per_s": n / (float(np.median(k_ms)) * 1e-3),
+                     "kernel_ms": float(np.median(k_ms)),
+                     "kernel_ms_stats": stats_ms(k_ms),
                      "step_ms": wall * 1e3 / steps,
                      "photons_per_step": float(rows[:, L.SR_LED_PHOTONS].mean()),
                      "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300))}
@@ -501,6 +685,7 @@ def samplers_leg(args):
     for name in res:
         res[name]["speedup_vs_s_proposal"] = res[name]["particle_steps_per_s"] / base
     net_bins = err <= 1e-3
+    table.free()
     return {"workload": f"{cfg.name}: 512^3 Yee grid, standing wave a0={cfg.a0:g}, {n} electrons "
                         f"in a 2-lambda slab, K={K}, kinematic cut, {steps} steps per sampler",
             "results": res,
@@ -508,7 +693,8 @@ def samplers_leg(args):
                     "bins_on_network": int(net_bins.sum()), "bins": int(err.size),
                     "judge_error_max_on_network": float(err[net_bins].max()) if net_bins.any()
                     else None,
-                    "judge_error_median": float(np.median(err))},
+                    "judge_error_median": float(np.median(err)),
+                    "judge_errors": [float(v) for v in err]},
             "spectrum": f"{SPEC_BINS} log bins of photon energy in [{SPEC_LO:g}, {SPEC_HI:g}] mc^2, "
                         f"energy-weighted, summed over the steps"}
 
@@ -516,7 +702,11 @@ def samplers_leg(args):
 def cpu_leg(cfg, check, seed, args):
     """The FP64 oracle on the first `cpu_sample` ids, started from their warm GPU
     state before the first timed step: compared on that step with the GPU's
-    photons of those ids, then timed for about --cpu-seconds of further steps."""
+    photons of those ids, then timed for about --cpu-seconds of further steps.
+    The standing wave is uniform in y and z, so the oracle is given the same x
+    profile on a grid of two cells along y and z (every particle sees the same
+    field values as on the full grid, and the host need not write a full grid
+    per step)."""
     from oracle import oracle as O
 
     m = args.cpu_sample
@@ -528,10 +718,12 @@ def cpu_leg(cfg, check, seed, args):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     kw = dict(hbar_n=cfg.hbar_n, alpha=cfg.alpha, n_samples=cfg.n_samples, recoil=cfg.recoil,
               kin_cut=cfg.kin_cut, threads=threads)
+    thin = (cfg.grid[0], 2, 2 if cfg.dim == 3 else 1)
+    cthin = synth.config(cfg.name[:2], grid=thin)
 
     def field_at_step(i):
-        E, B = synth.standing_wave_grid(cfg, i * cfg.dt)
-        return O.Field(cfg.dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=E, B=B)
+        E, B = synth.standing_wave_grid(cthin, i * cfg.dt)
+        return O.Field(cfg.dim, n=thin, dx=(cfg.dx,) * 3, E=E, B=B)
 
     f0 = field_at_step(i0)
     t0 = time.perf_counter()
@@ -552,23 +744,87 @@ def cpu_leg(cfg, check, seed, args):
     err = float(np.abs(h_g - h_o).sum() / max(h_o.sum(), 1e-300))
     base = {"value": m * steps / spent, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{m} of the {cfg.n_particles} electrons (ids 0..{m - 1}) from the warm "
-                      f"state at step {i0}, {steps} steps, same grid and fields; FP64 C oracle "
-                      f"with OpenMP, {spent:.1f} s"}
+                      f"state at step {i0}, {steps} steps, K={cfg.n_samples}, same field values "
+                      f"(x profile on a {thin[0]}x{thin[1]}x{thin[2]} grid); FP64 C oracle with "
+                      f"OpenMP on {threads} threads, {spent:.1f} s"}
     spec = {"step": i0, "particles": m, "photons_gpu": check["count"],
             "photons_oracle": int(ph0["eps"].size), "energy_spectrum_error": err,
             "bins": f"{SPEC_BINS} log bins of photon energy in [{SPEC_LO:g}, {SPEC_HI:g}] mc^2"}
     return base, spec
 
 
+def run(args):
+    import torch
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU (HIP device) -- none visible")
+    torch.cuda.set_device(0)
+    cfg = synth.config(args.config)
+    if cfg.dim not in (2, 3) or cfg.sampler != 0:
+        raise SystemExit(f"bench workload {args.config}: the headline is a grid workload with the "
+                         "S-proposal sampler (the learned sampler runs in the samplers leg)")
+    head = grid_leg(args, args.config, args.steps, args.warmup, not args.no_cpu_baseline,
+                    graph=not args.no_graph)
+    n = cfg.n_particles
+    out = {
+        "metric": METRIC,
+        "value": head.pop("value"),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": head.pop("config"),
+        "roofline": head.pop("roofline"),
+    }
+    if "cpu_baseline" in head:
+        out["cpu_baseline"] = head.pop("cpu_baseline")
+    out["timing"] = {"value_from": "hip_graph" if head.get("hip_graph") else "eager",
+                     "eager": head.pop("eager"), "hip_graph": head.pop("hip_graph"),
+                     "note": "both passes run the same K steps from the same warm state"}
+    out.update(head)
+    torch.cuda.empty_cache()
+    if not args.no_samplers:
+        s = samplers_leg(args)
+        out["samplers"] = s
+        r = s["results"]
+        out["plain_vs_surrogate"] = {
+            "plain": {"sampler": "s_proposal", "kernel_particle_steps_per_s":
+                      r["s_proposal"]["particle_steps_per_s"]},
+            "surrogate": {"sampler": "mlp_direct (network where the judge admits it, table "
+                                     "elsewhere)",
+                          "kernel_particle_steps_per_s": r["mlp_direct"]["particle_steps_per_s"],
+                          "spectrum_error_vs_table_direct":
+                              r["mlp_direct"]["spectrum_error_vs_table_direct"],
+                          "bins_on_network": s["mlp"]["bins_on_network"]},
+            "speedup": r["mlp_direct"]["particle_steps_per_s"] / r["s_proposal"]["particle_steps_per_s"]}
+        torch.cuda.empty_cache()
+    if not args.no_legs:
+        out["uniform_field"] = c1_leg(args)
+        torch.cuda.empty_cache()
+        for name in ("c5", "c2"):
+            if name != args.config:
+                out[f"kernel_{name}"] = kernel_leg(name, args.leg_steps, 5)
+                torch.cuda.empty_cache()
+    if not args.no_pic:
+        out["pic_loop"] = pic_leg(args)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c3")
     ap.add_argument("--sort-every", type=int, default=10)
-    ap.add_argument("--tile", default="", help="sort tile in cells, e.g. 256,1,1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=65536)
@@ -578,6 +834,9 @@ def main():
                     help="skip the plain-vs-surrogate sampler comparison on the 3D K=8 workload")
     ap.add_argument("--sampler-steps", type=int, default=12)
     ap.add_argument("--mlp-steps", type=int, default=30000)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the uniform-field, 64M-electron and 2D legs")
+    ap.add_argument("--leg-steps", type=int, default=10)
     ap.add_argument("--no-pic", action="store_true",
                     help="skip the closed PIC loop on the wakefield-shaped workload")
     ap.add_argument("--pic-steps", type=int, default=20)

@@ -315,6 +315,21 @@ class LedgerBuf:
 def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.SR_RECOIL_PHOTON,
                   dn_policy=L.SR_DN_WEIGHT, kin_cut=False, push_position=True,
                   mlp: "Mlp | None" = None, omega_grid: float = 0.0) -> L.Params:
+    """Step parameters.  With the learned sampler the network must have been
+    trained with the same kinematic-cut setting (its draws are x of the cut or
+    uncut spectrum), and when its fallback map sends every chi bin to the table
+    the table sampler is dispatched instead: the same decisions and draws,
+    without the network's LDS and compaction."""
+    if sampler == L.SR_SAMPLER_MLP:
+        if mlp is None:
+            raise ValueError("the learned sampler needs its network (mlp=)")
+        if mlp.kin_cut is None:
+            raise ValueError("the network has not been trained")
+        if bool(mlp.kin_cut) != bool(kin_cut):
+            raise ValueError(f"the network was trained with kin_cut={mlp.kin_cut}, "
+                             f"the step asks for kin_cut={bool(kin_cut)}")
+        if mlp.all_on_table():
+            sampler, mlp = L.SR_SAMPLER_TABLE, None
     return L.Params(float(hbar_n), float(alpha), int(n_samples), int(sampler), int(recoil),
                     int(dn_policy), int(bool(kin_cut)), int(bool(push_position)),
                     None if mlp is None else mlp.params.data_ptr(),
@@ -357,7 +372,10 @@ class Mlp:
         self.v = torch.zeros_like(self.master)
         self.grads = torch.zeros_like(self.master)
         self.work = torch.empty(int(lib().sr_mlp_grad_work()), device=DEV, dtype=torch.float32)
-        self.fallback = torch.zeros(L.SR_MLP_FALLBACK_BINS, device=DEV, dtype=torch.uint8)
+        # every chi bin on the table until the judge admits the network
+        self.fallback = torch.ones(L.SR_MLP_FALLBACK_BINS, device=DEV, dtype=torch.uint8)
+        self.fallback_host = np.ones(L.SR_MLP_FALLBACK_BINS, np.uint8)
+        self.kin_cut = None          # the cut setting the network was trained with
         self.t = 0
         L.check(lib().sr_mlp_cast(_ptr(self.master), _ptr(self.params), _stream()), "sr_mlp_cast")
 
@@ -380,9 +398,22 @@ class Mlp:
                                   _ptr(self.m), _ptr(self.v), self.t, lr, beta1, beta2, eps,
                                   _stream()), "sr_mlp_adam")
 
+    def set_fallback(self, fb):
+        """Set the per-chi-bin fallback map (1: that bin draws from the table)."""
+        fb = torch.as_tensor(fb).to(torch.uint8).reshape(-1)
+        assert fb.numel() == L.SR_MLP_FALLBACK_BINS
+        self.fallback.copy_(fb.to(DEV))
+        self.fallback_host = fb.cpu().numpy().astype(np.uint8)
+
+    def all_on_table(self) -> bool:
+        return bool(np.all(self.fallback_host != 0))
+
     def train(self, table: Table, steps: int, batch: int, lr: float, seed: int = 0x5A11,
               kin_cut: bool = True, lo: float = -4.0, hi: float = 2.0, lr_final: float | None = None):
         """Adam on fresh batches of table-generated pairs; cosine-decayed learning rate."""
+        if self.kin_cut is not None and bool(self.kin_cut) != bool(kin_cut):
+            raise ValueError("the network was trained with the other kinematic-cut setting")
+        self.kin_cut = bool(kin_cut)
         feats = torch.empty((batch, 2), device=DEV, dtype=torch.float32)
         target = torch.empty(batch, device=DEV, dtype=torch.float32)
         lr_final = lr * 0.01 if lr_final is None else lr_final
@@ -428,7 +459,7 @@ class Mlp:
             ht, _ = np.histogram(xt[b], bins=edges, weights=xt[b])
             hm, _ = np.histogram(xm[b], bins=edges, weights=xm[b])
             err[b] = np.abs(hm - ht).sum() / max(ht.sum(), 1e-300)
-        self.fallback.copy_(torch.from_numpy((err > tol).astype(np.uint8)))
+        self.set_fallback(torch.from_numpy((err > tol).astype(np.uint8)))
         return err
 
     def make_batch(self, table: Table, seed: int, batch_index: int, M: int, kin_cut=True,

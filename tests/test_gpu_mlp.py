@@ -161,7 +161,7 @@ def test_step_network_path_matches_standalone_forward(sr, table, oracle, trained
     forward pass of the same network at the same (chi, u)."""
     net, _, _, err = trained
     saved = net.fallback.clone()
-    net.fallback.zero_()
+    net.set_fallback(torch.zeros_like(saved))
     try:
         cfg = synth.config("c1", b0=(0.0, 0.0, 40.0), gamma_range=(1e3, 1e4))
         n, K, seed, step = 5000, 4, 91, 2
@@ -202,7 +202,7 @@ def test_step_network_path_matches_standalone_forward(sr, table, oracle, trained
         print(f"network path: {x_gpu.size} photons, median |x/x_exact - 1| "
               f"{np.median(np.abs(x_gpu / x_exact - 1)):.2e}", flush=True)
     finally:
-        net.fallback.copy_(saved)
+        net.set_fallback(saved)
 
 
 def test_sampler_speed_and_spectrum(sr, table, trained):
@@ -237,7 +237,7 @@ def test_sampler_speed_and_spectrum(sr, table, trained):
     try:
         for name, sampler, fb in variants:
             if fb is not None:
-                net.fallback.copy_(fb)
+                net.set_fallback(fb)
             prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, cfg.recoil, 0, cfg.kin_cut,
                                    True, mlp=net if sampler == 2 else None)
             times = []
@@ -260,7 +260,7 @@ def test_sampler_speed_and_spectrum(sr, table, trained):
             res[name] = {"ms": min(times[1:]), "photons": row[5], "emitted": row[0],
                          "ll": row[1], "hist": hist[:bins].cpu().numpy()}
     finally:
-        net.fallback.copy_(saved)
+        net.set_fallback(saved)
     ref = res["table_direct"]
     for name, r in res.items():
         r["spec_err"] = float(np.abs(r["hist"] - ref["hist"]).sum() / ref["hist"].sum())
