@@ -525,7 +525,9 @@ def pic_leg(args):
     ledger = api.LedgerBuf(warm + steps, n_chunks)
     tile = tuple(int(v) for v in args.pic_tile.split(","))
     sw = api.sort_work(grid, tile, n)
-    prm = api.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, kin_cut=cfg.kin_cut)
+    # a dense plasma (2 per cell) in 4x4x4 tiles: most blocks gather from an LDS field box
+    prm = api.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, kin_cut=cfg.kin_cut,
+                            gather=L.SR_GATHER_BOX)
     stream = torch.cuda.current_stream()
     names = ("sort", "copy_x", "emission", "current", "field", "photons", "ledger")
     times = {k: [] for k in names}
@@ -583,6 +585,7 @@ def pic_leg(args):
             "photons_per_step": float(rows[:, L.SR_LED_PHOTONS].mean()),
             "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
             "status_bits": int(status.item()) | int(ledger.read_status()),
+            "gather": "LDS field box where a block's stencils fit (SR_GATHER_BOX)",
             "timing": "HIP events on the stream around each part; sort amortised over its "
                       "every-10-steps calls"}
 

@@ -159,7 +159,20 @@ typedef struct {
                                hbar_n omega_grid is not emitted (no record, no
                                recoil, not in the ledger's emitted column).  0: no
                                floor.  Not with SR_SAMPLER_MLP (SR_E_INVAL)        */
+    int32_t gather;         /* SR_GATHER_DIRECT (0): every particle reads its stencil
+                               from the grid in global memory.  SR_GATHER_BOX: on 3D
+                               grids with uniform chunks, FP32 path, proposal, table
+                               or quantum sampler, a block of 256 particles whose
+                               stencils span at most SR_FIELD_BOX_NODES nodes (and do
+                               not straddle a periodic boundary) first copies those
+                               grid values into LDS with coalesced loads and
+                               interpolates from there; other blocks, and other
+                               configurations, read directly.  Both give
+                               bit-identical results.                               */
+    int32_t reserved;
 } sr_params;
+enum { SR_GATHER_DIRECT = 0, SR_GATHER_BOX = 1 };
+#define SR_FIELD_BOX_NODES 1344
 
 /* Chunking of the particle array.  Chunk c covers particles
  * [start[c], start[c+1]) when start != NULL (device, n_chunks+1 int64 values,

@@ -22,6 +22,8 @@ SR_NOALLOC_MAX_CHUNKS = 1 << 20
 SR_SAMPLER_S, SR_SAMPLER_TABLE, SR_SAMPLER_MLP, SR_SAMPLER_QUANTUM = 0, 1, 2, 3
 SR_RECOIL_NONE, SR_RECOIL_PHOTON, SR_RECOIL_LL = 0, 1, 2
 SR_DN_WEIGHT, SR_DN_CLAMP = 0, 1
+SR_GATHER_DIRECT, SR_GATHER_BOX = 0, 1
+SR_FIELD_BOX_NODES = 1344
 SR_VALID_QUANTUM, SR_VALID_NON_SYNCHROTRON, SR_VALID_SUMS = 1, 2, 6
 SR_MLP_PARAMS = 8577
 SR_MLP_FALLBACK_BINS = 24
@@ -51,7 +53,7 @@ class Params(C.Structure):
                 ("sampler", C.c_int32), ("recoil", C.c_int32), ("dn_policy", C.c_int32),
                 ("kin_cut", C.c_int32), ("push_position", C.c_int32),
                 ("mlp_params", C.c_void_p), ("mlp_fallback", C.c_void_p),
-                ("omega_grid", C.c_double)]
+                ("omega_grid", C.c_double), ("gather", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Chunking(C.Structure):

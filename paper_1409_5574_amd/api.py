@@ -314,7 +314,8 @@ class LedgerBuf:
 
 def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.SR_RECOIL_PHOTON,
                   dn_policy=L.SR_DN_WEIGHT, kin_cut=False, push_position=True,
-                  mlp: "Mlp | None" = None, omega_grid: float = 0.0) -> L.Params:
+                  mlp: "Mlp | None" = None, omega_grid: float = 0.0,
+                  gather: int = L.SR_GATHER_DIRECT) -> L.Params:
     """Step parameters.  With the learned sampler the network must have been
     trained with the same kinematic-cut setting (its draws are x of the cut or
     uncut spectrum), and when its fallback map sends every chi bin to the table
@@ -333,7 +334,8 @@ def params_struct(hbar_n, alpha, n_samples=1, sampler=L.SR_SAMPLER_S, recoil=L.S
     return L.Params(float(hbar_n), float(alpha), int(n_samples), int(sampler), int(recoil),
                     int(dn_policy), int(bool(kin_cut)), int(bool(push_position)),
                     None if mlp is None else mlp.params.data_ptr(),
-                    None if mlp is None else mlp.fallback.data_ptr(), float(omega_grid))
+                    None if mlp is None else mlp.fallback.data_ptr(), float(omega_grid),
+                    int(gather), 0)
 
 
 def eval_direct(table: Table, a: torch.Tensor, chi: torch.Tensor, kin_cut: bool) -> torch.Tensor:

@@ -26,6 +26,9 @@ constexpr int kMaxK = 16;       // largest supported number of trials per step
 template <typename R> __device__ __forceinline__ R sqrt_r(R v);
 template <> __device__ __forceinline__ float sqrt_r<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
 template <> __device__ __forceinline__ double sqrt_r<double>(double v) { return sqrt(v); }
+template <typename R> __device__ __forceinline__ R fma_r(R a, R b, R c);
+template <> __device__ __forceinline__ float fma_r<float>(float a, float b, float c) { return fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_r<double>(double a, double b, double c) { return fma(a, b, c); }
 template <typename R> __device__ __forceinline__ R rcp_r(R v);
 template <> __device__ __forceinline__ float rcp_r<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double rcp_r<double>(double v) { return 1.0 / v; }
@@ -370,7 +373,15 @@ __device__ __forceinline__ R row_lerp(const float *__restrict__ a, uint32_t row,
         lo = v.y;
         hi = ld(a, row);
     }
-    return gx * (R)lo + fx * (R)hi;
+    return fma_r<R>(gx, (R)lo, fx * (R)hi);
+}
+
+// The trilinear combination of four interpolated rows, with its roundings
+// fixed (explicit fused multiply-adds) so that the direct and the LDS-box
+// gathers give the same bits.
+template <typename R>
+__device__ __forceinline__ R trilerp(R gy, R fy, R gz, R fz, R c00, R c01, R c10, R c11) {
+    return fma_r<R>(gz, fma_r<R>(gy, c00, fy * c01), fz * fma_r<R>(gy, c10, fy * c11));
 }
 
 // Bilinear (2D) / trilinear (3D) interpolation of one component.  sx, sy, sz
@@ -387,7 +398,7 @@ __device__ __forceinline__ R cic(const float *__restrict__ a, const Axis<R> &X, 
     const R gx = (R)1 - fx, gy = (R)1 - fy;
     if (DIM == 2) {
         const uint32_t r0 = __umul24(iy0, (uint32_t)nx), r1 = __umul24(iy1, (uint32_t)nx);
-        return gy * row_lerp<R>(a, r0, P, gx, fx) + fy * row_lerp<R>(a, r1, P, gx, fx);
+        return fma_r<R>(gy, row_lerp<R>(a, r0, P, gx, fx), fy * row_lerp<R>(a, r1, P, gx, fx));
     } else {
         const uint32_t iz0 = sz ? Z.i1 : Z.i0, iz1 = sz ? Z.i1p : Z.i0p;
         const R fz = sz ? Z.f1 : Z.f0;
@@ -399,8 +410,48 @@ __device__ __forceinline__ R cic(const float *__restrict__ a, const Axis<R> &X, 
         const uint32_t p10 = __umul24(z1 + iy0, (uint32_t)nx), p11 = __umul24(z1 + iy1, (uint32_t)nx);
         const R c00 = row_lerp<R>(a, p00, P, gx, fx), c01 = row_lerp<R>(a, p01, P, gx, fx);
         const R c10 = row_lerp<R>(a, p10, P, gx, fx), c11 = row_lerp<R>(a, p11, P, gx, fx);
-        return gz * (gy * c00 + fy * c01) + fz * (gy * c10 + fy * c11);
+        return trilerp<R>(gy, fy, gz, fz, c00, c01, c10, c11);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Field box in LDS (3D, the SR_GATHER_BOX gather): the grid values of every
+// node a block's stencils read, for the six components, copied once per block
+// with coalesced loads.  The box covers nodes lo[a] .. lo[a] + ext[a] - 1
+// (periodic) on each axis and stores component c at
+// box[c][(lz ext[1] + ly) ext[0] + lx].
+// ---------------------------------------------------------------------------
+struct FieldBox {
+    int lo[3];
+    int ext[3];
+};
+constexpr int kBoxCells = SR_FIELD_BOX_NODES;
+
+// Local box index of node i (in [0, n)) on an axis whose box starts at lo.
+__device__ __forceinline__ uint32_t box_local(int i, int lo, int n) {
+    const int l = i - lo;
+    return (uint32_t)(l < 0 ? l + n : l);
+}
+
+// One component from the box, with the values and the arithmetic of
+// cic<R, 3>: bit-identical to the direct gather.
+template <typename R>
+__device__ __forceinline__ R cic_box(const float *__restrict__ b, const Axis<R> &X,
+                                     const Axis<R> &Y, const Axis<R> &Z, const FieldBox &B,
+                                     const int n[3], bool sx, bool sy, bool sz) {
+    const uint32_t lx = box_local(sx ? X.i1 : X.i0, B.lo[0], n[0]);
+    const R fx = sx ? X.f1 : X.f0;
+    const uint32_t y0 = box_local(sy ? Y.i1 : Y.i0, B.lo[1], n[1]);
+    const R fy = sy ? Y.f1 : Y.f0;
+    const uint32_t z0 = box_local(sz ? Z.i1 : Z.i0, B.lo[2], n[2]);
+    const R fz = sz ? Z.f1 : Z.f0;
+    const R gx = (R)1 - fx, gy = (R)1 - fy, gz = (R)1 - fz;
+    const uint32_t ex = (uint32_t)B.ext[0], ey = (uint32_t)B.ext[1];
+    const uint32_t r00 = (z0 * ey + y0) * ex + lx;
+    const uint32_t r01 = r00 + ex, r10 = r00 + ex * ey, r11 = r10 + ex;
+    const auto lerp = [&](uint32_t r) { return fma_r<R>(gx, (R)b[r], fx * (R)b[r + 1]); };
+    const R c00 = lerp(r00), c01 = lerp(r01), c10 = lerp(r10), c11 = lerp(r11);
+    return trilerp<R>(gy, fy, gz, fz, c00, c01, c10, c11);
 }
 
 // a*b - c*d with one rounding error (Kahan's fused algorithm).
@@ -427,6 +478,16 @@ namespace sr {
 __device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
 __device__ __forceinline__ float wave_max(float v) { return __ockl_wfred_max_f32(v); }
 __device__ __forceinline__ float wave_sum_f(float v) { return __ockl_wfred_add_f32(v); }
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

@@ -18,6 +18,7 @@
 #include <stddef.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
@@ -120,16 +121,45 @@ struct Pushed {
     bool bad;     // the push is not finite (a non-finite field value or momentum)
 };
 
+template <typename R>
+__device__ __forceinline__ Pushed<R> push_fields(const StepArgs<R> &a, const R p0[3], const R E[3],
+                                                 const R B[3]);
+
 template <typename R, int DIM>
 __device__ __forceinline__ Pushed<R> push_heff(const StepArgs<R> &a, const R pos[3],
                                                const R p0[3]) {
-    Pushed<R> o;
     R E[3], B[3];
     if (DIM == 0) {
         for (int q = 0; q < 3; ++q) { E[q] = uniform_e<R>(a.g, q); B[q] = uniform_b<R>(a.g, q); }
     } else {
         gather_grid<R, DIM>(a, pos, E, B);
     }
+    return push_fields<R>(a, p0, E, B);
+}
+
+// The same, with the fields interpolated from the block's LDS field box (3D).
+template <typename R>
+__device__ __forceinline__ Pushed<R> push_box(const StepArgs<R> &a, const R pos[3], const R p0[3],
+                                              const float (*box)[kBoxCells], const FieldBox &fb) {
+    Axis<R> X, Y, Z;
+    setup_axis<R>(a.g, 0, pos[0], X);
+    setup_axis<R>(a.g, 1, pos[1], Y);
+    setup_axis<R>(a.g, 2, pos[2], Z);
+    const int n[3] = {a.g.n[0], a.g.n[1], a.g.n[2]};
+    // Yee offsets as in gather_grid
+    const R E[3] = {cic_box<R>(box[0], X, Y, Z, fb, n, true, false, false),
+                    cic_box<R>(box[1], X, Y, Z, fb, n, false, true, false),
+                    cic_box<R>(box[2], X, Y, Z, fb, n, false, false, true)};
+    const R B[3] = {cic_box<R>(box[3], X, Y, Z, fb, n, false, true, true),
+                    cic_box<R>(box[4], X, Y, Z, fb, n, true, false, true),
+                    cic_box<R>(box[5], X, Y, Z, fb, n, true, true, false)};
+    return push_fields<R>(a, p0, E, B);
+}
+
+template <typename R>
+__device__ __forceinline__ Pushed<R> push_fields(const StepArgs<R> &a, const R p0[3], const R E[3],
+                                                 const R B[3]) {
+    Pushed<R> o;
     // ---- Boris push (q = -1), keeping the momentum increment d explicitly
     const R h = (R)(-0.5) * a.dt;
     const R um[3] = {p0[0] + h * E[0], p0[1] + h * E[1], p0[2] + h * E[2]};
@@ -240,7 +270,7 @@ constexpr int kPartFlags = SR_LEDGER_COLS;
 // LDS of the kernel.  With the MLP sampler: the network, and per wave the
 // compacted inputs of the emitted trials and a 16x64 transpose buffer, which
 // the ledger reduction reuses after the last round.
-template <int KMAX, int SAMPLER>
+template <int KMAX, int SAMPLER, bool BOX = false>
 struct alignas(16) StepSmem {
     union {
         struct {
@@ -262,22 +292,102 @@ struct PhotonStage {
     uint32_t base[kWaves];      // first buffer slot of each wave's chunk segment
 };
 template <int KMAX>
-struct StepSmem<KMAX, SR_SAMPLER_S> {
+struct StepSmem<KMAX, SR_SAMPLER_S, false> {
     LedgerSmem led;
     PhotonStage stage;
 };
 template <int KMAX>
-struct StepSmem<KMAX, SR_SAMPLER_TABLE> {
+struct StepSmem<KMAX, SR_SAMPLER_TABLE, false> {
     LedgerSmem led;
     PhotonStage stage;
 };
 template <int KMAX>
-struct StepSmem<KMAX, SR_SAMPLER_QUANTUM> {
+struct StepSmem<KMAX, SR_SAMPLER_QUANTUM, false> {
     LedgerSmem led;
     PhotonStage stage;
 };
+// With the LDS field box (SR_GATHER_BOX) the box shares its LDS with the
+// ledger and the photon stage: it is read only before either is written.
+// 32 352 bytes in all keeps five 256-thread blocks per compute unit.
+struct BoxReduce {
+    int mn[kWaves][3], mx[kWaves][3];
+};
+struct alignas(16) BoxSmem {
+    union {
+        struct {
+            LedgerSmem led;
+            PhotonStage stage;
+        };
+        float box[6][kBoxCells];
+    };
+    BoxReduce red;
+};
+template <int KMAX>
+struct StepSmem<KMAX, SR_SAMPLER_S, true> : BoxSmem {};
+template <int KMAX>
+struct StepSmem<KMAX, SR_SAMPLER_TABLE, true> : BoxSmem {};
+template <int KMAX>
+struct StepSmem<KMAX, SR_SAMPLER_QUANTUM, true> : BoxSmem {};
 template <typename S>
 __device__ __forceinline__ LedgerSmem &ledger_smem(S &s) { return s.led; }
+
+// Field box of a block (3D, uniform chunks, called by every thread of the
+// block): the nodes of every stencil of the block's particles, from the
+// extremes of their offset-0 base cells widened by one node on each side (the
+// offset-1/2 base node is the base cell or the one below it).  A block whose
+// cells straddle a periodic boundary, or whose box exceeds kBoxCells nodes or
+// wraps onto itself, returns false and gathers directly.  Otherwise the six
+// components are copied into LDS with coalesced loads (the caller syncs
+// before reading them).
+template <typename R>
+__device__ __forceinline__ bool load_field_box(const StepArgs<R> &a, BoxSmem &sm, bool act,
+                                               const int cell[3], FieldBox &fb) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int lo = wave_min_i(act ? cell[q] : 0x7fffffff);
+        const int hi = wave_max_i(act ? cell[q] : -0x7fffffff);
+        if (lane == 0) { sm.red.mn[wave][q] = lo; sm.red.mx[wave][q] = hi; }
+    }
+    __syncthreads();
+    int cells = 1;
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int lo = min(min(sm.red.mn[0][q], sm.red.mn[1][q]), min(sm.red.mn[2][q], sm.red.mn[3][q]));
+        const int hi = max(max(sm.red.mx[0][q], sm.red.mx[1][q]), max(sm.red.mx[2][q], sm.red.mx[3][q]));
+        const int n = a.g.n[q];
+        const int ext = hi - lo + 3;
+        ok = ok && hi >= lo && ext < n;
+        fb.lo[q] = lo == 0 ? n - 1 : lo - 1;
+        fb.ext[q] = ext;
+        cells *= ok ? ext : 1;
+    }
+    if (!(ok && cells <= kBoxCells)) return false;
+    // element e of the box, x fastest; the quotients are exact in binary32
+    // (e + 1/2 below 2^22)
+    const uint32_t ex = (uint32_t)fb.ext[0], ey = (uint32_t)fb.ext[1];
+    const float inv_ex = 1.0f / (float)ex, inv_ey = 1.0f / (float)ey;
+    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
+    for (uint32_t e = (uint32_t)tid; e < (uint32_t)cells; e += kBlock) {
+        const uint32_t r = (uint32_t)(((float)e + 0.5f) * inv_ex);
+        const uint32_t lx = e - r * ex;
+        const uint32_t lz = (uint32_t)(((float)r + 0.5f) * inv_ey);
+        const uint32_t ly = r - lz * ey;
+        int gx = fb.lo[0] + (int)lx, gy = fb.lo[1] + (int)ly, gz = fb.lo[2] + (int)lz;
+        gx -= gx >= nx ? nx : 0;
+        gy -= gy >= ny ? ny : 0;
+        gz -= gz >= nz ? nz : 0;
+        const uint32_t off = __umul24(__umul24((uint32_t)gz, (uint32_t)ny) + (uint32_t)gy,
+                                      (uint32_t)nx) + (uint32_t)gx;
+        float v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = ld(a.f[c], off);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sm.box[c][e] = v[c];
+    }
+    return true;
+}
 
 // Occupancy target: the FP32 3D kernels with 4 to 8 trials sit a couple of
 // VGPRs above the 96 that five waves per SIMD allow; asking for five costs no
@@ -290,11 +400,14 @@ constexpr int step_waves_per_eu() {
 
 // FLOOR: the grid-frequency floor is on (a.e_grid > 0); a template flag, so the
 // kernels without it carry none of its code.
-template <typename R, int DIM, int KMAX, int SAMPLER, bool FLOOR>
+// BOX: the SR_GATHER_BOX gather (3D, uniform chunks, proposal, table or
+// quantum sampler); the host launches it only there.
+template <typename R, int DIM, int KMAX, int SAMPLER, bool FLOOR, bool BOX>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<R, DIM, KMAX, SAMPLER>())))
 void push_emit_kernel(const StepArgs<R> a) {
-    __shared__ StepSmem<KMAX, SAMPLER> sm;
+    static_assert(!BOX || (DIM == 3 && SAMPLER != SR_SAMPLER_MLP), "the field box is 3D");
+    __shared__ StepSmem<KMAX, SAMPLER, BOX> sm;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if constexpr (SAMPLER == SR_SAMPLER_MLP) {
@@ -338,7 +451,7 @@ void push_emit_kernel(const StepArgs<R> a) {
     constexpr bool kLdsAcc = SAMPLER != SR_SAMPLER_MLP;
     double tot_emit = 0.0, tot_ll = 0.0, tot_de = 0.0, tot_clamp = 0.0, tot_drop = 0.0;
     float tot_w = 0.0f;
-    if constexpr (kLdsAcc) {
+    if constexpr (kLdsAcc && !BOX) {
         LedgerSmem &rs = ledger_smem(sm);
 #pragma unroll
         for (int q = 0; q < 5; ++q) rs.d[q][tid] = 0.0;
@@ -347,8 +460,12 @@ void push_emit_kernel(const StepArgs<R> a) {
     float chi_max = 0.0f;
     uint32_t flags = 0;
     uint32_t run_base = 0;
+    bool box_used = false;
 
-    for (uint32_t base = s0; base < e0; base += kChunk) {
+    // BOX (uniform chunks): exactly one round per wave, waves without a chunk
+    // running it with no active lane, so the block-wide steps of the field box
+    // are reached by every thread
+    for (uint32_t base = s0; BOX ? base == s0 : base < e0; base += kChunk) {
         double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0;
         float acc_w = 0.0f;
         const uint32_t i = base + lane;
@@ -360,16 +477,39 @@ void push_emit_kernel(const StepArgs<R> a) {
         R wi = (R)0, pos[3] = {(R)0, (R)0, (R)0}, pn[3] = {(R)0, (R)0, (R)0};
         R chi = (R)0, gb = (R)1, g_new = (R)1, p2 = (R)0, pbm = (R)0;
         bool bad = false;
+        bool use_box = false;
+        FieldBox fb{};
+        if constexpr (BOX) {
+            // positions first: the block's box from its particles' cells
+            int cell[3] = {0, 0, 0};
+            if (active) {
+                pos[0] = ld(a.x[0], i); pos[1] = ld(a.x[1], i); pos[2] = ld(a.x[2], i);
+                Axis<R> X, Y, Z;
+                setup_axis<R>(a.g, 0, pos[0], X);
+                setup_axis<R>(a.g, 1, pos[1], Y);
+                setup_axis<R>(a.g, 2, pos[2], Z);
+                cell[0] = X.i0; cell[1] = Y.i0; cell[2] = Z.i0;
+            }
+            use_box = load_field_box<R>(a, sm, active, cell, fb);
+            if (use_box) __syncthreads();
+            box_used = use_box;
+        }
         if (active) {
             wi = ld(a.w, i);
             pid = ld(a.id, i);
-            if (a.has_pos) {
+            if (!BOX && a.has_pos) {
                 pos[0] = ld(a.x[0], i);
                 if (DIM != 0 || a.x[1]) pos[1] = ld(a.x[1], i);
                 if ((DIM == 3 || DIM == 0) && a.x[2]) pos[2] = ld(a.x[2], i);
             }
             const R p0[3] = {ld(a.p[0], i), ld(a.p[1], i), ld(a.p[2], i)};
-            const Pushed<R> q = push_heff<R, DIM>(a, pos, p0);
+            Pushed<R> q;
+            if constexpr (BOX) {
+                if (use_box) q = push_box<R>(a, pos, p0, sm.box, fb);
+                else q = push_heff<R, DIM>(a, pos, p0);
+            } else {
+                q = push_heff<R, DIM>(a, pos, p0);
+            }
             pn[0] = q.pn[0]; pn[1] = q.pn[1]; pn[2] = q.pn[2];
             p2 = q.p2;
             gb = q.gb;
@@ -391,6 +531,13 @@ void push_emit_kernel(const StepArgs<R> a) {
             chi_max = fmaxf(chi_max, chif);
             eps_unit = 1.5f * chif * (float)gb;    // hbar omega_c: photon energy per unit x
             wi_f = (float)wi;
+        }
+        if constexpr (BOX) {
+            if (use_box) __syncthreads();          // every wave is done with the box
+            LedgerSmem &rs = ledger_smem(sm);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) rs.d[q][tid] = 0.0;
+            rs.f[0][tid] = 0.0f;
         }
 
         // ---- K trials.  Inactive lanes take part in the wave-wide steps with a
@@ -714,7 +861,8 @@ void push_emit_kernel(const StepArgs<R> a) {
             row[SR_LED_CLAMPED] = cl;
             row[SR_LED_PHOTONS] = (double)((rs.cnt[0] + rs.cnt[1]) + (rs.cnt[2] + rs.cnt[3]));
             row[kPartFlags] = (double)(rs.flags[0] | rs.flags[1] | rs.flags[2] | rs.flags[3]);
-            row[kPartFlags + 1] = 0.0;
+            // the last column marks the blocks that gathered from the field box
+            row[kPartFlags + 1] = box_used ? 1.0 : 0.0;
         }
     }
 }
@@ -970,6 +1118,7 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     if (prm->sampler == SR_SAMPLER_MLP && prm->omega_grid > 0.0) return SR_E_INVAL;
     if (prm->recoil < 0 || prm->recoil > 2 || prm->dn_policy < 0 || prm->dn_policy > 1)
         return SR_E_INVAL;
+    if (prm->gather != SR_GATHER_DIRECT && prm->gather != SR_GATHER_BOX) return SR_E_INVAL;
     const int64_t n_chunks = chunks->start ? chunks->n_chunks : (n + kChunk - 1) / kChunk;
     if (chunks->start == nullptr && chunks->n_chunks != n_chunks) return SR_E_INVAL;
     if (n_chunks < 0 || n_chunks > 0x7FFFFFFF) return SR_E_INVAL;
@@ -1015,33 +1164,40 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     const int KM = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : 16;
 
     // with events: the dispatch packet itself records the kernel's start and stop
-#define SR_LAUNCH(DIMV, KMV, SMP, FL)                                                          \
+    // the field-box gather: FP32 path, 3D, uniform chunks, not the learned sampler
+    constexpr bool kBoxR = std::is_same<R, float>::value;
+    const bool box = prm->gather == SR_GATHER_BOX && dim == 3 && chunks->start == nullptr &&
+                     prm->sampler != SR_SAMPLER_MLP;
+#define SR_LAUNCH(DIMV, KMV, SMP, FL, BX)                                                      \
     if (ev_start || ev_stop)                                                                   \
-        hipExtLaunchKernelGGL(push_emit_kernel<R, DIMV, KMV, SMP, FL>, grd, blk, 0, st,        \
+        hipExtLaunchKernelGGL(push_emit_kernel<R, DIMV, KMV, SMP, FL, BX>, grd, blk, 0, st,    \
                               (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, a);                \
     else                                                                                       \
-        push_emit_kernel<R, DIMV, KMV, SMP, FL><<<grd, blk, 0, st>>>(a)
-#define SR_BY_K(DIMV, SMP, FL)                         \
-    switch (KM) {                                      \
-        case 1: SR_LAUNCH(DIMV, 1, SMP, FL); break;    \
-        case 2: SR_LAUNCH(DIMV, 2, SMP, FL); break;    \
-        case 4: SR_LAUNCH(DIMV, 4, SMP, FL); break;    \
-        case 8: SR_LAUNCH(DIMV, 8, SMP, FL); break;    \
-        default: SR_LAUNCH(DIMV, 16, SMP, FL); break;  \
+        push_emit_kernel<R, DIMV, KMV, SMP, FL, BX><<<grd, blk, 0, st>>>(a)
+#define SR_BY_K(DIMV, SMP, FL, BX)                         \
+    switch (KM) {                                          \
+        case 1: SR_LAUNCH(DIMV, 1, SMP, FL, BX); break;    \
+        case 2: SR_LAUNCH(DIMV, 2, SMP, FL, BX); break;    \
+        case 4: SR_LAUNCH(DIMV, 4, SMP, FL, BX); break;    \
+        case 8: SR_LAUNCH(DIMV, 8, SMP, FL, BX); break;    \
+        default: SR_LAUNCH(DIMV, 16, SMP, FL, BX); break;  \
     }
-#define SR_BY_DIM(SMP, FL)                             \
-    switch (dim) {                                     \
-        case 0: SR_BY_K(0, SMP, FL); break;            \
-        case 2: SR_BY_K(2, SMP, FL); break;            \
-        default: SR_BY_K(3, SMP, FL); break;           \
+#define SR_BY_DIM(SMP, FL, BOXOK)                                      \
+    switch (dim) {                                                     \
+        case 0: SR_BY_K(0, SMP, FL, false); break;                     \
+        case 2: SR_BY_K(2, SMP, FL, false); break;                     \
+        default:                                                       \
+            if (box) { SR_BY_K(3, SMP, FL, (BOXOK && kBoxR)); }        \
+            else { SR_BY_K(3, SMP, FL, false); }                       \
+            break;                                                     \
     }
-#define SR_BY_FLOOR(SMP)                               \
-    if (a.e_grid > 0.0f) { SR_BY_DIM(SMP, true); }     \
-    else { SR_BY_DIM(SMP, false); }
+#define SR_BY_FLOOR(SMP)                                     \
+    if (a.e_grid > 0.0f) { SR_BY_DIM(SMP, true, true); }     \
+    else { SR_BY_DIM(SMP, false, true); }
     if (prm->sampler == SR_SAMPLER_S) { SR_BY_FLOOR(SR_SAMPLER_S); }
     else if (prm->sampler == SR_SAMPLER_TABLE) { SR_BY_FLOOR(SR_SAMPLER_TABLE); }
     else if (prm->sampler == SR_SAMPLER_QUANTUM) { SR_BY_FLOOR(SR_SAMPLER_QUANTUM); }
-    else { SR_BY_DIM(SR_SAMPLER_MLP, false); }
+    else { SR_BY_DIM(SR_SAMPLER_MLP, false, false); }
 #undef SR_BY_FLOOR
 #undef SR_BY_DIM
 #undef SR_BY_K

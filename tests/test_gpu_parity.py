@@ -120,7 +120,8 @@ def _orc_state(d):
 
 def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=None, dtype=np.float32,
                   p_scale=1.0, seed=777, step=3, t=0.4, sampler=0, chunks=None, dn_policy=0,
-                  label="", omega_grid=0.0, edit_state=None, edit_fields=None, status_ok=2):
+                  label="", omega_grid=0.0, edit_state=None, edit_fields=None, status_ok=2,
+                  gather=0, sort_tile=None):
     K = cfg.n_samples if K is None else K
     recoil = cfg.recoil if recoil is None else recoil
     kin_cut = cfg.kin_cut if kin_cut is None else kin_cut
@@ -129,6 +130,14 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
         st[k] = (st[k].astype(np.float64) * p_scale).astype(np.float32)
     if edit_state is not None:
         edit_state(st)
+    if sort_tile is not None:
+        # particles ordered by tile (x fastest), as the tile sort leaves them
+        key = np.zeros(n, np.int64)
+        for a in reversed(range(cfg.dim)):
+            q = cfg.grid[a] // sort_tile[a]
+            key = key * q + (np.floor(st["xyz"[a]] / cfg.dx).astype(np.int64) // sort_tile[a])
+        order = np.argsort(key, kind="stable")
+        st = {k: v[order].copy() for k, v in st.items()}
     old = _orc_state(st)
     dim = cfg.dim
     if dim == 0:
@@ -167,7 +176,7 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
     photons = sr.PhotonBuffer(n, K, n_chunks=n_chunks, dim=dim if dim else 3)
     ledger = sr.LedgerBuf(4, n_chunks if n_chunks is not None else sr.n_chunks_uniform(n))
     prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler, recoil, dn_policy, kin_cut, dim != 0,
-                           omega_grid=omega_grid)
+                           omega_grid=omega_grid, gather=gather)
     _say(f"step {label} n={n} K={K} dim={dim} dtype={np.dtype(dtype).name}")
     sr.gather_push_emit(parts, fields, grid, cfg.dt, seed, step, prm, table, photons, ledger, 1,
                         start=start)
@@ -207,6 +216,11 @@ def run_step_case(sr, table, oracle, cfg, n, *, K=None, recoil=None, kin_cut=Non
     rep["status"] = status
     rep["det"] = det
     rep["ph_g"] = ph_g
+    # blocks whose partial ledger row marks a gather from the LDS field box
+    nb = -(-(n_chunks if n_chunks is not None else sr.n_chunks_uniform(n)) // 4)
+    part = ledger.partials[:nb * 10].view(nb, 10).cpu().numpy()
+    rep["box_blocks"] = int((part[:, 9] == 1.0).sum())
+    rep["blocks"] = nb
     return rep
 
 
@@ -263,6 +277,70 @@ def test_step_dn_above_one(sr, table, oracle, dn_policy):
         assert np.all(w == np.float32(0.5))      # every photon carries w/K
     else:
         assert (w > 0.5).sum() > 100              # dN >= 1 photons carry w dN/K
+
+
+@pytest.mark.parametrize("sampler", [0, 3])
+def test_step_field_box_gather(sr, table, oracle, sampler):
+    # a dense 3D plasma (2 particles per cell) in tile order: most 256-particle
+    # blocks fit their stencils in an LDS box; parity with the oracle as for the
+    # direct gather (the same bits, checked below)
+    cfg = synth.config("c3", grid=(40, 32, 24), slab=None)
+    n = 2 * 40 * 32 * 24
+    rep = run_step_case(sr, table, oracle, cfg, n, p_scale=3000.0, sampler=sampler,
+                        kin_cut=sampler == 0, gather=1, sort_tile=(4, 4, 4),
+                        label=f"3d field box sampler {sampler}")
+    assert rep["box_blocks"] >= rep["blocks"] // 2, (rep["box_blocks"], rep["blocks"])
+    assert rep["photons_oracle"] > 1000
+
+
+def test_field_box_gather_is_bit_identical(sr, table):
+    """SR_GATHER_BOX against SR_GATHER_DIRECT from the same state: particles,
+    photon records and ledger row bit for bit, on a tile-sorted dense plasma
+    (most blocks from the box), an unsorted one (every box too large: the
+    fallback), and a grid of 8 cells along z where boxes wrap around the
+    periodic boundary or would wrap onto themselves."""
+    for grid, tile, label in (((48, 40, 32), (4, 4, 4), "sorted"), ((48, 40, 32), None, "unsorted"),
+                              ((64, 48, 8), (4, 4, 4), "thin z")):
+        cfg = synth.config("c3", grid=grid, slab=None)
+        n = 2 * int(np.prod(grid))
+        st = synth.gen_particles(cfg, n=n, seed=41)
+        for k in ("px", "py", "pz"):
+            st[k] = (st[k].astype(np.float64) * 2500.0).astype(np.float32)
+        if tile is not None:
+            key = np.zeros(n, np.int64)
+            for a in (2, 1, 0):
+                key = key * (grid[a] // tile[a]) + (np.floor(st["xyz"[a]] / cfg.dx).astype(np.int64)
+                                                    // tile[a])
+            o = np.argsort(key, kind="stable")
+            st = {k: v[o].copy() for k, v in st.items()}
+        E, B = synth.standing_wave_grid(cfg, 0.7)
+        fields = sr.Fields(E, B)
+        g = sr.grid_struct(3, n=grid, dx=(cfg.dx,) * 3)
+        outs = []
+        for gather in (0, 1):
+            parts = sr.Particles.from_numpy(st, dim=3)
+            photons = sr.PhotonBuffer(n, cfg.photons_per_particle, dim=3)
+            ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
+            prm = sr.params_struct(cfg.hbar_n, cfg.alpha, cfg.n_samples, recoil=cfg.recoil,
+                                   kin_cut=True, gather=gather)
+            _say(f"field box bit-identity {label} gather={gather} n={n}")
+            sr.gather_push_emit(parts, fields, g, cfg.dt, 5, 3, prm, table, photons, ledger, 0)
+            torch.cuda.synchronize()
+            nb = -(-sr.n_chunks_uniform(n) // 4)
+            used = int((ledger.partials[:nb * 10].view(nb, 10)[:, 9] == 1.0).sum().item())
+            outs.append((parts.to_numpy(), photons.gather(n), ledger.row(0), used, nb))
+        (pa, pha, la, _, _), (pb, phb, lb, used, nb) = outs
+        for k in ("x", "y", "z", "px", "py", "pz"):
+            assert np.array_equal(pa[k], pb[k]), (label, k)
+        for k in ("eps", "w", "dir", "pos", "parent", "k"):
+            assert np.array_equal(pha[k], phb[k]), (label, k)
+        assert np.array_equal(la, lb), label
+        print(f"field box {label}: {used}/{nb} blocks from the box, {pha['count']} photons",
+              flush=True)
+        if label == "sorted":
+            assert used > nb // 2
+        if label == "unsorted":
+            assert used == 0
 
 
 def test_step_zero_momentum_particles(sr, table, oracle):
