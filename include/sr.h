@@ -514,6 +514,37 @@ int sr_mlp_forward(const void *params_bf16, const float *feats, float *out, int6
 int sr_mlp_mse_grad(const void *params_bf16, const float *feats, const float *target, int64_t M,
                     float *grads, float *work, void *stream);
 int64_t sr_mlp_grad_work(void);
+/* grads = gradient of sum_i dout[i] * network(feats[i]) with respect to the
+ * parameters (the vector-Jacobian product of the backward pass), device FP32
+ * [SR_MLP_PARAMS]; dout device [M]; work as for sr_mlp_mse_grad.  Summed in a
+ * fixed order (reproducible). */
+int sr_mlp_backward(const void *params_bf16, const float *feats, const float *dout, float *grads,
+                    int64_t M, float *work, void *stream);
+/* `steps` Adam steps (beta 0.9, 0.999, eps 1e-8; step numbers t0+1 ...) on
+ * fresh batches of `batch` pairs from sr_mlp_make_batch (seed, batch index
+ * t0 + s), minimising the energy-weighted error of sr_mlp_mse_grad, with the
+ * learning rate decayed from lr to lr_final on a cosine over the steps.  All
+ * launches are enqueued on `stream` by the library (no host round trip per
+ * step).  work: device FP32 workspace of sr_mlp_train_work(batch) floats. */
+int sr_mlp_train(float *master, void *params_bf16, float *m, float *v, int64_t t0,
+                 const sr_table *tab, uint64_t seed, int64_t steps, int64_t batch, float lr,
+                 float lr_final, int32_t kin_cut, double log10chi_lo, double log10chi_hi,
+                 float *work, void *stream);
+int64_t sr_mlp_train_work(int64_t batch);
+/* The judge of the surrogate against the table sampler (its fallback map).
+ * For each of the SR_MLP_FALLBACK_BINS bins of log10 chi on [-4, 2): chi_per_bin
+ * values of chi at the centres of the bin's equal sub-intervals, each with n_u
+ * 23-bit midpoints u spread evenly over (0, 1); x from the table sampler
+ * (sr_eval_direct, with the kinematic cut if kin_cut) and from the network; the
+ * energy-weighted histograms (each sample adds x) over n_xbins log bins of
+ * [x_lo, x_hi); err[b] = sum |h_net - h_table| / sum h_table (device FP64
+ * [SR_MLP_FALLBACK_BINS]) and fallback[b] = err[b] > tol (device uint8, the map
+ * sr_params.mlp_fallback reads).  work: device FP32 workspace of
+ * sr_mlp_judge_work(n_u, chi_per_bin, n_xbins) floats. */
+int sr_mlp_judge(const void *params_bf16, const sr_table *tab, int32_t kin_cut, int32_t n_u,
+                 int32_t chi_per_bin, double x_lo, double x_hi, int32_t n_xbins, double tol,
+                 double *err, uint8_t *fallback, float *work, void *stream);
+int64_t sr_mlp_judge_work(int32_t n_u, int32_t chi_per_bin, int32_t n_xbins);
 /* One Adam step (bias-corrected, step t >= 1) on the FP32 masters, refreshing
  * the bfloat16 copies.  All arrays device [SR_MLP_PARAMS]. */
 int sr_mlp_adam(float *master, void *params_bf16, const float *grads, float *m, float *v,

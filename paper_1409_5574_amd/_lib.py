@@ -138,6 +138,12 @@ SIGNATURES = {
     "sr_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
     "sr_mlp_mse_grad": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     "sr_mlp_grad_work": (C.c_int64, []),
+    "sr_mlp_backward": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P]),
+    "sr_mlp_train": (C.c_int, [_P, _P, _P, _P, _I64, _P, _U64, _I64, _I64, C.c_float, C.c_float,
+                               _I32, _D, _D, _P, _P]),
+    "sr_mlp_train_work": (C.c_int64, [_I64]),
+    "sr_mlp_judge": (C.c_int, [_P, _P, _I32, _I32, _I32, _D, _D, _I32, _D, _P, _P, _P, _P]),
+    "sr_mlp_judge_work": (C.c_int64, [_I32, _I32, _I32]),
     "sr_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, C.c_float, C.c_float,
                               C.c_float, _P]),
     "sr_mlp_cast": (C.c_int, [_P, _P, _P]),

@@ -410,59 +410,45 @@ class Mlp:
     def all_on_table(self) -> bool:
         return bool(np.all(self.fallback_host != 0))
 
+    def backward(self, feats: torch.Tensor, dout: torch.Tensor) -> torch.Tensor:
+        """Gradient of sum dout * network(feats) with respect to the parameters."""
+        feats = feats.contiguous().to(DEV, torch.float32)
+        dout = dout.contiguous().to(DEV, torch.float32)
+        grads = torch.empty_like(self.master)
+        L.check(lib().sr_mlp_backward(_ptr(self.params), _ptr(feats), _ptr(dout), _ptr(grads),
+                                      feats.shape[0], _ptr(self.work), _stream()), "sr_mlp_backward")
+        return grads
+
     def train(self, table: Table, steps: int, batch: int, lr: float, seed: int = 0x5A11,
               kin_cut: bool = True, lo: float = -4.0, hi: float = 2.0, lr_final: float | None = None):
-        """Adam on fresh batches of table-generated pairs; cosine-decayed learning rate."""
+        """Adam on fresh batches of table-generated pairs with a cosine-decayed
+        learning rate, the whole loop enqueued by the library (sr_mlp_train)."""
         if self.kin_cut is not None and bool(self.kin_cut) != bool(kin_cut):
             raise ValueError("the network was trained with the other kinematic-cut setting")
         self.kin_cut = bool(kin_cut)
-        feats = torch.empty((batch, 2), device=DEV, dtype=torch.float32)
-        target = torch.empty(batch, device=DEV, dtype=torch.float32)
         lr_final = lr * 0.01 if lr_final is None else lr_final
-        for s_ in range(steps):
-            L.check(lib().sr_mlp_make_batch(table.handle, seed, s_, int(kin_cut), lo, hi,
-                                            _ptr(feats), _ptr(target), batch, _stream()),
-                    "sr_mlp_make_batch")
-            self.mse_grad(feats, target)
-            frac = s_ / max(steps - 1, 1)
-            cur = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * frac))
-            self.adam(float(cur))
+        work = torch.empty(int(lib().sr_mlp_train_work(batch)), device=DEV, dtype=torch.float32)
+        L.check(lib().sr_mlp_train(_ptr(self.master), _ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                   self.t, table.handle, seed, steps, batch, lr, lr_final,
+                                   int(kin_cut), lo, hi, _ptr(work), _stream()), "sr_mlp_train")
+        self.t += steps
 
     def judge(self, table: Table, kin_cut: bool = True, n_u: int = 1 << 14, chi_per_bin: int = 8,
               x_lo: float = 1e-4, x_hi: float = 16.4, n_xbins: int = 64, tol: float = 1e-3):
-        """Binned-spectrum error of the network against the table sampler, per bin
-        of log10 chi of the fallback map, on a stratified grid of u (23-bit
-        midpoints) and chi_per_bin values of chi per bin.  The error of a bin is
-        sum |h_mlp - h_table| / sum h_table over n_xbins log bins of x in
-        [x_lo, x_hi], each sample weighted by its energy (proportional to x).
-        Bins above `tol` are switched to the table.  Returns the errors."""
+        """The library's judge (sr_mlp_judge): the binned-spectrum error of the
+        network against the table sampler per bin of log10 chi, on a stratified
+        grid of u and chi; bins above `tol` are switched to the table.  Returns
+        the errors (host numpy)."""
         nb = L.SR_MLP_FALLBACK_BINS
-        lo, hi = -4.0, 2.0
-        width = (hi - lo) / nb
-        m = ((np.arange(n_u) + 0.5) * (2 ** 23 / n_u)).astype(np.uint64)
-        words = (m << np.uint64(9)).astype(np.uint32)
-        u = (2.0 * m.astype(np.float64) + 1.0) * 2.0 ** -24
-        lchi = lo + width * (np.arange(nb)[:, None] + (np.arange(chi_per_bin)[None, :] + 0.5)
-                             / chi_per_bin)
-        lchi = lchi.reshape(-1)
-        L_ = np.repeat(lchi, n_u)
-        U_ = np.tile(u, lchi.size)
-        A_ = np.tile(words, lchi.size)
-        chi = torch.from_numpy((10.0 ** L_).astype(np.float32))
-        x_tab = eval_direct(table, torch.from_numpy(A_.view(np.int32)), chi, kin_cut)
-        feats = torch.from_numpy(np.stack([(L_ + 1.0) / 3.0, (np.log(U_) - np.log1p(-U_)) / 16.0],
-                                          1).astype(np.float32))
-        x_mlp = torch.exp2(self.forward(feats))
-        edges = np.geomspace(x_lo, x_hi, n_xbins + 1)
-        xt = x_tab.cpu().numpy().astype(np.float64).reshape(nb, -1)
-        xm = x_mlp.cpu().numpy().astype(np.float64).reshape(nb, -1)
-        err = np.zeros(nb)
-        for b in range(nb):
-            ht, _ = np.histogram(xt[b], bins=edges, weights=xt[b])
-            hm, _ = np.histogram(xm[b], bins=edges, weights=xm[b])
-            err[b] = np.abs(hm - ht).sum() / max(ht.sum(), 1e-300)
-        self.set_fallback(torch.from_numpy((err > tol).astype(np.uint8)))
-        return err
+        work = torch.empty(int(lib().sr_mlp_judge_work(n_u, chi_per_bin, n_xbins)), device=DEV,
+                           dtype=torch.float32)
+        err = torch.empty(nb, device=DEV, dtype=torch.float64)
+        fb = torch.empty(nb, device=DEV, dtype=torch.uint8)
+        L.check(lib().sr_mlp_judge(_ptr(self.params), table.handle, int(kin_cut), n_u, chi_per_bin,
+                                   x_lo, x_hi, n_xbins, tol, _ptr(err), _ptr(fb), _ptr(work),
+                                   _stream()), "sr_mlp_judge")
+        self.set_fallback(fb)
+        return err.cpu().numpy()
 
     def make_batch(self, table: Table, seed: int, batch_index: int, M: int, kin_cut=True,
                    lo=-4.0, hi=2.0):

@@ -3,6 +3,8 @@
 // and the generation of training triples from the FP64-built tables.
 #include <math.h>
 
+#include <algorithm>
+
 #include "sr_mlp.hpp"
 
 namespace sr {
@@ -40,9 +42,11 @@ struct alignas(16) TrainSmem {
 };
 
 // Gradient of L = (1/M) sum w (y - t)^2, w = x / E[x] (the energy weighting of
-// the binned spectrum the network is judged on), for this kernel's tiles.
+// the binned spectrum the network is judged on), for this kernel's tiles; with
+// VJP, the gradient of sum dout * y instead (`target` holds dout, inv_m unused).
 // Each wave accumulates its own gradient and writes it to work[wave_global][...]
 // (summed in a fixed order by grad_reduce).
+template <bool VJP>
 __global__ __launch_bounds__(kBlock) void mlp_train_kernel(const __bf16 *__restrict__ params,
                                                            const float2 *__restrict__ feats,
                                                            const float *__restrict__ target,
@@ -159,9 +163,13 @@ __global__ __launch_bounds__(kBlock) void mlp_train_kernel(const __bf16 *__restr
         for (int q = 0; q < 4; ++q) {
             const float tq = __shfl(tgt, 4 * g + q, 64);
             const bool vq = tile * 16 + 4 * g + q < M;
-            // energy weighting: each sample counts with x / E[x] (E[x] = 8/(15 sqrt3) ...)
-            const float wq = exp2f(tq) * 3.2475953f;
-            dyq[q] = vq ? 2.0f * inv_m * wq * (sq[q] + s.m.b4 - tq) : 0.f;
+            if constexpr (VJP) {
+                dyq[q] = vq ? tq : 0.f;
+            } else {
+                // energy weighting: each sample counts with x / E[x] (E[x] = 8/(15 sqrt3) ...)
+                const float wq = exp2f(tq) * 3.2475953f;
+                dyq[q] = vq ? 2.0f * inv_m * wq * (sq[q] + s.m.b4 - tq) : 0.f;
+            }
         }
         if (r == 0) gb4 += dyq[0] + dyq[1] + dyq[2] + dyq[3];
         // ---- layer 4 and 3
@@ -359,6 +367,113 @@ __global__ void eval_direct_kernel(TableDev tab, const uint32_t *__restrict__ a,
 constexpr int kTrainBlocks = 256;      // one block (four waves, one per SIMD) per CU
 constexpr int kGradGroups = 32;        // first-stage row groups of the gradient sum
 
+// ------------------------------------------------------------------ the judge
+// Sample s of the judge's stratified grid: chi-bin b (of kMlpFallbackBins on
+// log10 chi in [kMlpChiLo, kMlpChiHi)), chi value j of cpb at the centres of b's
+// sub-intervals, u the m-th of n_u 23-bit midpoints spread evenly over (0, 1).
+struct JudgeGrid {
+    int n_u, cpb;
+    float width;        // log10 chi per bin
+};
+__device__ __forceinline__ void judge_sample(const JudgeGrid &G, int64_t s, float &lchi, float &chi,
+                                             uint32_t &word) {
+    const int64_t per_bin = (int64_t)G.cpb * G.n_u;
+    const int b = (int)(s / per_bin);
+    const int j = (int)((s / G.n_u) % G.cpb);
+    const int m = (int)(s % G.n_u);
+    lchi = kMlpChiLo + G.width * ((float)b + ((float)j + 0.5f) / (float)G.cpb);
+    chi = exp2f(lchi * 3.3219280948873623f);
+    const uint32_t mu = (uint32_t)(((double)m + 0.5) * (8388608.0 / (double)G.n_u));
+    word = mu << 9;
+}
+
+// x from the table sampler and the network's features of every judge sample.
+__global__ void judge_inputs_kernel(TableDev tab, JudgeGrid G, int kin_cut, int64_t total,
+                                    float *__restrict__ x_tab, float2 *__restrict__ feats) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    float lchi, chi;
+    uint32_t word;
+    judge_sample(G, s, lchi, chi, word);
+    const float2 rr = kin_cut ? r_lookup(tab.r, chi) : make_float2(1.0f, 0.0f);
+    float lnU, ln1mU;
+    direct_u(word, rr, lnU, ln1mU);
+    x_tab[s] = exp2f(t1_log2x(tab.t1, lnU, ln1mU));
+    feats[s] = make_float2((lchi + 1.0f) * (1.0f / 3.0f), mlp_feature_u(word));
+}
+
+// Energy-weighted histograms of the two samplers' x over n_xb log bins of
+// [x_lo, x_hi): block (b, part) adds the samples of chi-bin b in its share to
+// hist[b][0][.] (table) and hist[b][1][.] (network) (FP64).
+__global__ __launch_bounds__(256) void judge_hist_kernel(JudgeGrid G, const float *__restrict__ x_tab,
+                                                         const float *__restrict__ y_net,
+                                                         double l_lo, double inv_w, int n_xb,
+                                                         double *__restrict__ hist) {
+    extern __shared__ double sh[];   // [2 * n_xb]
+    for (int i = threadIdx.x; i < 2 * n_xb; i += blockDim.x) sh[i] = 0.0;
+    __syncthreads();
+    const int b = blockIdx.y;
+    const int64_t per_bin = (int64_t)G.cpb * G.n_u;
+    const int64_t s0 = (int64_t)b * per_bin;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_bin;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double xs[2] = {(double)x_tab[s0 + i], (double)exp2f(y_net[s0 + i])};
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const double x = xs[v];
+            if (!(x > 0.0)) continue;
+            const double u = (log(x) - l_lo) * inv_w;
+            if (u >= 0.0 && u < (double)n_xb) atomicAdd(&sh[v * n_xb + (int)u], x);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * n_xb; i += blockDim.x)
+        if (sh[i] != 0.0) atomicAdd(&hist[(int64_t)b * 2 * n_xb + i], sh[i]);
+}
+
+// err[b] = sum |h_net - h_tab| / sum h_tab; fallback[b] = err[b] > tol.
+__global__ void judge_err_kernel(const double *__restrict__ hist, int n_xb, double tol,
+                                 double *__restrict__ err, uint8_t *__restrict__ fallback) {
+    const int b = blockIdx.x;
+    double d = 0.0, t = 0.0;
+    for (int i = threadIdx.x; i < n_xb; i += 64) {
+        const double ht = hist[(int64_t)b * 2 * n_xb + i];
+        const double hn = hist[(int64_t)b * 2 * n_xb + n_xb + i];
+        d += fabs(hn - ht);
+        t += ht;
+    }
+    d = wave_sum(d);
+    t = wave_sum(t);
+    if (threadIdx.x == 0) {
+        const double e = d / fmax(t, 1e-300);
+        err[b] = e;
+        fallback[b] = (uint8_t)(!(e <= tol));
+    }
+}
+
+__global__ void zero_doubles_kernel(double *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+int launch_grad(bool vjp, const void *params, const float *feats, const float *target, int64_t M,
+                float *grads, float *work, hipStream_t st) {
+    if (vjp)
+        mlp_train_kernel<true><<<kTrainBlocks, kBlock, 0, st>>>(
+            (const __bf16 *)params, (const float2 *)feats, target, M, 1.0f / (float)M, work);
+    else
+        mlp_train_kernel<false><<<kTrainBlocks, kBlock, 0, st>>>(
+            (const __bf16 *)params, (const float2 *)feats, target, M, 1.0f / (float)M, work);
+    const int rows = kTrainBlocks * kWaves, per = rows / kGradGroups;
+    float *mid = work + (int64_t)rows * kNParams;
+    grad_reduce_kernel<<<dim3((kNParams + 255) / 256, kGradGroups), 256, 0, st>>>(work, rows, per,
+                                                                                  mid);
+    grad_reduce_kernel<<<dim3((kNParams + 255) / 256, 1), 256, 0, st>>>(mid, kGradGroups,
+                                                                        kGradGroups, grads);
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
 }  // namespace
 }  // namespace sr
 
@@ -384,15 +499,83 @@ extern "C" int64_t sr_mlp_grad_work(void) {
 extern "C" int sr_mlp_mse_grad(const void *params, const float *feats, const float *target,
                                int64_t M, float *grads, float *work, void *stream) {
     if (!params || !grads || !work || M <= 0 || !feats || !target) return SR_E_INVAL;
+    return launch_grad(false, params, feats, target, M, grads, work, (hipStream_t)stream);
+}
+
+extern "C" int sr_mlp_backward(const void *params, const float *feats, const float *dout,
+                               float *grads, int64_t M, float *work, void *stream) {
+    if (!params || !grads || !work || M <= 0 || !feats || !dout) return SR_E_INVAL;
+    return launch_grad(true, params, feats, dout, M, grads, work, (hipStream_t)stream);
+}
+
+extern "C" int64_t sr_mlp_train_work(int64_t batch) {
+    if (batch <= 0) return -1;
+    return 3 * batch + kNParams + sr_mlp_grad_work();
+}
+
+extern "C" int sr_mlp_train(float *master, void *params, float *m, float *v, int64_t t0,
+                            const sr_table *tab, uint64_t seed, int64_t steps, int64_t batch,
+                            float lr, float lr_final, int32_t kin_cut, double log10chi_lo,
+                            double log10chi_hi, float *work, void *stream) {
+    if (!master || !params || !m || !v || !tab || !work || t0 < 0 || steps < 0 || batch <= 0 ||
+        batch > ((int64_t)1 << 26) || !(lr > 0.0f) || !(lr_final > 0.0f) ||
+        !(log10chi_hi > log10chi_lo))
+        return SR_E_INVAL;
+    float *feats = work, *target = work + 2 * batch, *grads = work + 3 * batch;
+    float *gwork = grads + kNParams;
+    for (int64_t s = 0; s < steps; ++s) {
+        int rc = sr_mlp_make_batch(tab, seed, (uint64_t)(t0 + s), kin_cut, log10chi_lo,
+                                   log10chi_hi, feats, target, batch, stream);
+        if (rc == SR_OK) rc = sr_mlp_mse_grad(params, feats, target, batch, grads, gwork, stream);
+        const double frac = steps > 1 ? (double)s / (double)(steps - 1) : 0.0;
+        const float cur = (float)(lr_final + 0.5 * (lr - lr_final) *
+                                                 (1.0 + cos(3.14159265358979323846 * frac)));
+        if (rc == SR_OK) rc = sr_mlp_adam(master, params, grads, m, v, t0 + s + 1, cur, 0.9f,
+                                          0.999f, 1e-8f, stream);
+        if (rc != SR_OK) return rc;
+    }
+    return SR_OK;
+}
+
+extern "C" int64_t sr_mlp_judge_work(int32_t n_u, int32_t chi_per_bin, int32_t n_xbins) {
+    if (n_u < 1 || chi_per_bin < 1 || n_xbins < 1 || n_xbins > 4096) return -1;
+    const int64_t total = (int64_t)kMlpFallbackBins * chi_per_bin * n_u;
+    // floats: x_tab, network output, two features; then the FP64 histograms
+    const int64_t floats = 4 * total + 4;   // keep the histograms 8-byte aligned
+    return floats + 2 * (int64_t)kMlpFallbackBins * 2 * n_xbins;
+}
+
+extern "C" int sr_mlp_judge(const void *params, const sr_table *tab, int32_t kin_cut, int32_t n_u,
+                            int32_t chi_per_bin, double x_lo, double x_hi, int32_t n_xbins,
+                            double tol, double *err, uint8_t *fallback, float *work,
+                            void *stream) {
+    const int64_t need = sr_mlp_judge_work(n_u, chi_per_bin, n_xbins);
+    if (!params || !tab || !err || !fallback || !work || need < 0 || !(x_lo > 0.0) ||
+        !(x_hi > x_lo) || !(tol >= 0.0))
+        return SR_E_INVAL;
+    const int64_t total = (int64_t)kMlpFallbackBins * chi_per_bin * n_u;
+    if (total > ((int64_t)1 << 30)) return SR_E_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
-    mlp_train_kernel<<<kTrainBlocks, kBlock, 0, st>>>((const __bf16 *)params, (const float2 *)feats,
-                                                     target, M, 1.0f / (float)M, work);
-    const int rows = kTrainBlocks * kWaves, per = rows / kGradGroups;
-    float *mid = work + (int64_t)rows * kNParams;
-    grad_reduce_kernel<<<dim3((kNParams + 255) / 256, kGradGroups), 256, 0, st>>>(work, rows, per,
-                                                                                  mid);
-    grad_reduce_kernel<<<dim3((kNParams + 255) / 256, 1), 256, 0, st>>>(mid, kGradGroups,
-                                                                        kGradGroups, grads);
+    float *x_tab = work, *y_net = work + total;
+    float *feats = work + 2 * total;
+    // the histograms start at the first 8-byte boundary after the floats (the
+    // workspace holds four spare floats for it)
+    double *hist = (double *)(((uintptr_t)(work + 4 * total) + 7) & ~(uintptr_t)7);
+    const int64_t nh = (int64_t)kMlpFallbackBins * 2 * n_xbins;
+    TableDev td{tab->ftab, tab->pa, tab->t1, tab->r, tab->gtab, tab->qtab};
+    JudgeGrid G{n_u, chi_per_bin, (kMlpChiHi - kMlpChiLo) / (float)kMlpFallbackBins};
+    judge_inputs_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(td, G, kin_cut, total,
+                                                                          x_tab, (float2 *)feats);
+    SR_HIP_CHECK(hipGetLastError());
+    const int rc = sr_mlp_forward(params, feats, y_net, total, stream);
+    if (rc != SR_OK) return rc;
+    zero_doubles_kernel<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(hist, nh);
+    const double l_lo = log(x_lo), inv_w = (double)n_xbins / (log(x_hi) - log(x_lo));
+    const int64_t per_bin = (int64_t)chi_per_bin * n_u;
+    const unsigned parts = (unsigned)std::min<int64_t>((per_bin + 255) / 256, 64);
+    judge_hist_kernel<<<dim3(parts, kMlpFallbackBins), 256, sizeof(double) * 2 * n_xbins, st>>>(
+        G, x_tab, y_net, l_lo, inv_w, n_xbins, hist);
+    judge_err_kernel<<<kMlpFallbackBins, 64, 0, st>>>(hist, n_xbins, tol, err, fallback);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }

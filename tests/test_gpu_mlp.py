@@ -72,6 +72,30 @@ def test_mlp_gradients_match_oracle(sr):
         o += k
 
 
+def test_mlp_backward_matches_oracle(sr):
+    # the vector-Jacobian product of the backward pass: d(sum dout * y)/dparams
+    flat = omlp.bf16_round(omlp.init(7))
+    net = sr.Mlp(flat.astype(np.float32))
+    rng = np.random.default_rng(4)
+    M = 3001
+    f = rng.uniform(-1.2, 1.2, (M, 2)).astype(np.float32)
+    dout = rng.normal(0.0, 1.0, M).astype(np.float32)
+    _say("mlp backward 3001")
+    g = net.backward(torch.from_numpy(f), torch.from_numpy(dout)).cpu().numpy()
+    ref = omlp.backward(flat, f.astype(np.float64), dout.astype(np.float64))
+    cos = float(g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref)))
+    assert cos > 0.999, cos
+    o = 0
+    for name, shape in omlp.SIZES:
+        k = int(np.prod(shape))
+        gg, rr = g[o:o + k], ref[o:o + k]
+        assert np.abs(gg - rr).max() <= 2e-2 * np.abs(rr).max() + 1e-12, name
+        o += k
+
+
+TRAIN_STEPS = 150_000
+
+
 @pytest.fixture(scope="module")
 def trained(sr, table):
     net = sr.Mlp(omlp.init(11).astype(np.float32))
@@ -79,12 +103,13 @@ def trained(sr, table):
     w = torch.exp2(target) / (8.0 / (15.0 * math.sqrt(3.0)))
     y0 = net.forward(feats)
     loss0 = float((w * (y0 - target) ** 2).mean())
-    _say("mlp training 4000 x 65536")
+    _say(f"mlp training {TRAIN_STEPS} x 65536")
     import time
     t0 = time.perf_counter()
-    net.train(table, steps=4000, batch=1 << 16, lr=3e-3)
+    net.train(table, steps=TRAIN_STEPS, batch=1 << 16, lr=2e-3)
     torch.cuda.synchronize()
-    print(f"mlp training: {time.perf_counter() - t0:.2f} s for 4000 x 65536 samples", flush=True)
+    print(f"mlp training: {time.perf_counter() - t0:.2f} s for {TRAIN_STEPS} x 65536 samples",
+          flush=True)
     torch.cuda.synchronize()
     y1 = net.forward(feats)
     loss1 = float((w * (y1 - target) ** 2).mean())
@@ -96,10 +121,66 @@ def trained(sr, table):
     return net, loss0, loss1, err
 
 
+def test_table_sampler_against_oracle_inverse_cdf(sr, table, oracle):
+    # the table sampler (the surrogate's judge and fallback) against the oracle's
+    # inverse number-CDF, with and without the kinematic cut
+    rng = np.random.default_rng(12)
+    n = 600
+    a = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    chi = (10.0 ** rng.uniform(-4.0, 1.5, n)).astype(np.float32)
+    u = ((a >> 9).astype(np.float64) + 0.5) / 2 ** 23
+    for cut in (False, True):
+        _say(f"table sampler vs oracle, cut={cut}")
+        x = sr.eval_direct(table, torch.from_numpy(a.view(np.int32)), torch.from_numpy(chi),
+                           cut).cpu().numpy().astype(np.float64)
+        ref = np.array([oracle.inv_number_cdf(float(c), float(uu), cut)
+                        for c, uu in zip(chi.astype(np.float64), u)])
+        keep = ref > 1e-5          # below: far under any photon energy that counts
+        rel = np.abs(x[keep] / ref[keep] - 1)
+        print(f"table sampler cut={cut}: max rel {rel.max():.2e}, median {np.median(rel):.2e}",
+              flush=True)
+        assert rel.max() <= 2e-5
+
+
 def test_mlp_training_reduces_loss(trained):
     net, loss0, loss1, err = trained
     assert loss1 < loss0 / 20
     assert np.all(np.isfinite(err))
+    # the trained network serves some chi bins within the 1e-3 spectrum bar
+    assert (err <= 1e-3).sum() >= 1, err
+    assert np.array_equal(net.fallback_host, (err > 1e-3).astype(np.uint8))
+
+
+def test_judge_matches_host_binning(sr, table, trained):
+    """The library's judge against the same statistic computed here from the
+    two samplers' x on the judge's grid (sr_eval_direct, sr_mlp_forward) and
+    numpy histograms."""
+    net, _, _, err = trained
+    n_u, cpb, nbx, lo, hi = 1 << 12, 4, 64, 1e-4, 16.4
+    err_dev = net.judge(table, n_u=n_u, chi_per_bin=cpb)
+    nb = 24
+    m = ((np.arange(n_u) + 0.5) * (2 ** 23 / n_u)).astype(np.uint64)
+    words = (m << np.uint64(9)).astype(np.uint32)
+    u = (2.0 * m.astype(np.float64) + 1.0) * 2.0 ** -24
+    lchi = (-4.0 + 0.25 * (np.arange(nb)[:, None] + (np.arange(cpb)[None, :] + 0.5) / cpb))
+    lchi = lchi.astype(np.float32).reshape(-1)
+    L_ = np.repeat(lchi, n_u)
+    chi = torch.from_numpy(np.exp2(L_ * np.float32(3.3219280948873623)).astype(np.float32))
+    x_tab = sr.eval_direct(table, torch.from_numpy(np.tile(words, lchi.size).view(np.int32)), chi,
+                           True).cpu().numpy().astype(np.float64).reshape(nb, -1)
+    f0 = ((L_ + np.float32(1.0)) * np.float32(1.0 / 3.0)).astype(np.float32)
+    f1 = np.tile(((np.log2(u) - np.log2(1 - u)) * (math.log(2) / 16)).astype(np.float32), lchi.size)
+    y = net.forward(torch.from_numpy(np.stack([f0, f1], 1))).cpu().numpy()
+    x_net = np.exp2(y.astype(np.float64)).reshape(nb, -1)
+    edges = np.geomspace(lo, hi, nbx + 1)
+    ref = np.zeros(nb)
+    for b in range(nb):
+        ht, _ = np.histogram(x_tab[b], bins=edges, weights=x_tab[b])
+        hn, _ = np.histogram(x_net[b], bins=edges, weights=x_net[b])
+        ref[b] = np.abs(hn - ht).sum() / ht.sum()
+    # the host recomputes the same statistic; FP32 features may differ by an ulp
+    np.testing.assert_allclose(err_dev, ref, rtol=0.05, atol=2e-5)
+    net.judge(table)    # restore the map of the default judge
 
 
 def test_step_mlp_sampler_against_oracle(sr, table, oracle, trained):
@@ -163,8 +244,9 @@ def test_step_network_path_matches_standalone_forward(sr, table, oracle, trained
     saved = net.fallback.clone()
     net.set_fallback(torch.zeros_like(saved))
     try:
-        cfg = synth.config("c1", b0=(0.0, 0.0, 40.0), gamma_range=(1e3, 1e4))
-        n, K, seed, step = 5000, 4, 91, 2
+        # chi from 5e-4 to 45 (gamma 5 ... 1e4 in B = 200): most chi bins
+        cfg = synth.config("c1", b0=(0.0, 0.0, 200.0), gamma_range=(5.0, 1e4))
+        n, K, seed, step = 30000, 8, 91, 2
         st = synth.gen_particles(cfg, n=n)
         orc = {k: (v.astype(np.float64) if v.dtype != np.uint32 else v.copy()) for k, v in st.items()}
         orc["x"] = orc["y"] = orc["z"] = None
@@ -196,11 +278,29 @@ def test_step_network_path_matches_standalone_forward(sr, table, oracle, trained
         rel = np.abs(x_gpu / np.exp2(y) - 1.0)
         # chi enters through binary32 on both sides; x is smooth in chi
         assert np.quantile(rel, 0.99) < 1e-4, rel.max()
-        # and the network's samples agree with the exact inverse CDF as well as
-        # the judge said they would
+        # and the network's samples agree with the oracle's exact inverse CDF
+        # as the judge said they would: on the chi bins it admitted, the
+        # energy-weighted spectrum of these photons (64 log bins of x on
+        # [1e-4, 16.4]) within the 1e-3 bar
         x_exact = det["xs"][s]
+        rel_x = np.abs(x_gpu / x_exact - 1)
+        b = np.floor((np.log10(chi) + 4.0) / 0.25).astype(int)
+        admitted = (b >= 0) & (b < 24) & (err[np.clip(b, 0, 23)] <= 1e-3)
+        edges = np.geomspace(1e-4, 16.4, 65)
+        he, _ = np.histogram(x_exact[admitted], bins=edges, weights=x_exact[admitted])
+        hn, _ = np.histogram(x_gpu[admitted], bins=edges, weights=x_gpu[admitted])
+        spec = float(np.abs(hn - he).sum() / max(he.sum(), 1e-300))
         print(f"network path: {x_gpu.size} photons, median |x/x_exact - 1| "
-              f"{np.median(np.abs(x_gpu / x_exact - 1)):.2e}", flush=True)
+              f"{np.median(rel_x):.2e}; admitted bins: {int(admitted.sum())} photons, spectrum "
+              f"error vs the oracle {spec:.2e}", flush=True)
+        assert admitted.sum() > 1000
+        assert np.median(rel_x[admitted]) <= 1e-3
+        # The judge bounds the spectrum error on its dense stratified grid
+        # (network vs table, and the table follows the oracle's inverse CDF to
+        # ~1e-6: test_table_sampler_against_oracle_inverse_cdf); one step's ~10^4
+        # photons fill 64 bins sparsely, and the migration across bin edges then
+        # cancels less, so the same network reads somewhat higher here.
+        assert spec <= 2e-3
     finally:
         net.set_fallback(saved)
 
@@ -276,7 +376,7 @@ def test_sampler_speed_and_spectrum(sr, table, trained):
     # the decision of a direct sampler does not depend on x: identical counts
     assert res["mlp_network"]["photons"] == ref["photons"]
     assert res["mlp_direct"]["photons"] == ref["photons"]
-    assert res["mlp_direct"]["spec_err"] <= 2e-3
+    assert res["mlp_direct"]["spec_err"] <= 1e-3
     # the S proposal draws different numbers: agreement within Monte-Carlo noise
     assert res["s_proposal"]["emitted"] == pytest.approx(ref["emitted"], rel=2e-2)
     assert res["s_proposal"]["ll"] == pytest.approx(ref["ll"], rel=1e-6)
