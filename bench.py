@@ -478,14 +478,40 @@ def c1_leg(args) -> dict:
     t0 = time.perf_counter()
     g.replay()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rows = ledger.rows.cpu().numpy()
+    wall_graph = time.perf_counter() - t0
     del g
+    # the whole run as one launch (sr_gather_push_emit_steps): state in registers
+    parts1 = api.Particles.from_numpy(st, dim=0)
+    parts1.x = [None, None, None]
+    photons1 = api.PhotonBuffer(n, 4, dim=3, with_step=True)
+    ledger1 = api.LedgerBuf(steps, api.n_chunks_uniform(n), steps_per_call=steps)
+    api.gather_push_emit_steps(parts1, grid, cfg.dt, 0xC1, 0, steps, prm, table, photons1, ledger1)
+    torch.cuda.synchronize()
+    times = []
+    for rep in range(3):
+        for d, s_ in zip(parts1.p, [torch.from_numpy(st[k]).cuda() for k in ("px", "py", "pz")]):
+            d.copy_(s_)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        api.gather_push_emit_steps(parts1, grid, cfg.dt, 0xC1, 0, steps, prm, table, photons1,
+                                   ledger1)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0, ev0.elapsed_time(ev1)))
+    wall = float(np.median([t[0] for t in times]))
+    kms = float(np.median([t[1] for t in times]))
+    rows = ledger1.rows.cpu().numpy()
     table.free()
+    # VALU work of the launch: instructions per wave-step from the kernel's
+    # counter profile (committed summary), if present
     return {"workload": f"{cfg.name}: {n} electrons, uniform B = 1 (1e5 T), {steps} steps, K=1, "
-                        f"photon recoil, as one HIP graph",
+                        f"photon recoil, all steps in one launch (sr_gather_push_emit_steps)",
             "particle_steps_per_s": n * steps / wall, "ms_per_run": wall * 1e3,
-            "us_per_step": wall * 1e6 / steps,
+            "launch_ms": kms, "us_per_step": wall * 1e6 / steps,
+            "per_step_launches_as_graph": {"particle_steps_per_s": n * steps / wall_graph,
+                                           "ms_per_run": wall_graph * 1e3},
             "photons_per_run": float(rows[:, L.SR_LED_PHOTONS].sum()),
             "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300))}
 

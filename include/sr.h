@@ -420,6 +420,24 @@ int sr_gather_push_emit_noalloc(sr_particles_f32 *parts, const sr_fields_f32 *fi
                                 const sr_chunking *chunks, sr_photon_buf *photons,
                                 double *ledger_row, uint32_t *status, void *stream);
 
+/* n_steps steps of sr_gather_push_emit in one launch for uniform fields (grid->dim
+ * == 0, SR_E_UNSUPPORTED otherwise; uniform chunks; proposal, table or quantum
+ * sampler; no grid floor): every particle stays in registers across the steps
+ * (step numbers step0 .. step0 + n_steps - 1 key the random streams), and the
+ * ledger of step step0 + s goes to ledger->rows[s] (n_rows >= n_steps), summed
+ * in a fixed order, with the condition bits latched into *ledger->status.  The
+ * photon segments are shared by all the steps of the call: chunk c's
+ * seg_count[c] counts the photons of every step, photons->step (if not NULL)
+ * receives each record's step, and a photon beyond the segment counts as
+ * dropped in its step's row.  ledger->partials: sr_ledger_partials_steps(
+ * n_chunks, n_steps) doubles.  The uniform-field case of section "Comparison
+ * and benchmarking" (a particle in a constant magnetic field). */
+int sr_gather_push_emit_steps(sr_particles_f32 *parts, const sr_grid *grid, double dt, uint64_t seed,
+                              uint64_t step0, int64_t n_steps, const sr_params *prm,
+                              const sr_table *tab, sr_photon_buf *photons, sr_ledger *ledger,
+                              void *stream);
+int64_t sr_ledger_partials_steps(int64_t n_chunks, int64_t n_steps);
+
 /* Sum the partial rows a step over n_chunks chunks wrote into ledger->rows[row]
  * (FP64, fixed order, so the result is reproducible; column SR_LED_CHI_MAX is
  * a maximum) and OR the step's condition bits into *ledger->status.  The

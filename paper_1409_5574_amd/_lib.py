@@ -117,6 +117,10 @@ SIGNATURES = {
                                               C.POINTER(Grid), _D, _U64, _U64,
                                               C.POINTER(Params), _P, C.POINTER(Chunking),
                                               C.POINTER(PhotonBuf), _P, _P, _P]),
+    "sr_gather_push_emit_steps": (C.c_int, [C.POINTER(Particles32), C.POINTER(Grid), _D, _U64,
+                                            _U64, _I64, C.POINTER(Params), _P,
+                                            C.POINTER(PhotonBuf), C.POINTER(Ledger), _P]),
+    "sr_ledger_partials_steps": (C.c_int64, [_I64, _I64]),
     "sr_ledger_reduce": (C.c_int, [C.POINTER(Ledger), _I64, _I64, _P]),
     "sr_ledger_partials": (C.c_int64, [_I64]),
     "sr_energy_ledger": (C.c_int, [C.POINTER(Ledger), _I64, _P, _P]),

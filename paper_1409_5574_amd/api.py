@@ -282,9 +282,13 @@ class PhotonBuffer:
 
 
 class LedgerBuf:
-    def __init__(self, n_rows: int, n_chunks: int):
+    def __init__(self, n_rows: int, n_chunks: int, steps_per_call: int = 1):
+        """Ledger rows and partials; steps_per_call > 1 sizes the partials for
+        sr_gather_push_emit_steps with that many steps."""
         self.rows = torch.zeros((max(n_rows, 1), L.SR_LEDGER_COLS), device=DEV, dtype=torch.float64)
         plen = int(lib().sr_ledger_partials(n_chunks))
+        if steps_per_call > 1:
+            plen = max(plen, int(lib().sr_ledger_partials_steps(n_chunks, steps_per_call)))
         self.partials = torch.zeros(max(plen, 1), device=DEV, dtype=torch.float64)
         self.status = torch.zeros(1, device=DEV, dtype=torch.int32)
         self.n_rows = n_rows
@@ -487,6 +491,21 @@ def gather_push_emit(parts: Particles, fields: Fields | None, grid: L.Grid, dt: 
     L.check(rc, "sr_gather_push_emit")
     if row is not None:
         ledger_reduce(ledger, cs.n_chunks, row, ls)
+
+
+def gather_push_emit_steps(parts: Particles, grid: L.Grid, dt: float, seed: int, step0: int,
+                           n_steps: int, prm: L.Params, table: Table, photons: PhotonBuffer,
+                           ledger: "LedgerBuf", structs: tuple | None = None):
+    """n_steps emission steps in one launch (uniform fields): ledger rows
+    0 .. n_steps-1 receive the steps step0 ...; the photon segments hold the
+    photons of every step (with their step index if the buffer has one)."""
+    if structs is None:
+        structs = make_structs(parts, None, photons, ledger)
+    ps, _, _, phs, ls = structs
+    L.check(lib().sr_gather_push_emit_steps(C.byref(ps), C.byref(grid), float(dt),
+                                            seed & 0xFFFFFFFFFFFFFFFF, int(step0), int(n_steps),
+                                            C.byref(prm), table.handle, C.byref(phs), C.byref(ls),
+                                            _stream()), "sr_gather_push_emit_steps")
 
 
 def gather_push_emit_noalloc(parts: Particles, fields: Fields | None, grid: L.Grid, dt: float,

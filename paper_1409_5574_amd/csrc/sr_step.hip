@@ -1025,6 +1025,203 @@ __global__ __launch_bounds__(kBlock) void epilogue_second_kernel(
     hist_reduce_value(work, nb_hist, nvals, hist, (int)blockIdx.x - led_blocks);
 }
 
+// ---------------------------------------------------------------------------
+// Many steps in one launch in a uniform field (no grid): every particle's state
+// stays in registers across the steps, one wave per block.  Per step: the push
+// and H_eff (eq:effective_H), the K trials of section "Monte Carlo method",
+// photon append into the chunk's segment (shared by all the steps of the
+// launch, each record tagged with its step), recoil and position; each wave
+// writes one partial ledger row per step (partials[s][wave]), which
+// steps_reduce_kernel sums per step in a fixed order.
+template <int KMAX, int SAMPLER>
+__global__ __launch_bounds__(64) void push_emit_steps_kernel(const StepArgs<float> a,
+                                                             int64_t n_steps) {
+    const int lane = threadIdx.x;
+    const uint32_t c = blockIdx.x;                      // chunk = wave = block
+    const uint32_t s0 = c * (uint32_t)kChunk;
+    const uint32_t e0 = min(s0 + (uint32_t)kChunk, (uint32_t)a.n);
+    const uint32_t i = s0 + lane;
+    const bool active = i < e0;
+    const uint32_t pp = (uint32_t)a.per_particle;
+    const uint32_t seg_base = s0 * pp, seg_cap = (e0 - s0) * pp;
+    const PhotonOut P = cold_args<float>();
+    const int K = a.K;
+    const float invK = 1.0f / (float)K;
+    const int64_t nb = gridDim.x;
+
+    float wi = 0.0f, pos[3] = {0.0f, 0.0f, 0.0f}, p[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t pid = 0;
+    if (active) {
+        wi = ld(a.w, i);
+        pid = ld(a.id, i);
+        if (a.has_pos) {
+            pos[0] = ld(a.x[0], i);
+            if (a.x[1]) pos[1] = ld(a.x[1], i);
+            if (a.x[2]) pos[2] = ld(a.x[2], i);
+        }
+        p[0] = ld(a.p[0], i); p[1] = ld(a.p[1], i); p[2] = ld(a.p[2], i);
+    }
+    const float E[3] = {a.g.e0[0], a.g.e0[1], a.g.e0[2]};
+    const float B[3] = {a.g.b0[0], a.g.b0[1], a.g.b0[2]};
+    uint32_t run_base = 0;
+    for (int64_t si = 0; si < n_steps; ++si) {
+        const uint32_t step = a.step + (uint32_t)si;
+        double acc_emit = 0.0, acc_ll = 0.0, acc_de = 0.0, acc_clamp = 0.0, acc_drop = 0.0;
+        float chif = 0.0f, eps_unit = 0.0f, Hf = 0.0f, dirf[3] = {0.0f, 0.0f, 0.0f};
+        float pn[3] = {p[0], p[1], p[2]}, gb = 1.0f, g_new = 1.0f, p2 = 0.0f, pbm = 0.0f,
+              chi = 0.0f;
+        uint32_t flags = 0;
+        bool bad = false;
+        if (active) {
+            const Pushed<float> q = push_fields<float>(a, p, E, B);
+            pn[0] = q.pn[0]; pn[1] = q.pn[1]; pn[2] = q.pn[2];
+            p2 = q.p2; gb = q.gb; g_new = q.g_new; pbm = q.pbm; chi = q.chi;
+            Hf = q.H;
+            chif = q.chi;
+            bad = q.bad;
+            if (bad) flags |= SR_W_NONFINITE;
+            if (pbm > 0.0f) {
+                const float inv = rcp_r<float>(pbm);
+                dirf[0] = q.pb[0] * inv; dirf[1] = q.pb[1] * inv; dirf[2] = q.pb[2] * inv;
+            }
+            eps_unit = 1.5f * chif * gb;
+        }
+        float delta_ph = 0.0f;
+        uint32_t wave_tot = 0;
+        float2 rr = make_float2(1.0f, 0.0f);
+        if (SAMPLER == SR_SAMPLER_TABLE && active && a.kin_cut) rr = r_lookup(a.tab.r, chif);
+        constexpr bool kProposal = SAMPLER == SR_SAMPLER_S || SAMPLER == SR_SAMPLER_QUANTUM;
+        const float rate = !active ? 0.0f : (kProposal ? a.rate_c * Hf : a.direct_c * Hf * rr.x);
+        const TrialCut cut = trial_cut(SAMPLER == SR_SAMPLER_S && a.kin_cut != 0, chif);
+        uint4 words = make_uint4(0, 0, 0, 0);
+        for (int k = 0; k < KMAX; ++k) {
+            if (k >= K) break;
+            if ((k & 1) == 0)
+                words = philox4x32_10(make_uint4(pid, step, (uint32_t)(k >> 1), 0u), a.seed_lo,
+                                      a.seed_hi);
+            const uint32_t wa = (k & 1) ? words.z : words.x;
+            const uint32_t wb = (k & 1) ? words.w : words.y;
+            float dn = rate, lg = 0.0f, xq = 0.0f;
+            bool lower = true;
+            if (SAMPLER == SR_SAMPLER_S) {
+                dn = rate * trial_q(wa, a.tab.gtab, a.tab.pa, lg, lower);
+                if (trial_is_cut(cut, lg, lower)) dn = 0.0f;
+            } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
+                dn = rate * quantum_q(wa, a.tab.qtab, a.tab.pa, chif, xq);
+            }
+            bool emit;
+            float frac = invK;
+            if (dn >= 1.0f) {
+                emit = true;
+                if (a.dn_policy == SR_DN_WEIGHT) frac = dn * invK;
+            } else {
+                emit = wb < (uint32_t)(dn * 4294967296.0f);
+            }
+            const uint64_t m = __ballot(emit);
+            if (m) {
+                if (emit) {
+                    float x;
+                    if (SAMPLER == SR_SAMPLER_S) {
+                        x = trial_x(wa, lg, lower);
+                    } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
+                        x = xq;
+                    } else {
+                        float lnU, ln1mU;
+                        direct_u(wa, rr, lnU, ln1mU);
+                        x = __builtin_amdgcn_exp2f(t1_log2x(a.tab.t1, lnU, ln1mU));
+                    }
+                    const float eps = eps_unit * x;
+                    const float wph = wi * frac;
+                    delta_ph += frac * eps;
+                    const uint32_t slot = run_base + wave_tot + lane_prefix(m);
+                    if (slot < seg_cap) {
+                        store_photon(P, seg_base + slot, eps, wph, dirf, pos, pid, (uint32_t)k, step);
+                    } else {
+                        acc_drop += (double)wph * (double)eps;
+                        flags |= SR_W_PHOTON_OVERFLOW;
+                    }
+                }
+                wave_tot += (uint32_t)__popcll(m);
+            }
+        }
+        float acc_w = 0.0f;
+        if (active) {
+            acc_emit = (double)wi * (double)delta_ph;
+            const float beta2 = p2 * rcp_r<float>(gb * gb);
+            if (!bad) acc_ll = (double)(wi * a.ll_c * chi * chi * beta2);
+            float delta = 0.0f;
+            if (a.recoil == SR_RECOIL_PHOTON) delta = delta_ph;
+            else if (a.recoil == SR_RECOIL_LL) delta = a.ll_c * chi * chi * pbm * rcp_r<float>(gb);
+            float g_after = g_new;
+            if (delta > 0.0f) {
+                const float pm = sqrt_r<float>(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+                float fac = pm > 0.0f ? 1.0f - delta * rcp_r<float>(pm) : -1.0f;
+                float removed = delta;
+                if (fac < 0.0f) {
+                    acc_clamp = (double)(wi * (delta - pm));
+                    removed = pm;
+                    fac = 0.0f;
+                    flags |= SR_W_RECOIL_CLAMP;
+                }
+                pn[0] *= fac; pn[1] *= fac; pn[2] *= fac;
+                const float pm_after = fac * pm;
+                g_after = sqrt_r<float>(1.0f + pm_after * pm_after);
+                acc_de = (double)(-wi * removed * (pm_after + pm) * rcp_r<float>(g_after + g_new));
+            }
+            if (!(isfinite(pn[0]) && isfinite(pn[1]) && isfinite(pn[2]))) flags |= SR_W_NONFINITE;
+            if (a.push_position && a.has_pos) {
+                const float vdt = a.dt * rcp_r<float>(g_after);
+                pos[0] += vdt * pn[0]; pos[1] += vdt * pn[1]; pos[2] += vdt * pn[2];
+            }
+            p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+            acc_w = wi;
+        }
+        run_base += wave_tot;
+        // this wave's partial ledger row of the step (fixed-order wave sums)
+        const double se = wave_sum(acc_emit), sl = wave_sum(acc_ll), sd = wave_sum(acc_de);
+        const double sc = __ballot(acc_clamp != 0.0) ? wave_sum(acc_clamp) : 0.0;
+        const double sdr = __ballot(acc_drop != 0.0) ? wave_sum(acc_drop) : 0.0;
+        const float sw = wave_sum_f(acc_w), cm = wave_max(chif);
+        uint32_t wf = 0;
+        if (__ballot(flags != 0)) {
+            wf = flags;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) wf |= (uint32_t)__shfl_xor((int)wf, o, 64);
+        }
+        if (lane == 0) {
+            double *row = P.partials + (si * nb + c) * kPartCols;
+            row[SR_LED_EMITTED] = se;
+            row[SR_LED_LL] = sl;
+            row[SR_LED_RECOIL] = sd;
+            row[SR_LED_CLAMPED] = sc;
+            row[SR_LED_DROPPED] = sdr;
+            row[SR_LED_PHOTONS] = (double)wave_tot;
+            row[SR_LED_WEIGHT] = (double)sw;
+            row[SR_LED_CHI_MAX] = (double)cm;
+            row[kPartFlags] = (double)wf;
+            row[kPartFlags + 1] = 0.0;
+        }
+    }
+    if (active) {
+        st(a.p[0], i, p[0]); st(a.p[1], i, p[1]); st(a.p[2], i, p[2]);
+        if (a.push_position && a.has_pos) {
+            st(a.x[0], i, pos[0]);
+            if (a.x[1]) st(a.x[1], i, pos[1]);
+            if (a.x[2]) st(a.x[2], i, pos[2]);
+        }
+    }
+    if (lane == 0) P.seg_count[c] = run_base;
+}
+
+// Ledger row s of a multi-step launch: the nb partial rows of step s, summed in
+// a fixed order, with the condition bits latched into *status.
+__global__ __launch_bounds__(kBlock) void steps_reduce_kernel(const double *__restrict__ partials,
+                                                              int64_t nb, double *__restrict__ rows,
+                                                              uint32_t *__restrict__ status) {
+    const int64_t s = blockIdx.x;
+    ledger_sum_block(partials + s * nb * kPartCols, 0, nb, rows + s * SR_LEDGER_COLS, status);
+}
+
 void split_inv(double dx, float &hi, float &lo) {
     const double inv = 1.0 / dx;
     hi = (float)inv;
@@ -1097,12 +1294,11 @@ int particle_args(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid
 }
 
 template <typename R, typename PARTS>
-int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
-                uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
-                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream,
-                void *ev_start = nullptr, void *ev_stop = nullptr) {
+int prepare_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                 uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
+                 const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, bool one_step,
+                 StepArgs<R> &a, int64_t &n_chunks_out) {
     if (!parts || !grid || !prm || !tab || !chunks || !ph || !led) return SR_E_INVAL;
-    StepArgs<R> a;
     const int rc = particle_args<R>(parts, fields, grid, dt, prm, a);
     if (rc != SR_OK) return rc;
     const int64_t n = parts->n;
@@ -1128,8 +1324,8 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
         (!ph->eps || !ph->w || !ph->dir[0] || !ph->dir[1] || !ph->dir[2] || !ph->parent))
         return SR_E_INVAL;
     if (!led->partials || !led->status) return SR_E_INVAL;
-    if (led->partials_len < sr_ledger_partials(n_chunks)) return SR_E_INVAL;
-    if (n_chunks == 0) return SR_OK;
+    if (one_step && led->partials_len < sr_ledger_partials(n_chunks)) return SR_E_INVAL;
+    n_chunks_out = n_chunks;
 
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
@@ -1158,6 +1354,22 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
     a.ph.k = ph->k;
     a.ph.step = ph->step;
     a.ph.partials = led->partials;
+    return SR_OK;
+}
+
+template <typename R, typename PARTS>
+int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, double dt,
+                uint64_t seed, uint64_t step, const sr_params *prm, const sr_table *tab,
+                const sr_chunking *chunks, sr_photon_buf *ph, sr_ledger *led, void *stream,
+                void *ev_start = nullptr, void *ev_stop = nullptr) {
+    StepArgs<R> a;
+    int64_t n_chunks = 0;
+    const int rc = prepare_step<R>(parts, fields, grid, dt, seed, step, prm, tab, chunks, ph, led,
+                                   true, a, n_chunks);
+    if (rc != SR_OK) return rc;
+    if (n_chunks == 0) return SR_OK;
+    const int dim = grid->dim;
+    const int K = prm->n_samples;
 
     hipStream_t st = (hipStream_t)stream;
     const dim3 grd((unsigned)partial_rows(n_chunks)), blk(kBlock);
@@ -1202,6 +1414,51 @@ int launch_step(PARTS *parts, const sr_fields_f32 *fields, const sr_grid *grid, 
 #undef SR_BY_DIM
 #undef SR_BY_K
 #undef SR_LAUNCH
+    SR_HIP_CHECK(hipGetLastError());
+    return SR_OK;
+}
+
+// Ledger partials for a multi-step launch over n_chunks chunks (doubles).
+inline int64_t steps_partials(int64_t n_chunks, int64_t n_steps) {
+    return n_steps * n_chunks * kPartCols;
+}
+
+int launch_steps(sr_particles_f32 *parts, const sr_grid *grid, double dt, uint64_t seed,
+                 uint64_t step0, int64_t n_steps, const sr_params *prm, const sr_table *tab,
+                 sr_photon_buf *ph, sr_ledger *led, void *stream) {
+    if (!parts || !grid || !prm || !tab || !ph || !led) return SR_E_INVAL;
+    if (n_steps < 1 || n_steps > 0x7FFFFFFF) return SR_E_INVAL;
+    if (grid->dim != 0) return SR_E_UNSUPPORTED;      // uniform fields only
+    if (prm->sampler == SR_SAMPLER_MLP || prm->omega_grid != 0.0) return SR_E_UNSUPPORTED;
+    const sr_chunking chunks{(parts->n + kChunk - 1) / kChunk, nullptr};
+    StepArgs<float> a;
+    int64_t n_chunks = 0;
+    const int rc = prepare_step<float>(parts, nullptr, grid, dt, seed, step0, prm, tab, &chunks,
+                                       ph, led, false, a, n_chunks);
+    if (rc != SR_OK) return rc;
+    if (!led->rows || led->n_rows < n_steps) return SR_E_INVAL;
+    if (led->partials_len < steps_partials(n_chunks, n_steps)) return SR_E_INVAL;
+    if (n_chunks == 0) return SR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int K = prm->n_samples;
+    const int KM = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : 16;
+    const unsigned nb = (unsigned)n_chunks;
+#define SR_STEPS(KMV, SMP) push_emit_steps_kernel<KMV, SMP><<<nb, 64, 0, st>>>(a, n_steps)
+#define SR_STEPS_K(SMP)                      \
+    switch (KM) {                            \
+        case 1: SR_STEPS(1, SMP); break;     \
+        case 2: SR_STEPS(2, SMP); break;     \
+        case 4: SR_STEPS(4, SMP); break;     \
+        case 8: SR_STEPS(8, SMP); break;     \
+        default: SR_STEPS(16, SMP); break;   \
+    }
+    if (prm->sampler == SR_SAMPLER_S) { SR_STEPS_K(SR_SAMPLER_S); }
+    else if (prm->sampler == SR_SAMPLER_TABLE) { SR_STEPS_K(SR_SAMPLER_TABLE); }
+    else { SR_STEPS_K(SR_SAMPLER_QUANTUM); }
+#undef SR_STEPS_K
+#undef SR_STEPS
+    steps_reduce_kernel<<<(unsigned)n_steps, kBlock, 0, st>>>(led->partials, (int64_t)nb, led->rows,
+                                                              led->status);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }
@@ -1465,6 +1722,18 @@ extern "C" int sr_gather_push_emit_noalloc(sr_particles_f32 *parts, const sr_fie
                                       photons, &led, stream);
     if (rc != SR_OK) return rc;
     return reduce_ledger(&led, n_chunks, 0, (hipStream_t)stream);
+}
+
+extern "C" int sr_gather_push_emit_steps(sr_particles_f32 *parts, const sr_grid *grid, double dt,
+                                         uint64_t seed, uint64_t step0, int64_t n_steps,
+                                         const sr_params *prm, const sr_table *tab,
+                                         sr_photon_buf *photons, sr_ledger *ledger, void *stream) {
+    return launch_steps(parts, grid, dt, seed, step0, n_steps, prm, tab, photons, ledger, stream);
+}
+
+extern "C" int64_t sr_ledger_partials_steps(int64_t n_chunks, int64_t n_steps) {
+    if (n_chunks < 0 || n_steps < 0) return 0;
+    return steps_partials(n_chunks, n_steps);
 }
 
 extern "C" int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row,

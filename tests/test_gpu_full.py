@@ -382,6 +382,69 @@ def test_config1_full_run(sr, table, oracle):
     assert np.quantile(rel, 0.99) <= steps * parity.P_TOL
 
 
+def test_config1_full_run_in_one_launch(sr, table, oracle):
+    """The whole config-1 run (16 384 electrons, 1000 steps) as one launch of
+    sr_gather_push_emit_steps, against the oracle's 1000 steps: the same
+    tolerances as the per-step run, and the photon records' steps."""
+    cfg = synth.config("c1")
+    n, steps, seed = cfg.n_particles, cfg.steps, 20240601
+    st = synth.gen_particles(cfg)
+    parts = sr.Particles.from_numpy(st, dim=0)
+    parts.x = [None, None, None]
+    grid = sr.grid_struct(0, b0=cfg.b0)
+    photons = sr.PhotonBuffer(n, 4, dim=3, with_step=True)
+    ledger = sr.LedgerBuf(steps, sr.n_chunks_uniform(n), steps_per_call=steps)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, 1, recoil=cfg.recoil, push_position=False)
+    _say(f"config 1 in one launch {n} x {steps}")
+    sr.gather_push_emit_steps(parts, grid, cfg.dt, seed, 0, steps, prm, table, photons, ledger)
+    torch.cuda.synchronize()
+    g = parts.to_numpy()
+    rows = ledger.rows.cpu().numpy()
+    ph = photons.gather(n)
+    assert ledger.read_status() & ~2 == 0
+    assert ph["count"] == ph["stored"] == rows[:, 5].sum()
+    nb, lo, hi = 64, 1e-3, 1e5
+    edges = np.exp2(np.log2(lo) + (np.log2(hi) - np.log2(lo)) * np.arange(nb + 1) / nb)
+    h_gpu, _ = np.histogram(ph["eps"], bins=edges, weights=ph["w"].astype(np.float64) * ph["eps"])
+
+    orc = _orc(st)
+    orc["x"] = orc["y"] = orc["z"] = None
+    f = oracle.Field(0, b0=cfg.b0)
+    h_orc = np.zeros(nb)
+    led = np.zeros((steps, 5))
+    n_orc = np.zeros(steps)
+    for s in range(steps):
+        pho, led[s], _ = oracle.step(orc, f, cfg.dt, seed, s, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
+                                     n_samples=1, recoil=cfg.recoil, push_position=False)
+        h, _ = np.histogram(pho["eps"], bins=edges, weights=pho["w"] * pho["eps"])
+        h_orc += h
+        n_orc[s] = pho["eps"].size
+    spec_err = float(np.abs(h_gpu - h_orc).sum() / h_orc.sum())
+    e_gpu, e_orc = rows[:, 0].sum(), led[:, 0].sum()
+    ll_gpu, ll_orc = rows[:, 1].sum(), led[:, 1].sum()
+    pg = np.stack([g["px"], g["py"], g["pz"]], 1)[np.argsort(g["id"])]
+    po = np.stack([orc["px"], orc["py"], orc["pz"]], 1)
+    rel = np.linalg.norm(pg - po, axis=1) / np.maximum(np.linalg.norm(po, axis=1), 1e-30)
+    # the photon records' steps: per-step counts equal the ledger's photon column
+    cnt = photons.seg_count.cpu().numpy().view(np.uint32).astype(np.int64)
+    idx = np.concatenate([np.arange(c * L_CHUNK * 4, c * L_CHUNK * 4 + k) for c, k in enumerate(cnt)])
+    steps_of = photons.step[torch.from_numpy(idx).cuda()].cpu().numpy()
+    per_step = np.bincount(steps_of, minlength=steps)
+    print(f"config1 one launch: photons gpu {ph['count']} oracle {int(n_orc.sum())}, spectrum err "
+          f"{spec_err:.2e}, emitted rel {abs(e_gpu / e_orc - 1):.2e}, LL rel "
+          f"{abs(ll_gpu / ll_orc - 1):.2e}, |dp|/p median {np.median(rel):.2e}", flush=True)
+    assert np.array_equal(per_step, rows[:, 5].astype(np.int64))
+    assert spec_err <= 1e-3
+    assert abs(e_gpu / e_orc - 1) <= 1e-4
+    assert abs(ll_gpu / ll_orc - 1) <= 1e-4
+    np.testing.assert_allclose(rows[:, 1], led[:, 1], rtol=1e-4)
+    assert np.median(rel) <= 1e-5
+    assert np.quantile(rel, 0.99) <= steps * parity.P_TOL
+
+
+L_CHUNK = 64
+
+
 # ------------------------------------------------------------------ full-size, sampled
 def _device_fields(sr, cfg, t):
     """The generator's field, rounded to binary32, expanded along y and z on the device."""
