@@ -221,7 +221,11 @@ typedef struct sr_table sr_table;
 
 /* ------------------------------------------------------------ entry points */
 
-/* Build the device tables (the "spectrum-table construction" of the FP64 split):
+/* Build the device tables (the "spectrum-table construction" of the FP64 split).
+ * Their ranges and resolutions are fixed by the accuracy the step needs (the
+ * trial density to ~1e-7 relative over every R' a 23-bit uniform can take, F
+ * on x in [2^-18.5, 22.6], the cut fraction on log10 chi in [-6, 4]) and are
+ * reported by sr_table_query; they are not arguments:
  *  - the synchrotron function F(x) = x int_x^inf K_{5/3} (section "Modelling
  *    the relativistic case"), as piecewise cubics in log2 x;
  *  - the trial density F(x)/(x S(x)) of the proposal sampler of section "Monte
@@ -448,7 +452,10 @@ int sr_ledger_reduce(const sr_ledger *ledger, int64_t n_chunks, int64_t row, voi
 /* Workspace length (doubles) for ledger->partials with n_chunks chunks. */
 int64_t sr_ledger_partials(int64_t n_chunks);
 
-/* Copy ledger row `row` to host out[SR_LEDGER_COLS].  SYNCHRONOUS on stream. */
+/* The per-step energy ledger of section "Comparison and benchmarking" (Fig. 3:
+ * the energy the emitted photons carry against the Landau-Lifshitz radiation-
+ * reaction loss of eq:LLformOfRRForce): copy ledger row `row` (columns
+ * SR_LED_*, FP64) to host out[SR_LEDGER_COLS].  SYNCHRONOUS on stream. */
 int sr_energy_ledger(const sr_ledger *ledger, int64_t row, double *out, void *stream);
 
 /* Read (and, if clear != 0, zero) the latched status bits.  SYNCHRONOUS. */

@@ -34,6 +34,17 @@ def test_header_declares_entry_points():
         assert must in names
 
 
+def test_boundary_calls_of_the_hot_path():
+    # the calls the path's boundary is specified with: the step (FP32 and FP64),
+    # the ledger, the tables, the surrogate's forward, backward and Adam step,
+    # the status word and error text
+    names = _declared()
+    for must in ("sr_gather_push_emit", "sr_gather_push_emit_f64", "sr_energy_ledger",
+                 "sr_table_build", "sr_table_free", "sr_mlp_forward", "sr_mlp_backward",
+                 "sr_mlp_adam", "sr_status", "sr_strerror"):
+        assert must in names, must
+
+
 def test_library_exports_every_declared_symbol(lib):
     from paper_1409_5574_amd import _lib
     out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
@@ -95,6 +106,24 @@ def test_step_rejects_bad_arguments_on_host(lib):
         rc = lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), dt, 1, 0, C.byref(bad_prm),
                                      dummy, C.byref(ch), C.byref(ph), C.byref(led), None)
         assert rc == L.SR_E_INVAL
+    # an unknown gather mode
+    grid.dim = 0
+    bad_gather = L.Params(1e-5, 7.3e-3, 1, 0, 1, 0, 0, 0, None, None, 0.0, 2)
+    assert lib.sr_gather_push_emit(C.byref(p), None, C.byref(grid), 0.1, 1, 0, C.byref(bad_gather),
+                                   dummy, C.byref(ch), C.byref(ph), C.byref(led),
+                                   None) == L.SR_E_INVAL
+    # multi-step launches: uniform fields, no learned sampler, no grid floor
+    g3 = L.Grid()
+    g3.dim = 3
+    assert lib.sr_gather_push_emit_steps(C.byref(p), C.byref(g3), 0.1, 1, 0, 10, C.byref(prm),
+                                         dummy, C.byref(ph), C.byref(led),
+                                         None) == L.SR_E_UNSUPPORTED
+    mlp_prm = L.Params(1e-5, 7.3e-3, 1, 2, 1, 0, 0, 0, dummy, dummy)
+    assert lib.sr_gather_push_emit_steps(C.byref(p), C.byref(grid), 0.1, 1, 0, 10, C.byref(mlp_prm),
+                                         dummy, C.byref(ph), C.byref(led),
+                                         None) == L.SR_E_UNSUPPORTED
+    assert lib.sr_gather_push_emit_steps(C.byref(p), C.byref(grid), 0.1, 1, 0, 0, C.byref(prm),
+                                         dummy, C.byref(ph), C.byref(led), None) == L.SR_E_INVAL
     assert lib.sr_table_build(None, None) == L.SR_E_INVAL
     assert lib.sr_energy_ledger(None, 0, None, None) == L.SR_E_INVAL
     assert lib.sr_ledger_reduce(None, 1, 0, None) == L.SR_E_INVAL
@@ -246,6 +275,9 @@ def test_pic_calls_reject_bad_arguments_on_host(lib):
     assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), 0.05, None) == L.SR_E_INVAL
     ph.seg_count = d
     assert lib.sr_photon_advance(C.byref(ph), C.byref(ch), 10, C.byref(g), -1.0, None) == L.SR_E_INVAL
+    # the multi-step launch is for uniform fields only
+    assert lib.sr_gather_push_emit_steps(C.byref(p), C.byref(g), 0.05, 1, 0, 10, None, None, None,
+                                         None, None) == L.SR_E_INVAL
     # sizes whose byte offsets would not fit the kernels' 32-bit offsets
     p.n = 1 << 29
     assert lib.sr_deposit_rho(C.byref(p), C.byref(g), -1.0, d, None) == L.SR_E_UNSUPPORTED
