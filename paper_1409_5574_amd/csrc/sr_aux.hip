@@ -129,9 +129,30 @@ __device__ __forceinline__ bool block_key_range(uint32_t k, bool valid, uint32_t
 
 // Keys a block groups in LDS: particles sorted some steps ago fall in a few
 // nearby tiles, so one global atomic per distinct key of the block replaces
-// one per run of equal keys in each wave.  A block whose keys span more
-// (particles far from sorted) takes the per-run atomics.
+// one per run of equal keys in each wave.  Keys within a span of kSortSpan
+// index an LDS array directly; a block whose keys span more (particles that
+// drifted across tile rows and planes) groups them in an LDS hash table of
+// kHashSlots slots (a block has at most 256 distinct keys).
 constexpr uint32_t kSortSpan = 2048;
+constexpr uint32_t kHashSlots = 512;
+constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
+
+// The slot of key k in the block's table (inserting it if absent); linear
+// probing from a multiplicative hash.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t *hk, uint32_t k) {
+    uint32_t h = (k * 2654435761u) >> 23;   // 9 bits
+    for (;;) {
+        const uint32_t prev = atomicCAS(&hk[h], kHashEmpty, k);
+        if (prev == kHashEmpty || prev == k) return h;
+        h = (h + 1u) & (kHashSlots - 1u);
+    }
+}
+// The slot of a key already in the table.
+__device__ __forceinline__ uint32_t hash_find(const uint32_t *hk, uint32_t k) {
+    uint32_t h = (k * 2654435761u) >> 23;
+    while (hk[h] != k) h = (h + 1u) & (kHashSlots - 1u);
+    return h;
+}
 
 __global__ __launch_bounds__(256) void sort_count(const float *x, const float *y, const float *z,
                                                   int64_t n, SortGeom g, uint32_t *keys,
@@ -151,8 +172,17 @@ __global__ __launch_bounds__(256) void sort_count(const float *x, const float *y
         __syncthreads();
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x)
             if (lc[e]) atomicAdd(&counts[lo + e], lc[e]);
-    } else if (valid && r.head) {
-        atomicAdd(&counts[k], (uint32_t)r.len);
+    } else {
+        uint32_t *hk = lc, *hc = lc + kHashSlots;
+        for (uint32_t e = threadIdx.x; e < kHashSlots; e += blockDim.x) {
+            hk[e] = kHashEmpty;
+            hc[e] = 0u;
+        }
+        __syncthreads();
+        if (valid && r.head) atomicAdd(&hc[hash_slot(hk, k)], (uint32_t)r.len);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < kHashSlots; e += blockDim.x)
+            if (hc[e]) atomicAdd(&counts[hk[e]], hc[e]);
     }
 }
 
@@ -217,6 +247,7 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
     const WaveRun r = wave_run(k, valid);
     uint32_t base = 0;
     const bool local = hi - lo < kSortSpan;
+    uint32_t *hk = lc, *hc = lc + kHashSlots;
     if (local) {
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) lc[e] = 0u;
         __syncthreads();
@@ -229,12 +260,23 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
             if (c) lc[e] = atomicAdd(&cursor[lo + e], c);
         }
         __syncthreads();
-    } else if (valid && r.head) {
-        base = atomicAdd(&cursor[k], (uint32_t)r.len);
+    } else {
+        for (uint32_t e = threadIdx.x; e < kHashSlots; e += blockDim.x) {
+            hk[e] = kHashEmpty;
+            hc[e] = 0u;
+        }
+        __syncthreads();
+        if (valid && r.head) base = atomicAdd(&hc[hash_slot(hk, k)], (uint32_t)r.len);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < kHashSlots; e += blockDim.x) {
+            const uint32_t c = hc[e];
+            if (c) hc[e] = atomicAdd(&cursor[hk[e]], c);
+        }
+        __syncthreads();
     }
     base = (uint32_t)__shfl((int)base, r.head_lane, 64);
     if (!valid) return;
-    if (local) base += lc[k - lo];
+    base += local ? lc[k - lo] : hc[hash_find(hk, k)];
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)base + (lane - r.head_lane);
 #pragma unroll
