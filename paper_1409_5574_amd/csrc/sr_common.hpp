@@ -116,7 +116,25 @@ struct TableDev {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
 // ---------------------------------------------------------------------------
+// A wave-uniform value the optimiser cannot see through: a loop bound tested
+// each trial as a scalar compare, rather than kept as a precomputed lane mask
+// per trial in scalar registers.
+__device__ __forceinline__ int uniform_opaque(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// a ^ b ^ c in one VALU instruction (gfx950 three-input bit operation; the
+// truth table 0x96 is the XOR of its three inputs)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// The key (k0, k1) must be wave-uniform.  The empty asm hides it from the
+// optimiser, so each call steps the key schedule with scalar adds instead of
+// keeping all twenty round keys live in scalar registers across the kernel.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) {
@@ -125,8 +143,13 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         }
         const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(m1 >> 32) ^ c.y ^ k0, (uint32_t)m1,
-                       (uint32_t)(m0 >> 32) ^ c.w ^ k1, (uint32_t)m0);
+        if (r == 0) {
+            c = make_uint4((uint32_t)(m1 >> 32) ^ c.y ^ k0, (uint32_t)m1,
+                           (uint32_t)(m0 >> 32) ^ c.w ^ k1, (uint32_t)m0);
+        } else {
+            c = make_uint4(xor3((uint32_t)(m1 >> 32), c.y, k0), (uint32_t)m1,
+                           xor3((uint32_t)(m0 >> 32), c.w, k1), (uint32_t)m0);
+        }
     }
     return c;
 }

@@ -560,7 +560,7 @@ void push_emit_kernel(const StepArgs<R> a) {
             uint4 words = make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                if (k >= K) break;
+                if (k >= uniform_opaque(K)) break;
                 if ((k & 1) == 0)
                     words = philox4x32_10(make_uint4(pid, a.step, (uint32_t)(k >> 1), 0u),
                                           a.seed_lo, a.seed_hi);
