@@ -89,6 +89,12 @@ def counter_traffic(config: str):
         return None
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as each part of the run ends (the JSON line is the
+    only output on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -363,6 +369,7 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
         "status_bits": int(status),
     }
     if check is not None:
+        progress(f"timed passes done; CPU baseline: the oracle on {args.cpu_sample} electrons")
         out["cpu_baseline"], out["spectrum_check"] = cpu_leg(cfg, check, seed, args)
     del parts, alt, photons, snaps, work_fields, sort_work, snap
     table.free()
@@ -794,8 +801,10 @@ def run(args):
     if cfg.dim not in (2, 3) or cfg.sampler != 0:
         raise SystemExit(f"bench workload {args.config}: the headline is a grid workload with the "
                          "S-proposal sampler (the learned sampler runs in the samplers leg)")
+    progress(f"headline {args.config}: {args.warmup} warm-up + {args.steps} timed steps")
     head = grid_leg(args, args.config, args.steps, args.warmup, not args.no_cpu_baseline,
                     graph=not args.no_graph)
+    progress(f"headline done: {head['ms_per_step']:.3f} ms/step")
     n = cfg.n_particles
     out = {
         "metric": METRIC,
@@ -821,8 +830,10 @@ def run(args):
     out.update(head)
     torch.cuda.empty_cache()
     if not args.no_samplers:
+        progress(f"samplers: training the network ({args.mlp_steps} steps), then each sampler")
         s = samplers_leg(args)
         out["samplers"] = s
+        progress("samplers done")
         r = s["results"]
         out["plain_vs_surrogate"] = {
             "plain": {"sampler": "s_proposal", "kernel_particle_steps_per_s":
@@ -837,13 +848,16 @@ def run(args):
         torch.cuda.empty_cache()
     if not args.no_legs:
         out["uniform_field"] = c1_leg(args)
+        progress("uniform-field leg done")
         torch.cuda.empty_cache()
         for name in ("c5", "c2"):
             if name != args.config:
                 out[f"kernel_{name}"] = kernel_leg(name, args.leg_steps, 5)
+                progress(f"kernel leg {name} done")
                 torch.cuda.empty_cache()
     if not args.no_pic:
         out["pic_loop"] = pic_leg(args)
+        progress("PIC loop done")
     return out
 
 

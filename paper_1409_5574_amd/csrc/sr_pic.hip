@@ -218,7 +218,11 @@ __global__ __launch_bounds__(256) void rho_kernel(sr_particles_f32 P, PicGrid G,
 // |v| <= |c_z| for the 2D Jz.  A node takes at most one contribution per
 // particle and component, so a sum stays below 512 * 2^21 = 2^30, and the
 // integer adds are exact and independent of order.  The rounding error per
-// contribution is at most 2^-21 of the block's largest bound.
+// contribution is at most half a unit, 2^(e-22) <= 2^-21 B with B the block's
+// largest bound, so a node's block sum is within n 2^-21 B <= 2^-12 B of the
+// exact sum of its n <= 512 contributions.  That bound is absolute: a node
+// whose current is far below B in a block that also holds a much heavier or
+// faster particle keeps only that absolute accuracy.
 constexpr int kDepThreads = 512;   // particles per block
 constexpr int kDepWaves = kDepThreads / 64;
 constexpr int kDepCells = 3072;
