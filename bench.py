@@ -876,7 +876,7 @@ def main():
     ap.add_argument("--no-samplers", action="store_true",
                     help="skip the plain-vs-surrogate sampler comparison on the 3D K=8 workload")
     ap.add_argument("--sampler-steps", type=int, default=12)
-    ap.add_argument("--mlp-steps", type=int, default=150000)
+    ap.add_argument("--mlp-steps", type=int, default=300000)
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the uniform-field, 64M-electron and 2D legs")
     ap.add_argument("--leg-steps", type=int, default=10)
