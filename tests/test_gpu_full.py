@@ -442,6 +442,102 @@ def test_config1_full_run_in_one_launch(sr, table, oracle):
     assert np.quantile(rel, 0.99) <= steps * parity.P_TOL
 
 
+@pytest.mark.parametrize("sampler,K,recoil,dn_policy,kin_cut", [
+    (0, 8, 2, 0, True),     # S proposal, K = 8, LL recoil
+    (1, 4, 1, 1, True),     # table direct, clamped dN
+    (3, 2, 1, 0, True),     # quantum-corrected
+    (0, 16, 1, 0, False),   # S proposal, K = 16, no cut
+])
+def test_steps_launch_matches_per_step_launches(sr, table, sampler, K, recoil, dn_policy, kin_cut):
+    """sr_gather_push_emit_steps against one sr_gather_push_emit launch per step
+    (itself checked against the oracle), from the same state: the same trials
+    emit, and records, momenta and ledger rows agree to the parity bars.  The
+    two kernels compile the same arithmetic separately, so the compiler may
+    fuse a multiply-add in one and not the other: the results agree to FP32
+    rounding, not bit for bit.  3000 electrons (a ragged last chunk) in a
+    strong uniform field, 12 steps from step 5."""
+    cfg = synth.config("c1", b0=(0.3, 0.0, 40.0))
+    n, steps, step0, seed = 3000, 12, 5, 0xA11CE
+    st = synth.gen_particles(cfg, n=n, seed=77)
+    grid = sr.grid_struct(0, b0=cfg.b0)
+    prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler=sampler, recoil=recoil,
+                           dn_policy=dn_policy, kin_cut=kin_cut, push_position=False)
+    nch = sr.n_chunks_uniform(n)
+    _say(f"steps launch vs per-step launches: sampler {sampler} K {K} recoil {recoil} "
+         f"dn_policy {dn_policy}")
+
+    # one launch per step
+    pa = sr.Particles.from_numpy(st, dim=0)
+    pa.x = [None, None, None]
+    led_a = sr.LedgerBuf(steps, nch)
+    recs_a, rows_a = [], []
+    for s_ in range(steps):
+        ph = sr.PhotonBuffer(n, K, dim=3)
+        sr.gather_push_emit(pa, None, grid, cfg.dt, seed, step0 + s_, prm, table, ph, led_a, s_)
+        torch.cuda.synchronize()
+        g = ph.gather(n)
+        assert g["count"] == g["stored"]
+        recs_a.append(np.rec.fromarrays(
+            [np.full(g["count"], step0 + s_, np.int64), g["parent"].astype(np.int64),
+             g["k"].astype(np.int64), g["eps"], g["w"], g["dir"][:, 0], g["dir"][:, 1],
+             g["dir"][:, 2]], names="step,parent,k,eps,w,d0,d1,d2"))
+    rows_a = led_a.rows.cpu().numpy()
+    ga = pa.to_numpy()
+
+    # one launch for all the steps
+    pb = sr.Particles.from_numpy(st, dim=0)
+    pb.x = [None, None, None]
+    pp = 64
+    phb = sr.PhotonBuffer(n, pp, dim=3, with_step=True)
+    led_b = sr.LedgerBuf(steps, nch, steps_per_call=steps)
+    sr.gather_push_emit_steps(pb, grid, cfg.dt, seed, step0, steps, prm, table, phb, led_b)
+    torch.cuda.synchronize()
+    assert led_b.read_status() & 1 == 0             # no photon overflow
+    gb_ = phb.gather(n)
+    cnt = phb.seg_count.cpu().numpy().view(np.uint32).astype(np.int64)
+    idx = np.concatenate([np.arange(c * L_CHUNK * pp, c * L_CHUNK * pp + k)
+                          for c, k in enumerate(cnt)])
+    step_b = phb.step[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int64)
+    rec_b = np.rec.fromarrays(
+        [step_b, gb_["parent"].astype(np.int64), gb_["k"].astype(np.int64), gb_["eps"], gb_["w"],
+         gb_["dir"][:, 0], gb_["dir"][:, 1], gb_["dir"][:, 2]], names="step,parent,k,eps,w,d0,d1,d2")
+    rows_b = led_b.rows.cpu().numpy()
+    gbp = pb.to_numpy()
+
+    rec_a = np.concatenate(recs_a)
+    print(f"steps launch: {rec_b.size} photons, per-step launches {rec_a.size}", flush=True)
+    assert rec_a.size > 200
+    rec_a.sort(order=["step", "parent", "k"])
+    rec_b.sort(order=["step", "parent", "k"])
+    # the same trials emit: a trial whose dN lies within FP32 rounding of its
+    # word may decide differently (none did in the runs so far)
+    ka = (rec_a["step"] << 37) + (rec_a["parent"] << 5) + rec_a["k"]
+    kb = (rec_b["step"] << 37) + (rec_b["parent"] << 5) + rec_b["k"]
+    common_a = np.isin(ka, kb)
+    common_b = np.isin(kb, ka)
+    flips = int((~common_a).sum() + (~common_b).sum())
+    assert flips <= 2, flips
+    ra, rb = rec_a[common_a], rec_b[common_b]
+    for f in ("eps", "w"):
+        rel = np.abs(rb[f].astype(np.float64) / ra[f] - 1.0)
+        assert rel.max() <= parity.PH_TOL, (f, rel.max())
+    dd = max(np.abs(rb[f].astype(np.float64) - ra[f]).max() for f in ("d0", "d1", "d2"))
+    assert dd <= 1e-5, dd
+    pa_ = np.stack([ga["px"], ga["py"], ga["pz"]], 1)
+    pb_ = np.stack([gbp["px"], gbp["py"], gbp["pz"]], 1)
+    prel = np.linalg.norm(pb_ - pa_, axis=1) / np.maximum(np.linalg.norm(pa_, axis=1), 1e-30)
+    assert prel.max() <= steps * parity.P_TOL, prel.max()
+    # ledger rows: photons by the flips, the FP64 columns to the ledger bar
+    assert np.abs(rows_a[:, 5] - rows_b[:, 5]).sum() <= flips
+    np.testing.assert_allclose(rows_b[:, 7], rows_a[:, 7], rtol=1e-5)
+    np.testing.assert_allclose(rows_b[:, 6], rows_a[:, 6], rtol=1e-5)
+    for c in range(5):
+        scale = max(np.abs(rows_a[:, 0]).max(), np.abs(rows_a[:, 1]).max())
+        assert np.abs(rows_b[:, c] - rows_a[:, c]).max() <= parity.LEDGER_TOL * scale, c
+    print(f"steps launch vs per-step: flips {flips}, photon eps rel "
+          f"{np.abs(rb['eps'] / ra['eps'] - 1).max():.1e}, momenta rel {prel.max():.1e}", flush=True)
+
+
 L_CHUNK = 64
 
 
