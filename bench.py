@@ -378,7 +378,8 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
 
 
 # ---------------------------------------------------------------- kernel-only legs
-def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10) -> dict:
+def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10,
+               cpu_seconds: float = 0.0, cpu_sample: int = 65536) -> dict:
     """Emission-kernel time (median of per-dispatch HIP events) on a grid
     workload, sorted every `sort_every` steps; the field of each step is
     written before its emission launch."""
@@ -418,6 +419,17 @@ def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10) -> 
         if i == warmup:
             torch.cuda.synchronize()
             touched = touched_grid_values(parts, cfg)
+            if cpu_seconds > 0:
+                # the first cpu_sample ids, in id order, before step `warmup`
+                sel = torch.nonzero(parts.id.view(torch.int32) < cpu_sample).squeeze(1)
+                sel = sel[torch.argsort(parts.id.view(torch.int32)[sel])]
+                cpu_state = {k: (t[sel].cpu().numpy().astype(np.float64) if t is not None else None)
+                             for k, t in zip(("x", "y", "z", "px", "py", "pz", "w"),
+                                             parts.x + parts.p + [parts.w])}
+                cpu_state["id"] = parts.id[sel].cpu().numpy().view(np.uint32).copy()
+                if dim == 2:
+                    cpu_state["z"] = None
+                del sel
         j = i - warmup
         api.gather_push_emit(parts, fields, grid, cfg.dt, 0xC5, i, prm, table, photons, ledger, i,
                              events=ev[j] if j >= 0 else None)
@@ -445,6 +457,19 @@ def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10) -> 
     del parts, alt, photons, fields, sw
     table.free()
     torch.cuda.empty_cache()
+    if cpu_seconds > 0:
+        # the standing wave depends on x only: the oracle gets the same x profile
+        # on a grid of two cells along y and z
+        from oracle import oracle as O
+        thin = (cfg.grid[0], 2, 2 if dim == 3 else 1)
+        cthin = synth.config(cfg.name[:2], grid=thin)
+
+        def field_at_step(i):
+            E, B = synth.standing_wave_grid(cthin, i * cfg.dt)
+            return O.Field(dim, n=thin, dx=(cfg.dx,) * 3, E=E, B=B)
+
+        out["cpu_oracle"] = oracle_rate(cfg, cpu_state, warmup, 0xC5, cpu_seconds, field_at_step)
+        out["cpu_oracle"]["sample"] += f" (same field values: x profile on a {thin[0]}x{thin[1]}x{thin[2]} grid)"
     return out
 
 
@@ -511,6 +536,15 @@ def c1_leg(args) -> dict:
     kms = float(np.median([t[1] for t in times]))
     rows = ledger1.rows.cpu().numpy()
     table.free()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        sub = {k: (np.asarray(st[k], np.float64).copy() if k != "id" else
+                   np.asarray(st[k]).view(np.uint32).copy()) for k in ("px", "py", "pz", "w", "id")}
+        sub["x"] = sub["y"] = sub["z"] = None
+        f0 = O.Field(0, b0=cfg.b0)
+        cpu = oracle_rate(cfg, sub, 0, 0xC1, args.cpu_leg_seconds, lambda i: f0,
+                          push_position=False)
     # VALU work of the launch: instructions per wave-step from the kernel's
     # counter profile (committed summary), if present
     return {"workload": f"{cfg.name}: {n} electrons, uniform B = 1 (1e5 T), {steps} steps, K=1, "
@@ -520,7 +554,8 @@ def c1_leg(args) -> dict:
             "per_step_launches_as_graph": {"particle_steps_per_s": n * steps / wall_graph,
                                            "ms_per_run": wall_graph * 1e3},
             "photons_per_run": float(rows[:, L.SR_LED_PHOTONS].sum()),
-            "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300))}
+            "emitted_over_ll": float(rows[:, 0].sum() / max(rows[:, 1].sum(), 1e-300)),
+            "cpu_oracle": cpu}
 
 
 def pic_leg(args):
@@ -791,6 +826,29 @@ def cpu_leg(cfg, check, seed, args):
     return base, spec
 
 
+def oracle_rate(cfg, sub, i0, seed, seconds, field_at_step, push_position=True):
+    """The FP64 oracle's particle-steps/s on the state `sub` (host FP64 arrays,
+    modified in place), stepping from step i0 for about `seconds` of oracle
+    time on the host's OpenMP threads."""
+    from oracle import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    kw = dict(hbar_n=cfg.hbar_n, alpha=cfg.alpha, n_samples=cfg.n_samples, recoil=cfg.recoil,
+              kin_cut=cfg.kin_cut, threads=threads, push_position=push_position)
+    spent, steps = 0.0, 0
+    while steps == 0 or (spent + spent / steps <= seconds and steps < 100000):
+        f = field_at_step(i0 + steps)
+        t0 = time.perf_counter()
+        O.step(sub, f, cfg.dt, seed, i0 + steps, **kw)
+        spent += time.perf_counter() - t0
+        steps += 1
+    m = int(sub["px"].shape[0])
+    return {"value": m * steps / spent, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{m} electrons, {steps} steps from step {i0}, K={cfg.n_samples}; FP64 C "
+                      f"oracle with OpenMP on {threads} threads, {spent:.1f} s"}
+
+
 def run(args):
     import torch
 
@@ -852,7 +910,10 @@ def run(args):
         torch.cuda.empty_cache()
         for name in ("c5", "c2"):
             if name != args.config:
-                out[f"kernel_{name}"] = kernel_leg(name, args.leg_steps, 5)
+                out[f"kernel_{name}"] = kernel_leg(
+                    name, args.leg_steps, 5,
+                    cpu_seconds=0.0 if args.no_cpu_baseline else args.cpu_leg_seconds,
+                    cpu_sample=args.cpu_sample)
                 progress(f"kernel leg {name} done")
                 torch.cuda.empty_cache()
     if not args.no_pic:
@@ -870,6 +931,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-leg-seconds", type=float, default=8.0,
+                    help="oracle time for the CPU rates of the uniform-field and kernel legs")
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-graph", action="store_true",
                     help="report the eager-launch pass as the value (no HIP-graph pass)")
