@@ -187,6 +187,50 @@ __device__ __forceinline__ float trial_q(uint32_t a, const float4 *__restrict__ 
     return __builtin_amdgcn_exp2f(fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x));
 }
 
+// The pieces of the trial-density table that almost every trial reads, which
+// the proposal sampler's kernels with four or more trials keep in LDS: log2 R'
+// in [-8, 0) on the lower branch (256 pieces) and -log2(1 - R') in [1, 10) on
+// the upper one (288 pieces), 8.7 KB.  With R' uniform, 99.4% and 99.8% of a
+// branch's trials fall there.  Element e of the LDS copy holds
+// gtab[ghot_source(e)].
+constexpr int kGHotLo = 256;
+constexpr int kGHotUp = 288;
+constexpr int kGHot = kGHotLo + kGHotUp;
+__device__ __forceinline__ int ghot_source(int e) {
+    return e < kGHotLo ? kGLoN - kGHotLo + e : kGLoN + (e - kGHotLo);
+}
+
+// A 16-byte global load that the optimiser cannot merge with another load into
+// one generic (flat) access: written out, and waited for in the same statement.
+__device__ __forceinline__ float4 ld_global_wait(const float4 *p) {
+    float4 v;
+    asm volatile("global_load_dwordx4 %0, %1, off\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p)
+                 : "memory");
+    return v;
+}
+
+// trial_q with the hot pieces read from their LDS copy ghot: the same values,
+// so the same result.  Every lane reads the LDS copy (the cold lanes at a
+// clamped index) and only the rare cold lanes then read the table in global
+// memory, as a separate load.
+__device__ __forceinline__ float trial_q_hot(uint32_t a, const float4 *__restrict__ gtab,
+                                             const float4 *ghot, float pa, float &lg,
+                                             bool &lower) {
+    const float rp = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
+    lower = rp <= pa;
+    lg = __builtin_amdgcn_logf(lower ? rp : 1.0f - rp);   // 1 - rp is exact
+    const float u = (lower ? lg : -lg) * (float)kGPerUnit;
+    const int j0 = lower ? kGLoJ0 : kGUpJ0;
+    int j = (int)floorf(u) - j0;
+    j = min(max(j, 0), (lower ? kGLoN : kGUpN) - 1);
+    const float s = u - (float)(j + j0);
+    const bool hot = lower ? j >= kGLoN - kGHotLo : j < kGHotUp;
+    const int h = lower ? max(j - (kGLoN - kGHotLo), 0) : min(kGHotLo + j, kGHot - 1);
+    float4 c = ghot[h];
+    if (!hot) c = ld_global_wait(gtab + (lower ? 0 : kGLoN) + j);
+    return __builtin_amdgcn_exp2f(fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x));
+}
+
 // x of a trial (word a, trial_q's lg): R'^{3/4} as sqrt(R') sqrt(sqrt(R'))
 // (a few ulp, where 2^{3 lg/4} would lose ~1e-6 to the rounding of lg), or
 // -ln((9/7)(1 - R')).

@@ -291,10 +291,16 @@ struct PhotonStage {
     uint32_t cnt[kWaves];       // staged photons per wave
     uint32_t base[kWaves];      // first buffer slot of each wave's chunk segment
 };
+// The proposal sampler with four or more trials also keeps the hot pieces of
+// the trial-density table (31.3 KB in all: five 256-thread blocks per compute
+// unit); with fewer trials the table lookups are too few to pay for the copy.
+template <int KMAX>
+constexpr bool kHotTable = KMAX >= 4;
 template <int KMAX>
 struct StepSmem<KMAX, SR_SAMPLER_S, false> {
     LedgerSmem led;
     PhotonStage stage;
+    float4 ghot[kHotTable<KMAX> ? kGHot : 1];
 };
 template <int KMAX>
 struct StepSmem<KMAX, SR_SAMPLER_TABLE, false> {
@@ -419,6 +425,10 @@ void push_emit_kernel(const StepArgs<R> a) {
             mlp_load(sm.m, a.mlp, tid, kBlock);
             __syncthreads();
         }
+    }
+    if constexpr (SAMPLER == SR_SAMPLER_S && !BOX && kHotTable<KMAX>) {
+        for (int e = tid; e < kGHot; e += kBlock) sm.ghot[e] = a.tab.gtab[ghot_source(e)];
+        __syncthreads();
     }
     // one chunk per wave, kWaves consecutive chunks per block (blocks mapped so
     // that neighbouring chunks share an XCD)
@@ -569,7 +579,10 @@ void push_emit_kernel(const StepArgs<R> a) {
                 float dn = rate, lg = 0.0f, xq = 0.0f;
                 bool lower = true;
                 if (SAMPLER == SR_SAMPLER_S) {
-                    dn = rate * trial_q(wa, a.tab.gtab, a.tab.pa, lg, lower);
+                    if constexpr (SAMPLER == SR_SAMPLER_S && !BOX && kHotTable<KMAX>)
+                        dn = rate * trial_q_hot(wa, a.tab.gtab, sm.ghot, a.tab.pa, lg, lower);
+                    else
+                        dn = rate * trial_q(wa, a.tab.gtab, a.tab.pa, lg, lower);
                     if (trial_is_cut(cut, lg, lower)) dn = 0.0f;
                     if (FLOOR && trial_is_floored(flr, lg, lower)) dn = 0.0f;
                 } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
