@@ -246,8 +246,16 @@ __device__ __forceinline__ float trial_x(uint32_t a, float lg, bool lower) {
 // Quantum trial: dN / rate = Q(x, chi) / S(x) at the proposal's x(R') (the
 // classical recipe with the quantum kernel in place of F(x)/x), and x itself.
 // Zero at and above the kinematic edge delta = 1.5 chi x >= 1.
-__device__ __forceinline__ float quantum_q(uint32_t a, const float4 *__restrict__ qtab, float pa,
-                                           float chi, float &x) {
+//
+// With HOT, the pieces of log2 xi >= -6 (kQHot0 on: 208 pieces, 6.7 KB, which
+// all but ~0.4% of the trials read) come from their LDS copy qhot, element e
+// holding qtab[2 kQHot0 + e]; the rare colder lanes read the global table with
+// separate loads.  The same values either way, so the same result.
+constexpr int kQHot0 = (-6 * kQPerUnit) - kQJ0;
+constexpr int kQHot = 2 * (kQN - kQHot0);
+template <bool HOT>
+__device__ __forceinline__ float quantum_q_t(uint32_t a, const float4 *__restrict__ qtab,
+                                             const float4 *qhot, float pa, float chi, float &x) {
     const float rp = (float)((a >> 9) * 2u + 1u) * 0x1p-24f;
     const bool lower = rp <= pa;
     const float lg = __builtin_amdgcn_logf(lower ? rp : 1.0f - rp);
@@ -264,13 +272,29 @@ __device__ __forceinline__ float quantum_q(uint32_t a, const float4 *__restrict_
     int j = (int)floorf(u) - kQJ0;
     j = min(max(j, 0), kQN - 1);
     const float s = u - (float)(j + kQJ0);
-    const float4 ca = qtab[2 * j], cb = qtab[2 * j + 1];
+    float4 ca, cb;
+    if constexpr (HOT) {
+        const int h = 2 * max(j - kQHot0, 0);
+        ca = qhot[h];
+        cb = qhot[h + 1];
+        if (j < kQHot0) {
+            ca = ld_global_wait(qtab + 2 * j);
+            cb = ld_global_wait(qtab + 2 * j + 1);
+        }
+    } else {
+        ca = qtab[2 * j];
+        cb = qtab[2 * j + 1];
+    }
     const float ya = fmaf(fmaf(fmaf(ca.w, s, ca.z), s, ca.y), s, ca.x);
     const float yb = fmaf(fmaf(fmaf(cb.w, s, cb.z), s, cb.y), s, cb.x);
     const float c = om + 1.0f / om;
     const float q = c * __builtin_amdgcn_exp2f(fmaf(-0.66666666666666667f, t, ya)) -
                     __builtin_amdgcn_exp2f(yb);
     return q * __builtin_amdgcn_exp2f(fmaf(-1.4426950408889634f, xi, l2_inv_s));
+}
+__device__ __forceinline__ float quantum_q(uint32_t a, const float4 *__restrict__ qtab, float pa,
+                                           float chi, float &x) {
+    return quantum_q_t<false>(a, qtab, nullptr, pa, chi, x);
 }
 
 // Kinematic cut x > xc = 2/(3 chi) expressed on lg: on the lower branch

@@ -291,9 +291,10 @@ struct PhotonStage {
     uint32_t cnt[kWaves];       // staged photons per wave
     uint32_t base[kWaves];      // first buffer slot of each wave's chunk segment
 };
-// The proposal sampler with four or more trials also keeps the hot pieces of
-// the trial-density table (31.3 KB in all: five 256-thread blocks per compute
-// unit); with fewer trials the table lookups are too few to pay for the copy.
+// With four or more trials the proposal sampler also keeps the hot pieces of
+// the trial-density table in LDS (31.3 KB in all: five 256-thread blocks per
+// compute unit), and the quantum sampler those of its kernel table (29.3 KB);
+// with fewer trials the table lookups are too few to pay for the copy.
 template <int KMAX>
 constexpr bool kHotTable = KMAX >= 4;
 template <int KMAX>
@@ -311,6 +312,7 @@ template <int KMAX>
 struct StepSmem<KMAX, SR_SAMPLER_QUANTUM, false> {
     LedgerSmem led;
     PhotonStage stage;
+    float4 qhot[kHotTable<KMAX> ? kQHot : 1];   // 29.3 KB in all
 };
 // With the LDS field box (SR_GATHER_BOX) the box shares its LDS with the
 // ledger and the photon stage: it is read only before either is written.
@@ -428,6 +430,10 @@ void push_emit_kernel(const StepArgs<R> a) {
     }
     if constexpr (SAMPLER == SR_SAMPLER_S && !BOX && kHotTable<KMAX>) {
         for (int e = tid; e < kGHot; e += kBlock) sm.ghot[e] = a.tab.gtab[ghot_source(e)];
+        __syncthreads();
+    }
+    if constexpr (SAMPLER == SR_SAMPLER_QUANTUM && !BOX && kHotTable<KMAX>) {
+        for (int e = tid; e < kQHot; e += kBlock) sm.qhot[e] = a.tab.qtab[2 * kQHot0 + e];
         __syncthreads();
     }
     // one chunk per wave, kWaves consecutive chunks per block (blocks mapped so
@@ -586,7 +592,10 @@ void push_emit_kernel(const StepArgs<R> a) {
                     if (trial_is_cut(cut, lg, lower)) dn = 0.0f;
                     if (FLOOR && trial_is_floored(flr, lg, lower)) dn = 0.0f;
                 } else if (SAMPLER == SR_SAMPLER_QUANTUM) {
-                    dn = rate * quantum_q(wa, a.tab.qtab, a.tab.pa, chif, xq);
+                    if constexpr (SAMPLER == SR_SAMPLER_QUANTUM && !BOX && kHotTable<KMAX>)
+                        dn = rate * quantum_q_t<true>(wa, a.tab.qtab, sm.qhot, a.tab.pa, chif, xq);
+                    else
+                        dn = rate * quantum_q(wa, a.tab.qtab, a.tab.pa, chif, xq);
                     if (FLOOR && eps_unit * xq < a.e_grid) dn = 0.0f;
                 }
                 bool emit;
