@@ -224,9 +224,12 @@ __device__ __forceinline__ float trial_q_hot(uint32_t a, const float4 *__restric
     int j = (int)floorf(u) - j0;
     j = min(max(j, 0), (lower ? kGLoN : kGUpN) - 1);
     const float s = u - (float)(j + j0);
-    const bool hot = lower ? j >= kGLoN - kGHotLo : j < kGHotUp;
-    const int h = lower ? max(j - (kGLoN - kGHotLo), 0) : min(kGHotLo + j, kGHot - 1);
-    float4 c = ghot[h];
+    // LDS index: the lower pieces at j - (kGLoN - kGHotLo), always below
+    // kGHotLo, and the upper ones at kGHotLo + j, never below it; so a piece
+    // is hot exactly when its index lies in [0, kGHot)
+    const int idx = j + (lower ? kGHotLo - kGLoN : kGHotLo);
+    const bool hot = (uint32_t)idx < (uint32_t)kGHot;
+    float4 c = ghot[hot ? idx : 0];
     if (!hot) c = ld_global_wait(gtab + (lower ? 0 : kGLoN) + j);
     return __builtin_amdgcn_exp2f(fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x));
 }
