@@ -50,8 +50,11 @@ YEE = synth.yee_offsets()
 # HBM traffic of the emission kernel from hardware counters: a summary under
 # profiles/ records FETCH_SIZE and WRITE_SIZE per dispatch (scaled by a plain
 # copy of known size) together with a digest of the sources the kernel is built
-# from.  The figure is reported only while those sources are unchanged.
+# from (and the tile sort, which sets the particle order the kernel reads in)
+# and the sort interval of the run.  The figure is reported only while both
+# are unchanged.
 KERNEL_SOURCES = ["paper_1409_5574_amd/csrc/sr_step.hip", "paper_1409_5574_amd/csrc/sr_common.hpp",
+                  "paper_1409_5574_amd/csrc/sr_aux.hip",
                   "paper_1409_5574_amd/csrc/sr_mlp.hpp", "include/sr.h",
                   "paper_1409_5574_amd/build.py"]
 
@@ -69,9 +72,10 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(config: str):
+def counter_traffic(config: str, sort_every: int):
     """Bytes per launch from the committed counter summary, or None when there
-    is none or the kernel sources changed since the counters were taken."""
+    is none, the kernel sources changed since the counters were taken, or the
+    counters were taken at another sort interval."""
     try:
         text = open(traffic_file(config)).read()
     except OSError:
@@ -82,6 +86,8 @@ def counter_traffic(config: str):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("sources_sha256") != kernel_sources_digest():
+        return None
+    if vals.get("sort_every") != str(sort_every):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -350,7 +356,7 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
                    "fields": "one snapshot per timed step, resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic(cfg_name),
+                     "traffic": counter_traffic(cfg_name, args.sort_every),
                      "kernel": "push_emit_kernel<float,%d,%d,0,false>" % (dim, 1 if K <= 1 else K),
                      "kernel_ms": kmed, "kernel_ms_stats": stats_ms(k_ms),
                      "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -450,7 +456,7 @@ def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10,
            "algorithmic_bytes_per_launch": by,
            "grid_values_read_bytes": 4 * touched,
            "roofline_frac": by / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS,
-           "traffic": counter_traffic(cfg_name),
+           "traffic": counter_traffic(cfg_name, sort_every),
            "photons_per_step": ph,
            "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
            "status_bits": int(ledger.read_status())}
@@ -928,7 +934,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-every", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-leg-seconds", type=float, default=8.0,

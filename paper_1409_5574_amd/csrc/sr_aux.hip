@@ -107,11 +107,13 @@ __device__ __forceinline__ WaveRun wave_run(uint32_t k, bool valid) {
     return r;
 }
 
-// The block's smallest and largest valid key; false when no lane is valid.
-// Keys are below 2^31 (the tile count is checked on the host).
-__device__ __forceinline__ bool block_key_range(uint32_t k, bool valid, uint32_t &lo, uint32_t &hi) {
+// The block's smallest and largest key over the lanes that hold one (lane
+// values kmin <= kmax, ignored where `any` is false); false when no lane holds
+// one.  Keys are below 2^31 (the tile count is checked on the host).
+__device__ __forceinline__ bool block_key_range(uint32_t kmin, uint32_t kmax, bool any,
+                                                uint32_t &lo, uint32_t &hi) {
     __shared__ int rlo[4], rhi[4];
-    int a = valid ? (int)k : 0x7fffffff, b = valid ? (int)k : -1;
+    int a = any ? (int)kmin : 0x7fffffff, b = any ? (int)kmax : -1;
     for (int o = 32; o > 0; o >>= 1) {
         a = min(a, __shfl_xor(a, o, 64));
         b = max(b, __shfl_xor(b, o, 64));
@@ -127,20 +129,25 @@ __device__ __forceinline__ bool block_key_range(uint32_t k, bool valid, uint32_t
     return b >= a;
 }
 
-// Keys a block groups in LDS: particles sorted some steps ago fall in a few
-// nearby tiles, so one global atomic per distinct key of the block replaces
-// one per run of equal keys in each wave.  Keys within a span of kSortSpan
-// index an LDS array directly; a block whose keys span more (particles that
-// drifted across tile rows and planes) groups them in an LDS hash table of
-// kHashSlots slots (a block has at most 256 distinct keys).
-constexpr uint32_t kSortSpan = 2048;
-constexpr uint32_t kHashSlots = 512;
+// A block takes kSortPer consecutive particles, kSortPPT per thread in rounds
+// of 256 (coalesced loads, all in flight together), and groups their keys in
+// LDS: particles sorted some steps ago fall in a few nearby tiles, so one
+// global atomic per distinct key of the block replaces one per run of equal
+// keys in each wave.  Keys within a span of kSortSpan index an LDS array
+// directly; a block whose keys span more (particles that drifted across tile
+// rows and planes) groups them in an LDS hash table of kHashSlots slots, twice
+// the most distinct keys a block can hold.
+constexpr int kSortPPT = 4;
+constexpr int kSortPer = 256 * kSortPPT;
+constexpr uint32_t kSortSpan = 4096;
+constexpr uint32_t kHashSlots = 2048;
 constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
+static_assert(kHashSlots >= 2 * kSortPer && 2 * kHashSlots <= kSortSpan, "LDS table sizes");
 
 // The slot of key k in the block's table (inserting it if absent); linear
 // probing from a multiplicative hash.
 __device__ __forceinline__ uint32_t hash_slot(uint32_t *hk, uint32_t k) {
-    uint32_t h = (k * 2654435761u) >> 23;   // 9 bits
+    uint32_t h = (k * 2654435761u) >> 21;   // 11 bits
     for (;;) {
         const uint32_t prev = atomicCAS(&hk[h], kHashEmpty, k);
         if (prev == kHashEmpty || prev == k) return h;
@@ -149,26 +156,65 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t *hk, uint32_t k) {
 }
 // The slot of a key already in the table.
 __device__ __forceinline__ uint32_t hash_find(const uint32_t *hk, uint32_t k) {
-    uint32_t h = (k * 2654435761u) >> 23;
+    uint32_t h = (k * 2654435761u) >> 21;
     while (hk[h] != k) h = (h + 1u) & (kHashSlots - 1u);
     return h;
+}
+
+// First particle of the block: neighbouring particle ranges on one XCD, so
+// their tiles' counters and segments stay in that XCD's L2.
+__device__ __forceinline__ int64_t sort_block_first() {
+    return xcd_chunk(blockIdx.x, gridDim.x) * kSortPer + threadIdx.x;
+}
+
+// Lane range of the thread's valid keys.
+__device__ __forceinline__ bool lane_key_range(const uint32_t (&k)[kSortPPT],
+                                               const bool (&valid)[kSortPPT], uint32_t &a,
+                                               uint32_t &b) {
+    a = 0xFFFFFFFFu;
+    b = 0u;
+#pragma unroll
+    for (int r = 0; r < kSortPPT; ++r)
+        if (valid[r]) {
+            a = min(a, k[r]);
+            b = max(b, k[r]);
+        }
+    return valid[0];   // valid particles form a prefix of the rounds
 }
 
 __global__ __launch_bounds__(256) void sort_count(const float *x, const float *y, const float *z,
                                                   int64_t n, SortGeom g, uint32_t *keys,
                                                   uint32_t *counts) {
     __shared__ uint32_t lc[kSortSpan];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t k = valid ? tile_key(g, x[i], y[i], g.dim == 3 ? z[i] : 0.0f) : 0xFFFFFFFFu;
-    if (valid) keys[i] = k;
-    uint32_t lo, hi;
-    if (!block_key_range(k, valid, lo, hi)) return;   // no valid lane (block-wide)
-    const WaveRun r = wave_run(k, valid);
+    const int64_t i0 = sort_block_first();
+    uint32_t k[kSortPPT];
+    bool valid[kSortPPT];
+    float px[kSortPPT], py[kSortPPT], pz[kSortPPT];
+#pragma unroll
+    for (int r = 0; r < kSortPPT; ++r) {
+        const int64_t i = i0 + r * 256;
+        valid[r] = i < n;
+        px[r] = valid[r] ? x[i] : 0.0f;
+        py[r] = valid[r] ? y[i] : 0.0f;
+        pz[r] = valid[r] && g.dim == 3 ? z[i] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortPPT; ++r) {
+        k[r] = valid[r] ? tile_key(g, px[r], py[r], pz[r]) : 0xFFFFFFFFu;
+        if (valid[r]) keys[i0 + r * 256] = k[r];
+    }
+    uint32_t a, b, lo, hi;
+    const bool any = lane_key_range(k, valid, a, b);
+    if (!block_key_range(a, b, any, lo, hi)) return;   // no valid lane (block-wide)
+    WaveRun run[kSortPPT];
+#pragma unroll
+    for (int r = 0; r < kSortPPT; ++r) run[r] = wave_run(k[r], valid[r]);
     if (hi - lo < kSortSpan) {
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) lc[e] = 0u;
         __syncthreads();
-        if (valid && r.head) atomicAdd(&lc[k - lo], (uint32_t)r.len);
+#pragma unroll
+        for (int r = 0; r < kSortPPT; ++r)
+            if (valid[r] && run[r].head) atomicAdd(&lc[k[r] - lo], (uint32_t)run[r].len);
         __syncthreads();
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x)
             if (lc[e]) atomicAdd(&counts[lo + e], lc[e]);
@@ -179,7 +225,9 @@ __global__ __launch_bounds__(256) void sort_count(const float *x, const float *y
             hc[e] = 0u;
         }
         __syncthreads();
-        if (valid && r.head) atomicAdd(&hc[hash_slot(hk, k)], (uint32_t)r.len);
+#pragma unroll
+        for (int r = 0; r < kSortPPT; ++r)
+            if (valid[r] && run[r].head) atomicAdd(&hc[hash_slot(hk, k[r])], (uint32_t)run[r].len);
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < kHashSlots; e += blockDim.x)
             if (hc[e]) atomicAdd(&counts[hk[e]], hc[e]);
@@ -222,37 +270,53 @@ __global__ void scan_add(uint32_t *out, int64_t n, const uint32_t *block_prefix)
 // Each particle goes to its slot among the tile's particles, counted from the
 // tile's offset: offsets[key] serves as the tile's cursor (it ends as the
 // tile's end).  Slots are handed out per block and key (LDS), then per block
-// from the cursor (one global atomic per distinct key of the block); a block
-// whose keys span kSortSpan or more takes a global atomic per run.
+// from the cursor: one global atomic per distinct key of the block.
 __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst,
                                                     const uint32_t *keys, uint32_t *cursor) {
     __shared__ uint32_t lc[kSortSpan];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < src.n;
-    // the particle's values are read first: they do not depend on where it goes
-    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    uint32_t id = 0;
-    if (valid) {
+    const int64_t i0 = sort_block_first();
+    // the particles' values are read first: they do not depend on where they go
+    float v[kSortPPT][7];
+    uint32_t id[kSortPPT], k[kSortPPT];
+    bool valid[kSortPPT];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (src.x[a]) v[a] = src.x[a][i];
-            v[3 + a] = src.p[a][i];
+    for (int r = 0; r < kSortPPT; ++r) {
+        const int64_t i = i0 + r * 256;
+        valid[r] = i < src.n;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[r][c] = 0.0f;
+        id[r] = 0u;
+        k[r] = 0xFFFFFFFFu;
+        if (valid[r]) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (src.x[a]) v[r][a] = src.x[a][i];
+                v[r][3 + a] = src.p[a][i];
+            }
+            v[r][6] = src.w[i];
+            id[r] = src.id[i];
+            k[r] = keys[i];
         }
-        v[6] = src.w[i];
-        id = src.id[i];
     }
-    const uint32_t k = valid ? keys[i] : 0xFFFFFFFFu;
-    uint32_t lo, hi;
-    if (!block_key_range(k, valid, lo, hi)) return;   // no valid lane (block-wide)
-    const WaveRun r = wave_run(k, valid);
-    uint32_t base = 0;
+    uint32_t a, b, lo, hi;
+    const bool any = lane_key_range(k, valid, a, b);
+    if (!block_key_range(a, b, any, lo, hi)) return;   // no valid lane (block-wide)
+    WaveRun run[kSortPPT];
+    uint32_t base[kSortPPT];
+#pragma unroll
+    for (int r = 0; r < kSortPPT; ++r) {
+        run[r] = wave_run(k[r], valid[r]);
+        base[r] = 0u;
+    }
     const bool local = hi - lo < kSortSpan;
     uint32_t *hk = lc, *hc = lc + kHashSlots;
     if (local) {
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) lc[e] = 0u;
         __syncthreads();
-        // the run's place among the block's particles of its tile
-        if (valid && r.head) base = atomicAdd(&lc[k - lo], (uint32_t)r.len);
+        // each run's place among the block's particles of its tile
+#pragma unroll
+        for (int r = 0; r < kSortPPT; ++r)
+            if (valid[r] && run[r].head) base[r] = atomicAdd(&lc[k[r] - lo], (uint32_t)run[r].len);
         __syncthreads();
         // the block's first slot in the tile
         for (uint32_t e = threadIdx.x; e <= hi - lo; e += blockDim.x) {
@@ -266,7 +330,10 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
             hc[e] = 0u;
         }
         __syncthreads();
-        if (valid && r.head) base = atomicAdd(&hc[hash_slot(hk, k)], (uint32_t)r.len);
+#pragma unroll
+        for (int r = 0; r < kSortPPT; ++r)
+            if (valid[r] && run[r].head)
+                base[r] = atomicAdd(&hc[hash_slot(hk, k[r])], (uint32_t)run[r].len);
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < kHashSlots; e += blockDim.x) {
             const uint32_t c = hc[e];
@@ -274,18 +341,21 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
         }
         __syncthreads();
     }
-    base = (uint32_t)__shfl((int)base, r.head_lane, 64);
-    if (!valid) return;
-    base += local ? lc[k - lo] : hc[hash_find(hk, k)];
     const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)base + (lane - r.head_lane);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (src.x[a] && dst.x[a]) dst.x[a][j] = v[a];
-        dst.p[a][j] = v[3 + a];
+    for (int r = 0; r < kSortPPT; ++r) {
+        const uint32_t rb = (uint32_t)__shfl((int)base[r], run[r].head_lane, 64);
+        if (!valid[r]) continue;
+        const uint32_t slot0 = local ? lc[k[r] - lo] : hc[hash_find(hk, k[r])];
+        const int64_t j = (int64_t)slot0 + rb + (lane - run[r].head_lane);
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2) {
+            if (src.x[a2] && dst.x[a2]) dst.x[a2][j] = v[r][a2];
+            dst.p[a2][j] = v[r][3 + a2];
+        }
+        dst.w[j] = v[r][6];
+        dst.id[j] = id[r];
     }
-    dst.w[j] = v[6];
-    dst.id[j] = id;
 }
 
 // ------------------------------------------------------------ histogram
@@ -467,7 +537,8 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
     hipStream_t st = (hipStream_t)stream;
     const unsigned g256 = (unsigned)((nt + 255) / 256);
     fill_u32<<<g256, 256, 0, st>>>(counts, nt, 0u);
-    sort_count<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src->x[0], src->x[1], src->x[2], n, g,
+    const unsigned gsort = (unsigned)((n + kSortPer - 1) / kSortPer);
+    sort_count<<<gsort, 256, 0, st>>>(src->x[0], src->x[1], src->x[2], n, g,
                                                             keys, counts);
     scan_blocks<<<(unsigned)nblk, 256, 0, st>>>(counts, offsets, nt, bsum);
     if (nblk > 1) {
@@ -483,7 +554,7 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
         }
         scan_add<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(offsets, nt, bpre);
     }
-    sort_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(*src, *dst, keys, offsets);
+    sort_scatter<<<gsort, 256, 0, st>>>(*src, *dst, keys, offsets);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }

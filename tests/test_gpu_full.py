@@ -61,24 +61,34 @@ def test_standing_wave_refresh_matches_generator(sr):
             assert np.all(np.abs(g - ref) <= np.spacing(np.abs(ref).astype(np.float32)) + 1e-30)
 
 
-@pytest.mark.parametrize("case", ["few_tiles", "many_tiles", "nearly_sorted"])
+@pytest.mark.parametrize("case", ["few_tiles", "many_tiles", "nearly_sorted", "tiny", "two_d"])
 def test_sort_particles_is_tile_ordered_permutation(sr, case):
-    """few_tiles: 120 tiles, so every block groups its keys in LDS;
-    many_tiles: 2^21 one-cell tiles and unsorted particles, so blocks span
-    more keys than they group and take per-run global atomics;
+    """A block sorts 1024 consecutive particles, 4 per thread in rounds of 256.
+    few_tiles: 120 tiles, so every block groups its keys in an LDS array;
+    many_tiles: 2^21 one-cell tiles and unsorted particles, so every block has
+    up to 1024 distinct keys and groups them in its LDS hash table;
     nearly_sorted: sorted, then moved by up to two cells (the state of a
-    resort in the loop), 2^14 tiles."""
+    resort in the loop), 2^14 tiles; tiny: 77 particles, one block whose
+    later rounds are empty; two_d: a 2D grid, 3000 tiles.  Every size leaves
+    a ragged last block."""
+    dim = 3
     if case == "few_tiles":
         cfg = synth.config("c3", grid=(40, 32, 24), slab=None)
         tile, n = (8, 8, 4), 50001
     elif case == "many_tiles":
         cfg = synth.config("c3", grid=(256, 128, 64), slab=None)
         tile, n = (1, 1, 1), 200003
+    elif case == "tiny":
+        cfg = synth.config("c3", grid=(40, 32, 24), slab=None)
+        tile, n = (8, 8, 4), 77
+    elif case == "two_d":
+        cfg = synth.config("c2", grid=(480, 200, 1), slab=None)
+        tile, n, dim = (16, 2, 1), 70001, 2
     else:
         cfg = synth.config("c3", grid=(128, 64, 64), slab=None)
         tile, n = (4, 4, 8), 300007
     st = synth.gen_particles(cfg, n=n)
-    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    grid = sr.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
     work = sr.sort_work(grid, tile, n)
     if case == "nearly_sorted":
         parts0 = sr.Particles.from_numpy(st, dim=3)
@@ -95,7 +105,7 @@ def test_sort_particles_is_tile_ordered_permutation(sr, case):
         for k in ("px", "py", "pz", "w"):
             st[k] = st[k].astype(np.float32)
         del parts0, tmp
-    parts = sr.Particles.from_numpy(st, dim=3)
+    parts = sr.Particles.from_numpy(st, dim=dim)
     dst = parts.empty_like()
     _say(f"sort {case} {n}")
     sr.sort_particles(parts, dst, grid, tile, work)
@@ -105,12 +115,15 @@ def test_sort_particles_is_tile_ordered_permutation(sr, case):
     # every particle keeps its own state
     o = np.argsort(g["id"])
     oi = np.argsort(np.asarray(st["id"]))
-    for k in ("x", "y", "z", "px", "py", "pz"):
+    axes = ("x", "y", "z")[:dim]
+    for k in axes + ("px", "py", "pz", "w"):
         assert np.array_equal(g[k][o], np.asarray(st[k], np.float32)[oi].astype(np.float64))
     cell = [np.clip(np.floor(g[k].astype(np.float32) * np.float32(1 / cfg.dx)).astype(np.int64), 0,
-                    cfg.grid[a] - 1) for a, k in enumerate(("x", "y", "z"))]
-    nt = [-(-cfg.grid[a] // tile[a]) for a in range(3)]
-    key = (cell[0] // tile[0]) + nt[0] * ((cell[1] // tile[1]) + nt[1] * (cell[2] // tile[2]))
+                    cfg.grid[a] - 1) for a, k in enumerate(axes)]
+    nt = [-(-cfg.grid[a] // tile[a]) for a in range(dim)]
+    key = cell[0] // tile[0] + nt[0] * (cell[1] // tile[1])
+    if dim == 3:
+        key = key + nt[0] * nt[1] * (cell[2] // tile[2])
     assert np.all(np.diff(key) >= 0)
 
 
