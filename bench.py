@@ -934,7 +934,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--sort-every", type=int, default=5)
+    ap.add_argument("--sort-every", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-leg-seconds", type=float, default=8.0,

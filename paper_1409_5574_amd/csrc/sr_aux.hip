@@ -137,17 +137,17 @@ __device__ __forceinline__ bool block_key_range(uint32_t kmin, uint32_t kmax, bo
 // directly; a block whose keys span more (particles that drifted across tile
 // rows and planes) groups them in an LDS hash table of kHashSlots slots, twice
 // the most distinct keys a block can hold.
-constexpr int kSortPPT = 4;
+constexpr int kSortPPT = 2;
 constexpr int kSortPer = 256 * kSortPPT;
 constexpr uint32_t kSortSpan = 4096;
-constexpr uint32_t kHashSlots = 2048;
+constexpr uint32_t kHashSlots = 1024;
 constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
 static_assert(kHashSlots >= 2 * kSortPer && 2 * kHashSlots <= kSortSpan, "LDS table sizes");
 
 // The slot of key k in the block's table (inserting it if absent); linear
 // probing from a multiplicative hash.
 __device__ __forceinline__ uint32_t hash_slot(uint32_t *hk, uint32_t k) {
-    uint32_t h = (k * 2654435761u) >> 21;   // 11 bits
+    uint32_t h = (k * 2654435761u) >> 22;   // 10 bits
     for (;;) {
         const uint32_t prev = atomicCAS(&hk[h], kHashEmpty, k);
         if (prev == kHashEmpty || prev == k) return h;
@@ -156,7 +156,7 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t *hk, uint32_t k) {
 }
 // The slot of a key already in the table.
 __device__ __forceinline__ uint32_t hash_find(const uint32_t *hk, uint32_t k) {
-    uint32_t h = (k * 2654435761u) >> 21;
+    uint32_t h = (k * 2654435761u) >> 22;
     while (hk[h] != k) h = (h + 1u) & (kHashSlots - 1u);
     return h;
 }
@@ -183,8 +183,7 @@ __device__ __forceinline__ bool lane_key_range(const uint32_t (&k)[kSortPPT],
 }
 
 __global__ __launch_bounds__(256) void sort_count(const float *x, const float *y, const float *z,
-                                                  int64_t n, SortGeom g, uint32_t *keys,
-                                                  uint32_t *counts) {
+                                                  int64_t n, SortGeom g, uint32_t *counts) {
     __shared__ uint32_t lc[kSortSpan];
     const int64_t i0 = sort_block_first();
     uint32_t k[kSortPPT];
@@ -199,10 +198,7 @@ __global__ __launch_bounds__(256) void sort_count(const float *x, const float *y
         pz[r] = valid[r] && g.dim == 3 ? z[i] : 0.0f;
     }
 #pragma unroll
-    for (int r = 0; r < kSortPPT; ++r) {
-        k[r] = valid[r] ? tile_key(g, px[r], py[r], pz[r]) : 0xFFFFFFFFu;
-        if (valid[r]) keys[i0 + r * 256] = k[r];
-    }
+    for (int r = 0; r < kSortPPT; ++r) k[r] = valid[r] ? tile_key(g, px[r], py[r], pz[r]) : 0xFFFFFFFFu;
     uint32_t a, b, lo, hi;
     const bool any = lane_key_range(k, valid, a, b);
     if (!block_key_range(a, b, any, lo, hi)) return;   // no valid lane (block-wide)
@@ -269,10 +265,12 @@ __global__ void scan_add(uint32_t *out, int64_t n, const uint32_t *block_prefix)
 
 // Each particle goes to its slot among the tile's particles, counted from the
 // tile's offset: offsets[key] serves as the tile's cursor (it ends as the
-// tile's end).  Slots are handed out per block and key (LDS), then per block
-// from the cursor: one global atomic per distinct key of the block.
+// tile's end).  The key is computed again from the position, by the same
+// function on the same values as in sort_count, so it needs no buffer.  Slots
+// are handed out per block and key (LDS), then per block from the cursor: one
+// global atomic per distinct key of the block.
 __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_particles_f32 dst,
-                                                    const uint32_t *keys, uint32_t *cursor) {
+                                                    SortGeom g, uint32_t *cursor) {
     __shared__ uint32_t lc[kSortSpan];
     const int64_t i0 = sort_block_first();
     // the particles' values are read first: they do not depend on where they go
@@ -295,9 +293,11 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
             }
             v[r][6] = src.w[i];
             id[r] = src.id[i];
-            k[r] = keys[i];
         }
     }
+#pragma unroll
+    for (int r = 0; r < kSortPPT; ++r)
+        if (valid[r]) k[r] = tile_key(g, v[r][0], v[r][1], v[r][2]);
     uint32_t a, b, lo, hi;
     const bool any = lane_key_range(k, valid, a, b);
     if (!block_key_range(a, b, any, lo, hi)) return;   // no valid lane (block-wide)
@@ -348,6 +348,7 @@ __global__ __launch_bounds__(256) void sort_scatter(sr_particles_f32 src, sr_par
         if (!valid[r]) continue;
         const uint32_t slot0 = local ? lc[k[r] - lo] : hc[hash_find(hk, k[r])];
         const int64_t j = (int64_t)slot0 + rb + (lane - run[r].head_lane);
+        if (j >= src.n) continue;   // unreachable: both kernels compute the same key
 #pragma unroll
         for (int a2 = 0; a2 < 3; ++a2) {
             if (src.x[a2] && dst.x[a2]) dst.x[a2][j] = v[r][a2];
@@ -509,8 +510,8 @@ extern "C" int64_t sr_sort_work(const sr_grid *grid, const int32_t tile[3], int6
     int64_t nt;
     if (n < 0 || !sort_geom(grid, tile, g, nt)) return -1;
     const int64_t nblk = (nt + 1023) / 1024;
-    // counts, offsets, one spare (n_tiles each), block sums + their prefix, keys (n)
-    return (int64_t)sizeof(uint32_t) * (3 * nt + 2 * (nblk + 1024) + n);
+    // counts, offsets, one spare (n_tiles each), block sums + their prefix
+    return (int64_t)sizeof(uint32_t) * (3 * nt + 2 * (nblk + 1024));
 }
 
 extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *dst,
@@ -533,13 +534,11 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
     uint32_t *offsets = counts + nt;
     uint32_t *bsum = offsets + 2 * nt;   // after the spare n_tiles words
     uint32_t *bpre = bsum + nblk + 1024;
-    uint32_t *keys = bpre + nblk + 1024;
     hipStream_t st = (hipStream_t)stream;
     const unsigned g256 = (unsigned)((nt + 255) / 256);
     fill_u32<<<g256, 256, 0, st>>>(counts, nt, 0u);
     const unsigned gsort = (unsigned)((n + kSortPer - 1) / kSortPer);
-    sort_count<<<gsort, 256, 0, st>>>(src->x[0], src->x[1], src->x[2], n, g,
-                                                            keys, counts);
+    sort_count<<<gsort, 256, 0, st>>>(src->x[0], src->x[1], src->x[2], n, g, counts);
     scan_blocks<<<(unsigned)nblk, 256, 0, st>>>(counts, offsets, nt, bsum);
     if (nblk > 1) {
         // scan of the block sums: at most 1024*1024 tiles, so one more level of
@@ -554,7 +553,7 @@ extern "C" int sr_sort_particles(const sr_particles_f32 *src, sr_particles_f32 *
         }
         scan_add<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(offsets, nt, bpre);
     }
-    sort_scatter<<<gsort, 256, 0, st>>>(*src, *dst, keys, offsets);
+    sort_scatter<<<gsort, 256, 0, st>>>(*src, *dst, g, offsets);
     SR_HIP_CHECK(hipGetLastError());
     return SR_OK;
 }

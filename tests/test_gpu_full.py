@@ -63,10 +63,10 @@ def test_standing_wave_refresh_matches_generator(sr):
 
 @pytest.mark.parametrize("case", ["few_tiles", "many_tiles", "nearly_sorted", "tiny", "two_d"])
 def test_sort_particles_is_tile_ordered_permutation(sr, case):
-    """A block sorts 1024 consecutive particles, 4 per thread in rounds of 256.
+    """A block sorts 512 consecutive particles, 2 per thread in rounds of 256.
     few_tiles: 120 tiles, so every block groups its keys in an LDS array;
     many_tiles: 2^21 one-cell tiles and unsorted particles, so every block has
-    up to 1024 distinct keys and groups them in its LDS hash table;
+    up to 512 distinct keys and groups them in its LDS hash table;
     nearly_sorted: sorted, then moved by up to two cells (the state of a
     resort in the loop), 2^14 tiles; tiny: 77 particles, one block whose
     later rounds are empty; two_d: a 2D grid, 3000 tiles.  Every size leaves
