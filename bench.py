@@ -12,10 +12,14 @@ paper's scheme).  A step is one pass of the hot path over the ensemble:
 Each step reads its own field snapshot E, B(t^n), written into HBM before the
 timed region (the fields are an input of the step, as the particles are); a
 separate pass that also rewrites the field every step gives the end-to-end
-figure with the field refresh.  The K timed steps run twice from the same warm
-state: once as eager launches with HIP events recorded by every emission-kernel
-dispatch on its stream (the roofline figure: median per dispatch), once
-captured into a HIP graph and run as one graph launch (`value`).
+figure with the field refresh.  After an untimed rehearsal (the same steps
+repeated from the warm state for about two seconds, so that the GPU runs at
+its sustained clock), the K timed steps run three times from the same warm
+state: as eager launches with HIP events recorded by every emission-kernel
+dispatch on its stream (the roofline figure: median per dispatch), as plain
+eager launches, one library call per kernel (`value`), and captured into one
+HIP graph (reported beside it: on this ROCm its replay measured 1-3% slower
+than the plain launches, with the same kernels each a little slower).
 
 Other legs in the same line: the plain-vs-surrogate sampler comparison on the
 same 3D workload (the learned sampler of the metric), the uniform-field
@@ -265,6 +269,20 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
         del probe, sel
         torch.cuda.synchronize()
 
+    # ---------------- untimed rehearsal: the timed steps run again and again from
+    # the warm state for about --rehearse-seconds, so that the GPU has reached its
+    # sustained clock and every buffer of the timed region has been touched when
+    # the first timed pass starts (the state is restored before each pass)
+    t_r = time.perf_counter()
+    n_reh = 0
+    while time.perf_counter() - t_r < args.rehearse_seconds:
+        restore()
+        for j in range(timed_steps):
+            one_step(base + j, snaps[j])
+        torch.cuda.synchronize()
+        n_reh += 1
+    rehearsal = {"passes": n_reh, "seconds": time.perf_counter() - t_r}
+
     # ---------------- timed pass 1, eager launches: HIP events recorded by every
     # emission-kernel dispatch on its stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -284,8 +302,19 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
     k_ms = np.array([a.elapsed_time(b) for a, b in ev])
     status = ledger.read_status()
 
-    # ---------------- timed pass 2: the same K steps captured into one HIP graph
-    wall = wall_eager
+    # ---------------- timed pass 2, eager launches without events (`value`)
+    restore()
+    hist.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(timed_steps):
+        one_step(base + j, snaps[j])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rows_p = ledger.rows.cpu().numpy()[base: base + timed_steps]
+    plain_diff = float(np.max(np.abs(rows_p - rows) / np.maximum(np.abs(rows), 1e-300)))
+
+    # ---------------- timed pass 3: the same K steps captured into one HIP graph
     graph_info = None
     if graph:
         restore()
@@ -303,14 +332,15 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
         t0 = time.perf_counter()
         g.replay()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        wall_g = time.perf_counter() - t0
         rows_g = ledger.rows.cpu().numpy()[base: base + timed_steps]
-        graph_info = {"steps": [base, base + timed_steps - 1], "ms_per_step": wall * 1e3 / timed_steps,
+        graph_info = {"steps": [base, base + timed_steps - 1], "ms_per_step": wall_g * 1e3 / timed_steps,
+                      "particle_steps_per_s": n * timed_steps / wall_g,
                       "ledger_rel_diff_vs_eager": float(np.max(np.abs(rows_g - rows) /
                                                                np.maximum(np.abs(rows), 1e-300)))}
         del g
 
-    # ---------------- pass 3: the same steps with the field rewritten every step
+    # ---------------- pass 4: the same steps with the field rewritten every step
     # (the standing-wave refresh standing in for a PIC field solve), as a graph
     e2e = None
     if end_to_end and graph:
@@ -343,8 +373,13 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
     out = {
         "value": n * timed_steps / wall,
         "ms_per_step": wall * 1e3 / timed_steps,
-        "eager": {"value": n * timed_steps / wall_eager, "ms_per_step": wall_eager * 1e3 / timed_steps},
+        "eager": {"value": n * timed_steps / wall, "ms_per_step": wall * 1e3 / timed_steps,
+                  "steps": [base, base + timed_steps - 1],
+                  "ledger_rel_diff_vs_events_pass": plain_diff},
+        "eager_with_dispatch_events": {"value": n * timed_steps / wall_eager,
+                                       "ms_per_step": wall_eager * 1e3 / timed_steps},
         "hip_graph": graph_info,
+        "rehearsal": rehearsal,
         "end_to_end_with_field_refresh": e2e,
         "config": {"workload": f"{cfg.name}: {'x'.join(str(v) for v in cfg.grid[:dim])} Yee grid, "
                                f"standing wave a0={cfg.a0:g}, {n} electrons"
@@ -888,9 +923,12 @@ def run(args):
     }
     if "cpu_baseline" in head:
         out["cpu_baseline"] = head.pop("cpu_baseline")
-    out["timing"] = {"value_from": "hip_graph" if head.get("hip_graph") else "eager",
-                     "eager": head.pop("eager"), "hip_graph": head.pop("hip_graph"),
-                     "note": "both passes run the same K steps from the same warm state"}
+    out["timing"] = {"value_from": "eager",
+                     "eager": head.pop("eager"),
+                     "eager_with_dispatch_events": head.pop("eager_with_dispatch_events"),
+                     "hip_graph": head.pop("hip_graph"),
+                     "untimed_rehearsal": head.pop("rehearsal"),
+                     "note": "every pass runs the same K steps from the same warm state"}
     out.update(head)
     torch.cuda.empty_cache()
     if not args.no_samplers:
@@ -935,13 +973,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--rehearse-seconds", type=float, default=2.0,
+                    help="untimed repeats of the timed steps before the first timed pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-leg-seconds", type=float, default=8.0,
                     help="oracle time for the CPU rates of the uniform-field and kernel legs")
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-graph", action="store_true",
-                    help="report the eager-launch pass as the value (no HIP-graph pass)")
+                    help="skip the HIP-graph passes")
     ap.add_argument("--no-samplers", action="store_true",
                     help="skip the plain-vs-surrogate sampler comparison on the 3D K=8 workload")
     ap.add_argument("--sampler-steps", type=int, default=12)
