@@ -7,7 +7,7 @@
 
 namespace sr {
 
-constexpr int kHistBlocks = 512;   // most blocks of the accumulation pass
+constexpr int kHistBlocks = 1024;  // most blocks of the accumulation pass
 constexpr int kMaxBins = 1024;
 constexpr int kHistChunks = 64;    // chunks per block and group (four lanes each)
 
