@@ -78,10 +78,10 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(config: str, sort_every: int):
+def counter_traffic(config: str, sort_every: int, tile=(16, 4, 4)):
     """Bytes per launch from the committed counter summary, or None when there
     is none, the kernel sources changed since the counters were taken, or the
-    counters were taken at another sort interval."""
+    counters were taken at another sort interval or tile."""
     try:
         text = open(traffic_file(config)).read()
     except OSError:
@@ -94,6 +94,8 @@ def counter_traffic(config: str, sort_every: int):
     if vals.get("sources_sha256") != kernel_sources_digest():
         return None
     if vals.get("sort_every") != str(sort_every):
+        return None
+    if vals.get("tile") != ",".join(str(v) for v in tile):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -181,6 +183,8 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
     grid = api.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
     ncells = int(np.prod(cfg.grid[:dim]))
     tile = (64, 4, 1) if dim == 2 else (16, 4, 4)
+    if args.tile:
+        tile = tuple(int(v) for v in args.tile.split(","))[:dim] + (1,) * (3 - dim)
     st0 = synth.gen_particles(cfg)
     parts = api.Particles.from_numpy(st0, dim=dim)
     del st0
@@ -399,7 +403,7 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
                    "fields": "one snapshot per timed step, resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic(cfg_name, args.sort_every),
+                     "traffic": counter_traffic(cfg_name, args.sort_every, tile[:dim]),
                      "kernel": "push_emit_kernel<float,%d,%d,0,false>" % (dim, 1 if K <= 1 else K),
                      "kernel_ms": kmed, "kernel_ms_stats": stats_ms(k_ms),
                      "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -499,7 +503,7 @@ def kernel_leg(cfg_name: str, steps: int, warmup: int, sort_every: int = 10,
            "algorithmic_bytes_per_launch": by,
            "grid_values_read_bytes": 4 * touched,
            "roofline_frac": by / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS,
-           "traffic": counter_traffic(cfg_name, sort_every),
+           "traffic": counter_traffic(cfg_name, sort_every, tile[:dim]),
            "photons_per_step": ph,
            "chi_max": float(rows[:, L.SR_LED_CHI_MAX].max()),
            "status_bits": int(ledger.read_status())}
@@ -1001,6 +1005,9 @@ def main():
     ap.add_argument("--no-pic", action="store_true",
                     help="skip the closed PIC loop on the wakefield-shaped workload")
     ap.add_argument("--pic-steps", type=int, default=20)
+    ap.add_argument("--tile", default="",
+                    help="sort tile of the headline workload in cells, e.g. 16,4,4 (default: "
+                         "16,4,4 in 3D, 64,4 in 2D)")
     ap.add_argument("--pic-tile", default="4,4,4", help="sort tile of the PIC leg, in cells")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
