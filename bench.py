@@ -18,10 +18,10 @@ its sustained clock), the K timed steps run three times from the same warm
 state: as eager launches with HIP events recorded by every emission-kernel
 dispatch on its stream (the roofline figure: median per dispatch), as plain
 eager launches, one library call per kernel, and captured into one HIP graph.
-`value` is the faster of the last two (`timing.value_from`): on the 3D
-headline the plain launches (the graph replay measured 1-3% slower on this
-ROCm, the same kernels each a little slower inside it), on the 2D workload,
-whose kernels take tens of microseconds, the graph.
+`value` is the faster of the last two (`timing.value_from`); on this ROCm
+that has been the plain launches, on the 3D headline (the graph replay 1-3%
+slower, the same kernels each a little slower inside it) and on the 2D
+workload (within 2%).
 
 Other legs in the same line: the plain-vs-surrogate sampler comparison on the
 same 3D workload (the learned sampler of the metric), the uniform-field
