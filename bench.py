@@ -78,27 +78,45 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(config: str, sort_every: int, tile=(16, 4, 4)):
-    """Bytes per launch from the committed counter summary, or None when there
-    is none, the kernel sources changed since the counters were taken, or the
-    counters were taken at another sort interval or tile."""
+def counter_values(config: str, sort_every: int, tile=(16, 4, 4)) -> dict:
+    """The values of the committed counter summary, or {} when there is none,
+    the kernel sources changed since the counters were taken, or the counters
+    were taken at another sort interval or tile."""
     try:
         text = open(traffic_file(config)).read()
     except OSError:
-        return None
+        return {}
     vals = {}
     for line in text.splitlines():
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("sources_sha256") != kernel_sources_digest():
-        return None
+        return {}
     if vals.get("sort_every") != str(sort_every):
-        return None
+        return {}
     if vals.get("tile") != ",".join(str(v) for v in tile):
-        return None
+        return {}
+    return vals
+
+
+def counter_traffic(config: str, sort_every: int, tile=(16, 4, 4)):
+    """Bytes per launch from the committed counter summary, or None (see
+    counter_values)."""
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(counter_values(config, sort_every, tile)["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def counter_busy(config: str, sort_every: int, tile=(16, 4, 4)):
+    """The busy shares of the texture addresser and the VALU from the same
+    summary (what binds the kernel, since HBM does not), or None."""
+    vals = counter_values(config, sort_every, tile)
+    try:
+        return {"texture_addresser_busy": float(vals["texture_addresser_busy"]),
+                "valu_busy": float(vals["valu_busy"]),
+                "from": os.path.relpath(traffic_file(config), ROOT)}
     except (KeyError, ValueError):
         return None
 
@@ -404,6 +422,7 @@ def grid_leg(args, cfg_name: str, timed_steps: int, warmup: int, with_cpu: bool,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic(cfg_name, args.sort_every, tile[:dim]),
+                     "binding_counters": counter_busy(cfg_name, args.sort_every, tile[:dim]),
                      "kernel": "push_emit_kernel<float,%d,%d,0,false>" % (dim, 1 if K <= 1 else K),
                      "kernel_ms": kmed, "kernel_ms_stats": stats_ms(k_ms),
                      "algorithmic_bytes_per_launch": bytes_per_launch,

@@ -24,14 +24,18 @@ def test_counter_traffic_is_tied_to_sources_interval_and_tile(tmp_path, monkeypa
     digest = bench.kernel_sources_digest()
     prof = tmp_path / "profiles"
     prof.mkdir()
-    text = ("- traffic_bytes_per_launch: `123`\n- sort_every: `4`\n- tile: `16,4,4`\n"
+    text = ("- traffic_bytes_per_launch: `123`\n- texture_addresser_busy: `0.5`\n"
+            "- valu_busy: `0.25`\n- sort_every: `4`\n- tile: `16,4,4`\n"
             f"- sources_sha256: `{digest}`\n")
     (prof / "push_emit_cX_traffic.md").write_text(text)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # kernel_sources_digest reads the sources under ROOT: keep it on the repository
     monkeypatch.setattr(bench, "kernel_sources_digest", lambda: digest)
     assert bench.counter_traffic("cX", 4, (16, 4, 4)) == 123.0
+    busy = bench.counter_busy("cX", 4, (16, 4, 4))
+    assert busy["texture_addresser_busy"] == 0.5 and busy["valu_busy"] == 0.25
     assert bench.counter_traffic("cX", 10, (16, 4, 4)) is None
+    assert bench.counter_busy("cX", 10, (16, 4, 4)) is None
     assert bench.counter_traffic("cX", 4, (32, 2, 2)) is None
     assert bench.counter_traffic("cY", 4, (16, 4, 4)) is None
     monkeypatch.setattr(bench, "kernel_sources_digest", lambda: "0" * 64)
