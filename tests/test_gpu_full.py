@@ -127,6 +127,44 @@ def test_sort_particles_is_tile_ordered_permutation(sr, case):
     assert np.all(np.diff(key) >= 0)
 
 
+def test_sort_full_size_drifted(sr):
+    """The headline's full state (2^24 electrons, 512^3 grid, 16x4x4 tiles):
+    sorted, then every particle moved by up to two cells in each direction
+    (more than four steps of the standing wave), then sorted again, as the
+    step loop does.  Checked on the device: a permutation that keeps every
+    particle's state, in tile order."""
+    cfg = synth.config("c3")
+    n = cfg.n_particles
+    st = synth.gen_particles(cfg)
+    grid = sr.grid_struct(3, n=cfg.grid, dx=(cfg.dx,) * 3)
+    tile = (16, 4, 4)
+    work = sr.sort_work(grid, tile, n)
+    a = sr.Particles.from_numpy(st, dim=3)
+    del st
+    b = a.empty_like()
+    _say("full-size sort: first pass")
+    sr.sort_particles(a, b, grid, tile, work)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    for q in range(3):
+        L = float(cfg.grid[q] * cfg.dx)
+        moved = b.x[q] + (torch.rand(n, device="cuda", generator=gen) * 4.0 - 2.0) * float(cfg.dx)
+        moved = torch.remainder(moved, L)
+        b.x[q].copy_(torch.where(moved >= L, torch.zeros_like(moved), moved))
+    _say("full-size sort: drifted pass")
+    sr.sort_particles(b, a, grid, tile, work)
+    torch.cuda.synchronize()
+    ib = torch.argsort(b.id.view(torch.int32).to(torch.int64))
+    ia = torch.argsort(a.id.view(torch.int32).to(torch.int64))
+    assert torch.equal(b.id[ib], a.id[ia])
+    for s_, d_ in zip(b.x + b.p + [b.w], a.x + a.p + [a.w]):
+        assert torch.equal(s_[ib], d_[ia])
+    inv = torch.tensor(1.0 / cfg.dx, dtype=torch.float32, device="cuda")
+    c = [torch.clamp(torch.floor(a.x[q] * inv).to(torch.int64), 0, cfg.grid[q] - 1) for q in range(3)]
+    nt = [cfg.grid[q] // tile[q] for q in range(3)]
+    key = c[0] // tile[0] + nt[0] * (c[1] // tile[1] + nt[1] * (c[2] // tile[2]))
+    assert bool((key[1:] >= key[:-1]).all())
+
+
 def _step_for_photons(sr, table, cfg, n, K, p_scale, per_particle=None):
     st = synth.gen_particles(cfg, n=n)
     for k in ("px", "py", "pz"):
