@@ -612,11 +612,12 @@ def _host_grid(profiles, cfg):
 
 
 @pytest.mark.parametrize("name,sample,sampler", [("c2", 20000, 0), ("c3", 6000, 0), ("c5", 4000, 0),
-                                                 ("c3", 6000, 3)])
+                                                 ("c3", 6000, 1), ("c3", 6000, 3)])
 def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler):
     """One step at the workload's full size in the benchmark's launch
-    configuration, checked against the oracle on sampled particles (sampler 3:
-    the quantum-corrected kernel on the same workload)."""
+    configuration, checked against the oracle on sampled particles (sampler 1:
+    the table-direct sampler, 3: the quantum-corrected kernel, on the same
+    workload)."""
     cfg = synth.config(name)
     n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
     seed, step, t = 99, 7, 0.3
@@ -655,7 +656,8 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler):
     fo = oracle.Field(dim, n=cfg.grid, dx=(cfg.dx,) * 3, E=host[:3], B=host[3:])
     ph_o, led_o, det = oracle.step(orc, fo, cfg.dt, seed, step, hbar_n=cfg.hbar_n, alpha=cfg.alpha,
                                    n_samples=K, recoil=cfg.recoil, kin_cut=cfg.kin_cut,
-                                   sampler=oracle.SAMPLER_QUANTUM if sampler == 3 else 0,
+                                   sampler={0: oracle.SAMPLER_S, 1: oracle.SAMPLER_DIRECT,
+                                            3: oracle.SAMPLER_QUANTUM}[sampler],
                                    detail=True)
     del host, fo
     gi = np.argsort(g["id"])[ids]
