@@ -611,18 +611,22 @@ def _host_grid(profiles, cfg):
             for p in profiles]
 
 
-@pytest.mark.parametrize("name,sample,sampler", [("c2", 20000, 0), ("c3", 6000, 0), ("c5", 4000, 0),
-                                                 ("c3", 6000, 1), ("c3", 6000, 3)])
-def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler):
+@pytest.mark.parametrize("name,sample,sampler,warm", [("c2", 20000, 0, 0), ("c3", 6000, 0, 0),
+                                                      ("c5", 4000, 0, 0), ("c3", 6000, 1, 0),
+                                                      ("c3", 6000, 3, 0), ("c3", 6000, 0, 6)])
+def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler, warm):
     """One step at the workload's full size in the benchmark's launch
     configuration, checked against the oracle on sampled particles (sampler 1:
     the table-direct sampler, 3: the quantum-corrected kernel, on the same
-    workload)."""
+    workload).  With warm > 0 the step starts from the state the GPU reaches
+    after that many steps, each in the field of its own time and re-sorted
+    every 4 as in the benchmark, where the particles have gained energy and
+    emit about 40 times more photons."""
     cfg = synth.config(name)
     n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
     seed, step, t = 99, 7, 0.3
     st = synth.gen_particles(cfg)
-    _say(f"full size {name}: n={n} grid={cfg.grid} sampler={sampler}")
+    _say(f"full size {name}: n={n} grid={cfg.grid} sampler={sampler} warm={warm}")
     parts = sr.Particles.from_numpy(st, dim=dim)
     grid = sr.grid_struct(dim, n=cfg.grid, dx=(cfg.dx,) * 3)
     # the launch configuration the benchmark times: tile-sorted particles, uniform chunks
@@ -630,20 +634,39 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler):
     work = sr.sort_work(grid, tile, n)
     sorted_parts = parts.empty_like()
     sr.sort_particles(parts, sorted_parts, grid, tile, work)
-    del parts, work
     fields, profiles = _device_fields(sr, cfg, t)
     photons = sr.PhotonBuffer(n, cfg.photons_per_particle, dim=dim)
     ledger = sr.LedgerBuf(1, sr.n_chunks_uniform(n))
     prm = sr.params_struct(cfg.hbar_n, cfg.alpha, K, sampler=sampler, recoil=cfg.recoil,
                            kin_cut=cfg.kin_cut)
-    sr.gather_push_emit(sorted_parts, fields, grid, cfg.dt, seed, step, prm, table, photons,
+    if warm:
+        # the field of each warm-up step at its own time, as in the benchmark
+        for i in range(warm):
+            if i > 0 and i % 4 == 0:
+                sr.sort_particles(sorted_parts, parts, grid, tile, work)
+                sorted_parts, parts = parts, sorted_parts
+            fi, _ = _device_fields(sr, cfg, i * cfg.dt)
+            sr.gather_push_emit(sorted_parts, fi, grid, cfg.dt, seed, i, prm, table, photons,
+                                ledger, None)
+            torch.cuda.synchronize()
+            del fi
+        torch.cuda.synchronize()
+        # the warm state, indexed by particle id as the generator's state is
+        g0 = sorted_parts.to_numpy()
+        order = np.argsort(g0["id"])
+        st = {k: (v[order] if v is not None else None) for k, v in g0.items()}
+        del g0, order
+    step_parts = sorted_parts
+    del sorted_parts
+    del parts, work
+    sr.gather_push_emit(step_parts, fields, grid, cfg.dt, seed, step, prm, table, photons,
                         ledger, 0)
     torch.cuda.synchronize()
     status = ledger.read_status()
     assert status & ~2 == 0
-    g = sorted_parts.to_numpy()
+    g = step_parts.to_numpy()
     ph_all = photons.gather(n)
-    del sorted_parts, photons, fields
+    del step_parts, photons, fields
     torch.cuda.empty_cache()
 
     rng = np.random.default_rng(3)
@@ -673,6 +696,8 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler):
                               dn_tol=dn_tol)
     e_gpu = float((ph_g["w"].astype(np.float64) * ph_g["eps"]).sum())
     assert e_gpu == pytest.approx(led_o[0], rel=parity.LEDGER_TOL) or rep["decision_flips"]
+    if warm:
+        assert rep["photons_oracle"] > sample // 10   # the warm state emits
     print(f"{name}: sampled {sample}, photons {rep['photons_oracle']}, flips "
           f"{rep['decision_flips']}, |dp|/p {rep['p_rel_err']:.2e}", flush=True)
 
