@@ -613,7 +613,8 @@ def _host_grid(profiles, cfg):
 
 @pytest.mark.parametrize("name,sample,sampler,warm", [("c2", 20000, 0, 0), ("c3", 6000, 0, 0),
                                                       ("c5", 4000, 0, 0), ("c3", 6000, 1, 0),
-                                                      ("c3", 6000, 3, 0), ("c3", 6000, 0, 6)])
+                                                      ("c3", 6000, 3, 0), ("c3", 6000, 0, 6),
+                                                      ("c3", 6000, 1, 6), ("c3", 6000, 3, 6)])
 def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler, warm):
     """One step at the workload's full size in the benchmark's launch
     configuration, checked against the oracle on sampled particles (sampler 1:
