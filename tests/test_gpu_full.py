@@ -614,7 +614,8 @@ def _host_grid(profiles, cfg):
 @pytest.mark.parametrize("name,sample,sampler,warm", [("c2", 20000, 0, 0), ("c3", 6000, 0, 0),
                                                       ("c5", 4000, 0, 0), ("c3", 6000, 1, 0),
                                                       ("c3", 6000, 3, 0), ("c3", 6000, 0, 6),
-                                                      ("c3", 6000, 1, 6), ("c3", 6000, 3, 6)])
+                                                      ("c3", 6000, 1, 6), ("c3", 6000, 3, 6),
+                                                      ("c2", 20000, 0, 6)])
 def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler, warm):
     """One step at the workload's full size in the benchmark's launch
     configuration, checked against the oracle on sampled particles (sampler 1:
@@ -622,7 +623,7 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler, wa
     workload).  With warm > 0 the step starts from the state the GPU reaches
     after that many steps, each in the field of its own time and re-sorted
     every 4 as in the benchmark, where the particles have gained energy and
-    emit about 40 times more photons."""
+    emit many more photons (on c3 about 40 times more)."""
     cfg = synth.config(name)
     n, K, dim = cfg.n_particles, cfg.n_samples, cfg.dim
     seed, step, t = 99, 7, 0.3
@@ -698,7 +699,7 @@ def test_full_size_one_step_sampled(sr, table, oracle, name, sample, sampler, wa
     e_gpu = float((ph_g["w"].astype(np.float64) * ph_g["eps"]).sum())
     assert e_gpu == pytest.approx(led_o[0], rel=parity.LEDGER_TOL) or rep["decision_flips"]
     if warm:
-        assert rep["photons_oracle"] > sample // 10   # the warm state emits
+        assert rep["photons_oracle"] > sample // 50   # the warm state emits
     print(f"{name}: sampled {sample}, photons {rep['photons_oracle']}, flips "
           f"{rep['decision_flips']}, |dp|/p {rep['p_rel_err']:.2e}", flush=True)
 
